@@ -1,0 +1,248 @@
+"""CPU FP64 oracle of the Sharp Phase-Field Method (arXiv:1910.05180).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the GPU library never does, and
+the two share no code.  This module only marshals numpy arrays into the plain C
+library ``spfm_oracle.c`` (which holds every equation) and adds exact
+(``math.fsum``) reductions for the diagnostics of Sec. 2.3 and Sec. 3.
+
+Field arrays are numpy float64 of shape (nz, ny, nx), x fastest, periodic.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spfm_oracle.c")
+_SO = os.path.join(_HERE, "libspfm_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+LOCAL, GLOBAL, CF = 0, 1, 2
+COUPLINGS = {"local": LOCAL, "global": GLOBAL, "cf": CF}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C, OpenMP over z planes)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+           "-std=c11", "-D_DEFAULT_SOURCE", "-o", _SO, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _SO
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("lam", ctypes.c_double), ("Gamma", ctypes.c_double),
+        ("M", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("C_Gamma", ctypes.c_double), ("stencil", ctypes.c_int), ("coupling", ctypes.c_int),
+        ("u", ctypes.c_double * 3), ("gamma", ctypes.c_double * 3),
+        ("eps", ctypes.c_double), ("tau", ctypes.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build()
+            L = ctypes.CDLL(_SO)
+            dp = ctypes.POINTER(ctypes.c_double)
+            pp = ctypes.POINTER(Params)
+            L.orc_direction.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+            L.orc_direction.restype = ctypes.c_int
+            L.orc_nu.argtypes = [ctypes.c_int]
+            L.orc_nu.restype = ctypes.c_double
+            for f in (L.orc_g, L.orc_g_prime):
+                f.argtypes = [ctypes.c_double] * 4
+                f.restype = ctypes.c_double
+            L.orc_normal.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+            L.orc_rate.argtypes = [pp, dp, dp]
+            L.orc_rate_points.argtypes = [pp, dp, ctypes.c_long, ctypes.POINTER(ctypes.c_long), dp]
+            L.orc_step.argtypes = [pp, dp, ctypes.c_long]
+            L.orc_step.restype = ctypes.c_int
+            L.orc_energy.argtypes = [pp, dp, ctypes.c_int]
+            L.orc_energy.restype = ctypes.c_double
+            L.orc_calibrate_cgamma.argtypes = [ctypes.c_double]
+            L.orc_calibrate_cgamma.restype = ctypes.c_double
+            L.orc_stable_dt.argtypes = [pp]
+            L.orc_stable_dt.restype = ctypes.c_double
+            L.orc_init_planar.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                               ctypes.POINTER(ctypes.c_int),
+                                                               ctypes.c_double, dp]
+            L.orc_init_spheres.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                               ctypes.c_int, dp, dp, dp]
+            L.orc_num_threads.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def default_gamma(stencil: int):
+    """Shell weights (reading): the leading-order isotropic shell combinations
+    of Sec. 2.1's three Laplacian realisations; gamma_1 = 1 - gamma_2 - gamma_3."""
+    return {6: (1.0, 0.0, 0.0), 18: (1.0 / 3.0, 2.0 / 3.0, 0.0),
+            26: (14.0 / 30.0, 12.0 / 30.0, 4.0 / 30.0)}[stencil]
+
+
+def params(shape, *, dx=1.0, lam=4.0, Gamma=1.0, M=1.0, mu=0.0, dt=0.1, stencil=26,
+           coupling="local", u=(1.0, 0.0, 0.0), gamma=None, C_Gamma=None, eps=1e-12,
+           tau=1e-3) -> Params:
+    nz, ny, nx = shape
+    p = Params()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.dx, p.lam, p.Gamma, p.M, p.mu, p.dt = dx, lam, Gamma, M, mu, dt
+    p.stencil = stencil
+    p.coupling = COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
+    p.u[:] = u
+    p.gamma[:] = default_gamma(stencil) if gamma is None else gamma
+    if C_Gamma is None:
+        C_Gamma = 2.0 / 3.0 if p.coupling == CF else calibrate_cgamma(lam / dx)
+    p.C_Gamma = C_Gamma
+    p.eps, p.tau = eps, tau
+    return p
+
+
+def direction(k: int):
+    r = (ctypes.c_int * 3)()
+    shell = lib().orc_direction(k, r)
+    return (r[0], r[1], r[2]), shell
+
+
+def nu(shell: int) -> float:
+    return lib().orc_nu(shell)
+
+
+def g(phi: float, a: float, rho: float, lam: float) -> float:
+    return lib().orc_g(phi, a, rho, lam)
+
+
+def g_prime(phi: float, a: float, rho: float, lam: float) -> float:
+    return lib().orc_g_prime(phi, a, rho, lam)
+
+
+def _check(p: Params, phi: np.ndarray):
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous
+    assert phi.shape == (p.nz, p.ny, p.nx), (phi.shape, (p.nz, p.ny, p.nx))
+
+
+def normal(p: Params, phi: np.ndarray, x: int, y: int, z: int):
+    _check(p, phi)
+    n = np.zeros(3)
+    lib().orc_normal(ctypes.byref(p), _dp(phi), x, y, z, _dp(n))
+    return n
+
+
+def rate(p: Params, phi: np.ndarray) -> np.ndarray:
+    _check(p, phi)
+    out = np.empty_like(phi)
+    lib().orc_rate(ctypes.byref(p), _dp(phi), _dp(out))
+    return out
+
+
+def rate_points(p: Params, phi: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    _check(p, phi)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size)
+    lib().orc_rate_points(ctypes.byref(p), _dp(phi), idx.size,
+                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))
+    return out
+
+
+def step(p: Params, phi: np.ndarray, nsteps: int) -> np.ndarray:
+    out = np.array(phi, dtype=np.float64, order="C", copy=True)
+    _check(p, out)
+    if lib().orc_step(ctypes.byref(p), _dp(out), int(nsteps)) != 0:
+        raise MemoryError("oracle step allocation failed")
+    return out
+
+
+def energy(p: Params, phi: np.ndarray, with_mu: bool = False) -> float:
+    _check(p, phi)
+    return lib().orc_energy(ctypes.byref(p), _dp(phi), 1 if with_mu else 0)
+
+
+def calibrate_cgamma(lam_over_dx: float) -> float:
+    return lib().orc_calibrate_cgamma(float(lam_over_dx))
+
+
+def stable_dt(p: Params) -> float:
+    return lib().orc_stable_dt(ctypes.byref(p))
+
+
+def init_planar(shape, hkl, offset, *, dx=1.0, lam=4.0) -> np.ndarray:
+    nz, ny, nx = shape
+    out = np.empty(shape, dtype=np.float64)
+    h = (ctypes.c_int * 3)(*hkl)
+    lib().orc_init_planar(nx, ny, nz, dx, lam, h, float(offset), _dp(out))
+    return out
+
+
+def init_spheres(shape, centers, radii, *, dx=1.0, lam=4.0) -> np.ndarray:
+    nz, ny, nx = shape
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    out = np.empty(shape, dtype=np.float64)
+    lib().orc_init_spheres(nx, ny, nz, dx, lam, r.size, _dp(c), _dp(r), _dp(out))
+    return out
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics (exact sums).  The paper plots interface position and velocity
+# (Fig. 1b) but defines neither from the field; the readings used here:
+#   phase volume     V1 = dx^3 sum phi
+#   interface area   A_if = (4/lambda) dx^3 sum phi (1 - phi)   (exact for an
+#                    ideal planar profile: the integral of phi(1-phi) across it
+#                    is lambda/4)
+#   slab position    delta(t) = (V1(t) - V1(0)) / A_tot, A_tot = 2 L^2 |N| / gcd(N)
+#   sphere radius    R_V with (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) = V1
+# ---------------------------------------------------------------------------
+
+def exact_sums(phi: np.ndarray):
+    """Exactly rounded sums of phi and phi(1 - phi) (FP64 per element)."""
+    a = np.asarray(phi, dtype=np.float64).ravel()
+    return math.fsum(a.tolist()), math.fsum((a * (1.0 - a)).tolist())
+
+
+def phase_volume(phi: np.ndarray, dx: float = 1.0) -> float:
+    return exact_sums(phi)[0] * dx ** 3
+
+
+def interface_area(phi: np.ndarray, lam: float, dx: float = 1.0) -> float:
+    return 4.0 / lam * exact_sums(phi)[1] * dx ** 3
+
+
+def slab_area(shape, hkl, dx: float = 1.0) -> float:
+    """Total interface area of the periodic slab of orc_init_planar."""
+    nz, ny, nx = shape
+    nn = math.sqrt(sum(h * h for h in hkl))
+    gg = 0
+    for n_i, h in zip((nx, ny, nz), hkl):
+        gg = math.gcd(gg, abs(n_i * h))
+    P = gg * dx / nn
+    return 2.0 * nx * ny * nz * dx ** 3 / P
+
+
+def sphere_radius_from_volume(V1: float, lam: float) -> float:
+    """Solve (4 pi/3)(R^3 + R pi^2 lambda^2/16) = V1 for R by Newton's method."""
+    c = math.pi ** 2 * lam ** 2 / 16.0
+    R = (3.0 * V1 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    for _ in range(60):
+        f = 4.0 * math.pi / 3.0 * (R ** 3 + R * c) - V1
+        d = 4.0 * math.pi / 3.0 * (3.0 * R * R + c)
+        R -= f / d
+    return R

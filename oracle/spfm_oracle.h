@@ -1,0 +1,77 @@
+/*
+ * spfm_oracle.h -- plain CPU FP64 reference of the Sharp Phase-Field Method
+ * (SPFM) time step of Fleck, Schleifer & Zimbrod, "Frictionless motion of
+ * diffuse interfaces by sharp phase-field modeling" (arXiv:1910.05180).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against the paper.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  It shares no code, header,
+ * table or constant with the GPU library.
+ *
+ * Conventions (all from Sec. 2.1 of the paper):
+ *   - field phi[(z*ny + y)*nx + x], x fastest, periodic on every face;
+ *   - phi = 1 and phi = 0 are the two phases; the unit normal n points from
+ *     phi = 1 into phi = 0 (Eq. 3);
+ *   - a positive driving force mu favours phase phi = 0.
+ */
+#ifndef SPFM_ORACLE_H
+#define SPFM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_LOCAL = 0, ORC_GLOBAL = 1, ORC_CF = 2 };
+
+typedef struct {
+    int nx, ny, nz;   /* grid points along x, y, z */
+    double dx;        /* grid spacing */
+    double lambda;    /* interface width (Eq. 1, Eq. 3) */
+    double Gamma;     /* interface energy density (Eq. 1) */
+    double M;         /* kinetic coefficient (Eq. 2) */
+    double mu;        /* homogeneous driving force (Eq. 1) */
+    double dt;        /* explicit time step */
+    double C_Gamma;   /* interface energy calibration parameter (Eq. 1), > 0 */
+    int stencil;      /* 6, 18 or 26 neighbours = shells 1, 1-2, 1-3 (Tab. 1) */
+    int coupling;     /* ORC_LOCAL (TI_n), ORC_GLOBAL (TI_<hkl>), ORC_CF */
+    double u[3];      /* ORC_GLOBAL: direction of restored invariance */
+    double gamma[3];  /* shell weights gamma_1..3 (Eq. 1) */
+    double eps;       /* floor of phi and 1-phi inside the normal estimator */
+    double tau;       /* |grad psi| below tau -> fallback normal (1,0,0) */
+} orc_params;
+
+/* Tab. 1: direction k (0..12) as an integer vector; returns its shell 1..3. */
+int orc_direction(int k, int r[3]);
+/* nu_j = 3/m_j with m_j the number of directions of shell j (Sec. 2.1). */
+double orc_nu(int shell);
+/* Eq. 6: g_k(phi) for coupling parameter a and |r_k| = rho. */
+double orc_g(double phi, double a, double rho, double lambda);
+/* d g_k / d phi of Eq. 6. */
+double orc_g_prime(double phi, double a, double rho, double lambda);
+/* Local interface normal of the TI_n model at (x,y,z). */
+void orc_normal(const orc_params *p, const double *phi, int x, int y, int z, double n[3]);
+/* Right-hand side d phi / dt of Eq. 2 at every point. */
+void orc_rate(const orc_params *p, const double *phi, double *rate);
+/* Right-hand side at npts listed linear indices. */
+void orc_rate_points(const orc_params *p, const double *phi, long npts, const long *idx, double *rate);
+/* nsteps forward-Euler steps, in place.  Returns 0, or -1 on allocation failure. */
+int orc_step(const orc_params *p, double *phi, long nsteps);
+/* Total free energy of Eq. 1 (with_mu = 0 gives the interface energy F_int). */
+double orc_energy(const orc_params *p, const double *phi, int with_mu);
+/* Interface energy calibration C_Gamma for lambda/dx (reading: discrete energy
+ * of the ideal planar [100] profile equals Gamma times its area). */
+double orc_calibrate_cgamma(double lambda_over_dx);
+/* Largest dt for which the linearised explicit scheme is stable. */
+double orc_stable_dt(const orc_params *p);
+/* Eq. 3 initial fields. */
+void orc_init_planar(int nx, int ny, int nz, double dx, double lambda, const int hkl[3],
+                     double offset, double *phi);
+void orc_init_spheres(int nx, int ny, int nz, double dx, double lambda, int n,
+                      const double *centers, const double *radii, double *phi);
+/* Threads the oracle runs on. */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
