@@ -1,0 +1,143 @@
+"""Throughput of the SPFM explicit step on one MI355X.
+
+Headline: FP32, 26 neighbours, TI_n (local normal), tiled HIP kernel on the
+256^3 periodic grain workload (one grain of radius 60 dx at the box centre,
+lambda = 4 dx, mu = 0, Gamma = M = dx = 1, dt = 0.1), in GLUPS (10^9 lattice
+point updates per second) and as a fraction of the HBM roofline.  Beside it:
+the plain per-grid FP64 kernel on the same workload, and the CPU oracle timed
+on a bounded sample of it on the host cores.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+ALG_BYTES_F32 = 8              # read phi^n + write phi^{n+1} per point per step
+ALG_BYTES_F64 = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--only", default="", help="run only this leg: f32 | f64 (profiling)")
+    return ap.parse_args()
+
+
+def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup):
+    """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
+    Returns (wall seconds, event milliseconds) of the timed region."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = spfm.Spfm(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx,
+                      stencil=w.stencil, dtype=dtype, coupling="local", kernel=kernel, dt=w.dt)
+        s.init_spheres(w.centers, w.radii)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = e0.elapsed_time(e1)
+        d = s.diagnostics()
+        s.close()
+    return wall, ev_ms, d
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+
+    import oracle
+    shape = w.shape
+    phi = oracle.init_spheres(shape, w.centers, w.radii, lam=w.lam, dx=w.dx)
+    p = oracle.params(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, dt=w.dt,
+                      stencil=w.stencil, coupling="local", eps=1e-300)
+    t0 = time.perf_counter()
+    phi = oracle.step(p, phi, steps)
+    dt = time.perf_counter() - t0
+    n = int(np.prod(shape))
+    return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {shape[2]}^3 grain workload "
+                      f"(26 neighbours, TI_n), {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1910_05180_amd import inputs, spfm
+    spfm.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.sphere256(mu=0.0)
+    npts = w.shape[0] * w.shape[1] * w.shape[2]
+
+    out = {"metric": "GLUPS + % HBM peak, 256^3 FP32 26-nbr SPFM step vs FP64 plain"}
+    f32 = f64 = None
+    if args.only in ("", "f32"):
+        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
+                                   steps=args.steps, warmup=args.warmup)
+        f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
+    if args.only in ("", "f64"):
+        wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",
+                                      steps=args.fp64_steps, warmup=min(args.warmup, 5))
+        f64 = {"wall": wall64, "ev_ms": ev64, "diag": d64}
+
+    if f32 is not None:
+        steps = args.steps
+        ms_per_step = f32["wall"] * 1e3 / steps
+        glups = npts * steps / f32["wall"] / 1e9
+        kern_ms = f32["ev_ms"] / steps                  # average step-kernel duration
+        achieved = ALG_BYTES_F32 * npts / (kern_ms * 1e-3) / 1e9
+        out.update({
+            "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "grain256: 256^3 periodic grid, one grain R=60 dx at the "
+                                   "centre (ideal radial profile), lambda=4 dx, mu=0, "
+                                   "Gamma=M=dx=1, dt=0.1, 26 neighbours, TI_n local normal, "
+                                   "FP32 tiled kernel",
+                       "points": npts, "stencil": 26, "coupling": "local", "kernel": "tiled"},
+            "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "kernel_ms_per_step": kern_ms,
+            "phi_range": [f32["diag"]["phi_min"], f32["diag"]["phi_max"]],
+        })
+    if f64 is not None:
+        s64 = args.fp64_steps
+        g64 = npts * s64 / f64["wall"] / 1e9
+        out["fp64_plain"] = {"value": g64, "unit": "GLUPS", "steps": s64,
+                             "ms_per_step": f64["wall"] * 1e3 / s64,
+                             "pct_hbm_peak": 100.0 * ALG_BYTES_F64 * npts /
+                             (f64["ev_ms"] / s64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if f32 is not None:
+            out["speedup_vs_fp64_plain"] = out["value"] / g64
+    if not args.no_cpu and f32 is not None:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * spfm.h -- C ABI of the MI355X (gfx950) implementation of the explicit time
+ * step of the Sharp Phase-Field Method (SPFM) of Fleck, Schleifer & Zimbrod,
+ * "Frictionless motion of diffuse interfaces by sharp phase-field modeling"
+ * (arXiv:1910.05180).
+ *
+ * The problem (Sec. 2.1): a phase field phi on a uniform simple-cubic grid of
+ * spacing dx evolves by the Allen-Cahn law (Eq. 2)
+ *     3 lambda Gamma d_t phi = -2 M delta_phi F
+ * where F is the discrete free energy of Eq. 1: forward-difference gradient
+ * energy over the 3, 9 or 13 directions of the first one, two or three
+ * neighbour shells (Tab. 1; 6-, 18- or 26-neighbour stencils), the
+ * translationally invariant equilibrium potential g_k of Eq. 6 with grid
+ * coupling parameters a_k = tanh(2 r_k.n / lambda) (Eq. 5), and the driving
+ * force mu h3(phi), h3 = phi^2 (3 - 2 phi).  The coupling normal n is either a
+ * fixed direction (TI_<hkl> model) or the locally measured interface normal
+ * (TI_n model, Tab. 2); the continuum-field model (CF, potential
+ * 8 phi^2 (1-phi)^2 / 3 per direction) is available as a control.
+ * Time integration is forward Euler; the grid is periodic on all faces.
+ *
+ * Conventions.
+ *   Field layout: phi[(z*ny + y)*nx + x], x fastest, dtype float or double.
+ *   phi = 1 and phi = 0 are the two phases; the normal points from phi = 1
+ *   into phi = 0; mu > 0 favours phi = 0; planar interfaces move with
+ *   v = -M mu / Gamma along their normal (Sec. 2.1).
+ *   Pointers: "device" pointers are HIP device memory on the current device
+ *   (for instance torch.cuda tensors); "host" pointers are ordinary memory.
+ *   Ownership: the caller owns every pointer it passes; the library owns the
+ *   context and any buffer it allocated itself, and frees them in destroy.
+ *   Errors: every call returns an spfm_status; nothing is printed.  A failing
+ *   call leaves a description in spfm_last_error() (per host thread).
+ *   Streams: every call is ordered on the context's stream.  spfm_step and
+ *   the field setters are asynchronous; spfm_diagnostics and spfm_get_field
+ *   into host memory synchronise the stream.
+ *   Threads: a context must not be used by two host threads at once.
+ */
+#ifndef SPFM_H
+#define SPFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPFM_OK = 0,
+    SPFM_E_INVAL = -1,     /* invalid argument */
+    SPFM_E_NOMEM = -2,     /* device or host allocation failed */
+    SPFM_E_HIP = -3,       /* a HIP runtime call failed */
+    SPFM_E_UNSTABLE = -4,  /* dt above the explicit stability bound */
+    SPFM_E_DIVERGED = -5,  /* non-finite values or |phi| > 2 found */
+    SPFM_E_STATE = -6      /* call not valid in the current state */
+} spfm_status;
+
+typedef enum { SPFM_F32 = 0, SPFM_F64 = 1 } spfm_dtype;
+
+/* Tab. 2 models (all with h3): LOCAL = TI_n, GLOBAL = TI_<hkl> with u,
+ * CF = continuum-field potential (no translational invariance). */
+typedef enum { SPFM_LOCAL = 0, SPFM_GLOBAL = 1, SPFM_CF = 2 } spfm_coupling;
+
+/* Kernel choice: AUTO = tiled; PLAIN = one thread per point reading its 27
+ * neighbours from global memory; TILED = LDS-staged tiles marching along z. */
+typedef enum { SPFM_KERNEL_AUTO = 0, SPFM_KERNEL_PLAIN = 1, SPFM_KERNEL_TILED = 2 } spfm_kernel;
+
+typedef struct {
+    int32_t nx, ny, nz; /* grid points per axis, each >= 3; periodic */
+    double dx;          /* grid spacing, > 0 */
+} spfm_grid;
+
+/* Options.  An all-zero struct selects every default. */
+typedef struct {
+    int32_t dtype;      /* spfm_dtype; default SPFM_F32 */
+    int32_t coupling;   /* spfm_coupling; default SPFM_LOCAL */
+    double u[3];        /* GLOBAL: direction of restored invariance (any length > 0) */
+    double dt;          /* time step; <= 0 selects 0.1 dx^2 / (M Gamma) */
+    double gamma[3];    /* shell weights gamma_1..3 of Eq. 1; all zero selects
+                           (1,0,0), (1/3,2/3,0), (14,12,4)/30 for 6/18/26 neighbours */
+    double C_Gamma;     /* energy calibration of Eq. 1; <= 0 selects the value for
+                           which the ideal planar [100] profile carries energy Gamma
+                           per area (TI), or 2/3 (CF) */
+    double eps;         /* floor of phi and 1-phi in the normal estimator; <= 0
+                           selects 1e-30 (F32) or 1e-300 (F64) */
+    double tau;         /* |grad psi| below tau -> normal (1,0,0); <= 0 selects 1e-3 */
+    void *stream;       /* hipStream_t to order work on; NULL = the null stream */
+    void *d_phi[2];     /* optional caller-owned device ping-pong buffers of
+                           nx*ny*nz elements of dtype; both NULL = library allocates */
+    int32_t kernel;     /* spfm_kernel */
+    int32_t allow_unstable; /* nonzero: skip the dt stability check */
+} spfm_options;
+
+typedef struct {
+    int64_t step;              /* steps taken since the last field set or init */
+    double time;               /* step * dt */
+    double phase_volume;       /* V1 = dx^3 sum phi (FP64, compensated) */
+    double interface_area;     /* (4/lambda) dx^3 sum phi(1-phi) (FP64, compensated) */
+    double interface_position; /* planar init: (V1 - V1(0)) / A_slab; single sphere:
+                                  radius R with (4pi/3)(R^3 + R pi^2 lambda^2/16) = V1;
+                                  otherwise NaN */
+    double velocity;           /* change of interface_position per unit time since the
+                                  previous spfm_diagnostics call; NaN on the first */
+    double phi_min, phi_max;
+    double sum_phi, sum_x;     /* the raw sums: sum phi, sum phi(1-phi) */
+    int32_t diverged;          /* number of points non-finite or |phi| > 2 */
+} spfm_diag;
+
+/* Parameters the library resolved at create time. */
+typedef struct {
+    double lambda, Gamma, M, mu, dt, dx, C_Gamma, eps, tau;
+    double gamma[3];
+    double dt_max;             /* explicit stability bound */
+    int32_t stencil, coupling, dtype, kernel;
+} spfm_info;
+
+typedef struct spfm_ctx spfm_ctx;
+typedef struct spfm_batch spfm_batch;
+
+/* Create a context for one periodic grid (Sec. 2.1 statement of the problem).
+ * lambda: interface width (Eq. 3), Gamma: interface energy, M: kinetic
+ * coefficient, mu: driving force (Eq. 1-2); stencil: 6, 18 or 26.
+ * Returns SPFM_E_INVAL for non-positive lambda, Gamma, M or dx, an unknown
+ * stencil, coupling or dtype, a grid edge below 3, a zero GLOBAL direction,
+ * F32 with lambda < 0.3 dx, or exactly one of d_phi given;
+ * SPFM_E_UNSTABLE when dt exceeds the explicit bound (unless allow_unstable).
+ * Argument checks happen before any HIP call.  The field is zero until set. */
+spfm_status spfm_create(const spfm_grid *grid, double lambda, double Gamma, double M, double mu,
+                        int stencil, const spfm_options *opt, spfm_ctx **out);
+/* Free the context and the buffers it allocated.  NULL is a no-op. */
+void spfm_destroy(spfm_ctx *ctx);
+
+/* Copy nx*ny*nz values of the context dtype into the current field.  Resets
+ * the step counter and the interface reference (position becomes NaN). */
+spfm_status spfm_set_field(spfm_ctx *ctx, const void *src, int src_on_device);
+/* Copy the current field out (synchronises when dst is host memory). */
+spfm_status spfm_get_field(spfm_ctx *ctx, void *dst, int dst_on_device);
+/* Device pointer of the current field (valid until the next spfm_step). */
+spfm_status spfm_field_ptr(spfm_ctx *ctx, void **d_ptr);
+
+/* Eq. 3 initial fields, computed on the device.
+ * Planar: periodic slab with integer normal hkl (not all zero): the field
+ * depends on s = p.N/|N| - c with period P = gcd_i(n_i |N_i|) dx / |N|; one
+ * period is phi = 1 of thickness P/2 between two ideal interfaces, summed over
+ * periodic images; c = box centre projected on N plus offset.
+ * Spheres: phi = 1 - prod_i (1 - phi_i), phi_i the ideal radial profile of
+ * radius radii[i] around centers[3i..3i+2] (host arrays, minimum-image
+ * distance).  Both reset the step counter and set the interface reference. */
+spfm_status spfm_init_planar(spfm_ctx *ctx, const int32_t hkl[3], double offset);
+spfm_status spfm_init_spheres(spfm_ctx *ctx, int32_t n, const double *centers,
+                              const double *radii);
+
+/* Change the driving force (re-checks the stability bound). */
+spfm_status spfm_set_mu(spfm_ctx *ctx, double mu);
+/* Enqueue n >= 0 forward-Euler steps (Eq. 2) on the context stream. */
+spfm_status spfm_step(spfm_ctx *ctx, int64_t n);
+/* FP64 compensated reductions of the current field (synchronises). */
+spfm_status spfm_diagnostics(spfm_ctx *ctx, spfm_diag *out);
+spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
+
+/* Many independent periodic grids of different sizes stepped together: one
+ * kernel launch per step covers every tile of every grid, and spfm_batch_step
+ * captures the launches of n steps in one HIP graph.  Arrays have n entries.
+ * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
+ * eps, tau, allow_unstable) apply to every grid; each grid gets its own
+ * lambda, Gamma, M, mu; d_phi must be NULL. */
+spfm_status spfm_batch_create(int32_t n, const spfm_grid *grids, const double *lambda,
+                              const double *Gamma, const double *M, const double *mu,
+                              int stencil, const spfm_options *opt, spfm_batch **out);
+void spfm_batch_destroy(spfm_batch *b);
+spfm_status spfm_batch_init_planar(spfm_batch *b, const int32_t *hkl /* 3n */,
+                                   const double *offset /* n */);
+spfm_status spfm_batch_set_field(spfm_batch *b, int32_t i, const void *src, int src_on_device);
+spfm_status spfm_batch_get_field(spfm_batch *b, int32_t i, void *dst, int dst_on_device);
+spfm_status spfm_batch_step(spfm_batch *b, int64_t n);
+spfm_status spfm_batch_diagnostics(spfm_batch *b, spfm_diag *out /* n entries */);
+/* Total points over all grids. */
+int64_t spfm_batch_points(const spfm_batch *b);
+
+/* Host-only helpers (no HIP call): the calibration C_Gamma(lambda/dx) used
+ * when C_Gamma <= 0, and the explicit stability bound for a parameter set. */
+double spfm_calibrate_cgamma(double lambda_over_dx, int coupling);
+double spfm_stable_dt(int stencil, int coupling, const double u[3], const double gamma[3],
+                      double lambda, double Gamma, double M, double mu, double dx,
+                      double C_Gamma);
+
+const char *spfm_status_string(spfm_status s);
+const char *spfm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPFM_H */

@@ -1,0 +1,657 @@
+// C ABI of the SPFM GPU library (declared in include/spfm.h).
+//
+// A context owns (or adopts) two device buffers holding phi^n and phi^{n+1},
+// the step coefficients, a small reduction scratch area and, on non-null
+// streams, cached HIP graphs of kGraphSteps consecutive step launches (one per
+// starting buffer) that spfm_step replays for long runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/spfm.h"
+#include "host_math.h"
+
+using namespace spfm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+spfm_status fail(spfm_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SPFM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr int kGraphSteps = 16;
+
+struct Resolved {
+    Params p;
+    int dtype, kernel, allow_unstable;
+    double dt_max;
+};
+
+// Validate and resolve everything that does not touch the GPU.
+spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, double mu,
+                    int stencil, const spfm_options* opt, Resolved* r) {
+    if (!g) return fail(SPFM_E_INVAL, "grid is NULL");
+    spfm_options o;
+    if (opt) o = *opt; else std::memset(&o, 0, sizeof o);
+    if (g->nx < 3 || g->ny < 3 || g->nz < 3)
+        return fail(SPFM_E_INVAL, "grid edges must be >= 3 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+    if ((int64_t)g->nx * g->ny >= (int64_t)1 << 31 || (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40) ||
+        g->nz > 65535 || g->ny > 65535 * kTileY)
+        return fail(SPFM_E_INVAL, "grid too large (nx*ny < 2^31, ny <= 262140, nz <= 65535)");
+    if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SPFM_E_INVAL, "dx must be > 0");
+    if (!(lambda > 0.0) || !(Gamma > 0.0) || !(M > 0.0) || !std::isfinite(lambda) ||
+        !std::isfinite(Gamma) || !std::isfinite(M))
+        return fail(SPFM_E_INVAL, "lambda, Gamma and M must be finite and > 0");
+    if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
+    if (stencil != 6 && stencil != 18 && stencil != 26)
+        return fail(SPFM_E_INVAL, "stencil must be 6, 18 or 26 (got %d)", stencil);
+    if (o.dtype != SPFM_F32 && o.dtype != SPFM_F64) return fail(SPFM_E_INVAL, "unknown dtype %d", o.dtype);
+    if (o.coupling != SPFM_LOCAL && o.coupling != SPFM_GLOBAL && o.coupling != SPFM_CF)
+        return fail(SPFM_E_INVAL, "unknown coupling %d", o.coupling);
+    if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_TILED)
+        return fail(SPFM_E_INVAL, "unknown kernel %d", o.kernel);
+    const double un = std::sqrt(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2]);
+    if (o.coupling == SPFM_GLOBAL && !(un > 0.0 && std::isfinite(un)))
+        return fail(SPFM_E_INVAL, "GLOBAL coupling needs a nonzero direction u");
+    if (o.dtype == SPFM_F32 && lambda < 0.3 * g->dx)
+        return fail(SPFM_E_INVAL, "F32 needs lambda >= 0.3 dx (got lambda/dx = %g)", lambda / g->dx);
+    if ((o.d_phi[0] == nullptr) != (o.d_phi[1] == nullptr))
+        return fail(SPFM_E_INVAL, "give both d_phi buffers or neither");
+    if (o.d_phi[0] && o.d_phi[0] == o.d_phi[1]) return fail(SPFM_E_INVAL, "d_phi buffers must differ");
+    Params& p = r->p;
+    p.nx = g->nx; p.ny = g->ny; p.nz = g->nz;
+    p.dx = g->dx; p.lambda = lambda; p.Gamma = Gamma; p.M = M; p.mu = mu;
+    p.stencil = stencil; p.coupling = o.coupling;
+    for (int i = 0; i < 3; ++i) p.u[i] = o.u[i];
+    if (o.gamma[0] == 0.0 && o.gamma[1] == 0.0 && o.gamma[2] == 0.0) {
+        default_gamma(stencil, p.gamma);
+    } else {
+        for (int i = 0; i < 3; ++i) {
+            if (!(o.gamma[i] >= 0.0) || !std::isfinite(o.gamma[i]))
+                return fail(SPFM_E_INVAL, "shell weights must be finite and >= 0");
+            p.gamma[i] = o.gamma[i];
+        }
+    }
+    p.C_Gamma = o.C_Gamma > 0.0 ? o.C_Gamma : calibrate_cgamma(lambda / g->dx, o.coupling);
+    if (!(p.C_Gamma > 0.0) || !std::isfinite(p.C_Gamma)) return fail(SPFM_E_INVAL, "bad C_Gamma");
+    p.eps = o.eps > 0.0 ? o.eps : (o.dtype == SPFM_F32 ? 1e-30 : 1e-300);
+    p.tau = o.tau > 0.0 ? o.tau : 1e-3;
+    p.dt = o.dt > 0.0 ? o.dt : 0.1 * g->dx * g->dx / (M * Gamma);
+    if (!std::isfinite(p.dt)) return fail(SPFM_E_INVAL, "dt must be finite");
+    r->dtype = o.dtype;
+    r->kernel = o.kernel == SPFM_KERNEL_AUTO ? SPFM_KERNEL_TILED : o.kernel;
+    r->allow_unstable = o.allow_unstable;
+    r->dt_max = stable_dt(stencil, o.coupling, p.u, p.gamma, lambda, Gamma, M, mu, g->dx, p.C_Gamma);
+    if (!o.allow_unstable && p.dt > r->dt_max)
+        return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, r->dt_max);
+    return SPFM_OK;
+}
+
+size_t elem_size(int dtype) { return dtype == SPFM_F64 ? 8 : 4; }
+
+bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+// Reduction scratch: per-block partials and the pinned host copy of the result.
+struct Reducer {
+    double* d_partials = nullptr;
+    ReduceOut* d_out = nullptr;
+    ReduceOut* h_out = nullptr;
+    spfm_status init() {
+        HIP_TRY(hipMalloc(&d_partials, sizeof(double) * kReduceBlocks * kPartialStride));
+        HIP_TRY(hipMalloc(&d_out, sizeof(ReduceOut)));
+        HIP_TRY(hipHostMalloc(&h_out, sizeof(ReduceOut), hipHostMallocDefault));
+        return SPFM_OK;
+    }
+    void release() {
+        if (d_partials) (void)hipFree(d_partials);
+        if (d_out) (void)hipFree(d_out);
+        if (h_out) (void)hipHostFree(h_out);
+        d_partials = nullptr; d_out = nullptr; h_out = nullptr;
+    }
+    // Reduce n values of dtype at d_phi into *h_out (synchronises s).
+    spfm_status run(const void* d_phi, int dtype, int64_t n, hipStream_t s) {
+        hipError_t e = dtype == SPFM_F64
+                           ? launch_reduce<double>((const double*)d_phi, n, d_partials, d_out, s)
+                           : launch_reduce<float>((const float*)d_phi, n, d_partials, d_out, s);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "reduction launch: %s", hipGetErrorString(e));
+        HIP_TRY(hipMemcpyAsync(h_out, d_out, sizeof(ReduceOut), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SPFM_OK;
+    }
+};
+
+// Interface bookkeeping of the diagnostics.
+struct Tracker {
+    int kind = 0;            // 0 none, 1 planar slab, 2 single sphere
+    double V1_ref = 0.0, A_ref = 0.0;
+    bool ref_pending = false;
+    bool have_last = false;
+    double last_pos = 0.0, last_time = 0.0;
+    void reset(int k, double area) {
+        kind = k; A_ref = area; ref_pending = (k == 1); have_last = false;
+    }
+    void fill(spfm_diag* d, const ReduceOut& r, double dx, double lambda, int64_t step, double dt) {
+        const double dv = dx * dx * dx;
+        d->step = step;
+        d->time = step * dt;
+        d->sum_phi = r.sum_phi;
+        d->sum_x = r.sum_x;
+        d->phase_volume = r.sum_phi * dv;
+        d->interface_area = 4.0 / lambda * r.sum_x * dv;
+        d->phi_min = r.phi_min;
+        d->phi_max = r.phi_max;
+        d->diverged = (int32_t)std::min<unsigned long long>(r.bad, 0x7fffffffULL);
+        if (kind == 1 && ref_pending) { V1_ref = d->phase_volume; ref_pending = false; }
+        double pos = NAN;
+        if (kind == 1) {
+            pos = (d->phase_volume - V1_ref) / A_ref;
+        } else if (kind == 2) {
+            // (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) = V1, Newton from the sharp radius
+            const double V = d->phase_volume, c = M_PI * M_PI * lambda * lambda / 16.0;
+            double R = std::cbrt(3.0 * V / (4.0 * M_PI));
+            for (int it = 0; it < 60 && R > 0.0; ++it)
+                R -= (4.0 * M_PI / 3.0 * (R * R * R + R * c) - V) / (4.0 * M_PI / 3.0 * (3.0 * R * R + c));
+            pos = R;
+        }
+        d->interface_position = pos;
+        d->velocity = (have_last && d->time != last_time) ? (pos - last_pos) / (d->time - last_time) : NAN;
+        if (d->time != last_time || !have_last) {
+            last_pos = pos; last_time = d->time; have_last = true;
+        }
+    }
+};
+
+double slab_area(int nx, int ny, int nz, double dx, const int32_t hkl[3]) {
+    auto gcd = [](int64_t a, int64_t b) {
+        a = a < 0 ? -a : a; b = b < 0 ? -b : b;
+        while (b) { int64_t t = a % b; a = b; b = t; }
+        return a;
+    };
+    const double nn = std::sqrt((double)hkl[0] * hkl[0] + (double)hkl[1] * hkl[1] + (double)hkl[2] * hkl[2]);
+    const int64_t g = gcd(gcd(gcd(0, (int64_t)nx * hkl[0]), (int64_t)ny * hkl[1]), (int64_t)nz * hkl[2]);
+    const double P = (double)g * dx / nn;
+    return 2.0 * (double)nx * ny * nz * dx * dx * dx / P;
+}
+
+// Replays of kGraphSteps launches captured from a step function, one graph per
+// starting buffer; invalidated whenever the coefficients change.
+struct GraphCache {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    void clear() {
+        for (auto& e : exec) {
+            if (e) (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    }
+};
+
+}  // namespace
+
+struct spfm_ctx {
+    Resolved r;
+    hipStream_t stream = nullptr;
+    void* buf[2] = {nullptr, nullptr};
+    bool owns = false;
+    int cur = 0;
+    int64_t nsteps = 0;
+    StepCoef<float> kf;
+    StepCoef<double> kd;
+    Reducer red;
+    Tracker track;
+    GraphCache graphs;
+
+    int64_t points() const { return (int64_t)r.p.nx * r.p.ny * r.p.nz; }
+    size_t bytes() const { return (size_t)points() * elem_size(r.dtype); }
+
+    hipError_t launch_one(int from) {
+        const void* in = buf[from];
+        void* out = buf[1 - from];
+        const int S = r.p.stencil, C = r.p.coupling;
+        if (r.dtype == SPFM_F64) {
+            return r.kernel == SPFM_KERNEL_PLAIN
+                       ? launch_step_plain<double>((const double*)in, (double*)out, kd, S, C, stream)
+                       : launch_step_tiled<double>((const double*)in, (double*)out, kd, S, C, stream);
+        }
+        return r.kernel == SPFM_KERNEL_PLAIN
+                   ? launch_step_plain<float>((const float*)in, (float*)out, kf, S, C, stream)
+                   : launch_step_tiled<float>((const float*)in, (float*)out, kf, S, C, stream);
+    }
+    void refresh_coef() {
+        kf = make_coef<float>(r.p);
+        kd = make_coef<double>(r.p);
+        graphs.clear();
+    }
+};
+
+struct spfm_batch {
+    int n = 0;
+    std::vector<Resolved> r;
+    std::vector<int64_t> offset;   // element offset of each grid in the buffers
+    int64_t total = 0;              // allocated elements (with padding)
+    int64_t points = 0;
+    hipStream_t stream = nullptr;
+    float* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t nsteps = 0;
+    StepCoef<float>* d_coef = nullptr;
+    int64_t* d_offset = nullptr;
+    TileItem* d_items = nullptr;
+    int nitems = 0;
+    int stencil = 26, coupling = 0;
+    Reducer red;
+    std::vector<Tracker> track;
+    GraphCache graphs;
+
+    hipError_t launch_one(int from) {
+        return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
+                                   stencil, coupling, stream);
+    }
+};
+
+namespace {
+
+template <typename Obj>
+spfm_status run_steps(Obj* o, int64_t n) {
+    if (n < 0) return fail(SPFM_E_INVAL, "negative step count");
+    int64_t left = n;
+    if (o->stream != nullptr && n >= 2 * kGraphSteps) {
+        for (int from = 0; from < 2; ++from) {
+            if (o->graphs.exec[from]) continue;
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(o->stream, hipStreamCaptureModeRelaxed));
+            hipError_t le = hipSuccess;
+            for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) le = o->launch_one((from + s) & 1);
+            hipError_t ce = hipStreamEndCapture(o->stream, &g);
+            if (le != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(SPFM_E_HIP, "step launch during capture: %s", hipGetErrorString(le));
+            }
+            if (ce != hipSuccess) return fail(SPFM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&o->graphs.exec[from], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                o->graphs.exec[from] = nullptr;
+                return fail(SPFM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            }
+        }
+        while (left >= kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(o->graphs.exec[o->cur], o->stream));
+            left -= kGraphSteps;   // kGraphSteps is even: the current buffer is unchanged
+            o->nsteps += kGraphSteps;
+        }
+    }
+    for (; left > 0; --left) {
+        hipError_t e = o->launch_one(o->cur);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "step launch: %s", hipGetErrorString(e));
+        o->cur ^= 1;
+        o->nsteps += 1;
+    }
+    return SPFM_OK;
+}
+
+spfm_status copy_in(void* dst, const void* src, size_t bytes, int src_on_device, hipStream_t s) {
+    if (!src) return fail(SPFM_E_INVAL, "source is NULL");
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (!src_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return SPFM_OK;
+}
+
+spfm_status copy_out(void* dst, const void* src, size_t bytes, int dst_on_device, hipStream_t s) {
+    if (!dst) return fail(SPFM_E_INVAL, "destination is NULL");
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return SPFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, double M, double mu,
+                        int stencil, const spfm_options* opt, spfm_ctx** out) {
+    if (!out) return fail(SPFM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Resolved r;
+    spfm_status st = resolve(grid, lambda, Gamma, M, mu, stencil, opt, &r);
+    if (st != SPFM_OK) return st;
+    spfm_ctx* c = new (std::nothrow) spfm_ctx;
+    if (!c) return fail(SPFM_E_NOMEM, "host allocation failed");
+    c->r = r;
+    c->stream = opt ? (hipStream_t)opt->stream : nullptr;
+    const size_t bytes = c->bytes();
+    if (opt && opt->d_phi[0]) {
+        c->buf[0] = opt->d_phi[0];
+        c->buf[1] = opt->d_phi[1];
+        c->owns = false;
+    } else {
+        c->owns = true;
+        if (hipMalloc(&c->buf[0], bytes) != hipSuccess || hipMalloc(&c->buf[1], bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            spfm_destroy(c);
+            return fail(SPFM_E_NOMEM, "device allocation of 2 x %zu bytes failed", bytes);
+        }
+        if (hipMemsetAsync(c->buf[0], 0, bytes, c->stream) != hipSuccess) {
+            spfm_destroy(c);
+            return fail(SPFM_E_HIP, "hipMemsetAsync failed");
+        }
+    }
+    st = c->red.init();
+    if (st != SPFM_OK) { spfm_destroy(c); return st; }
+    c->refresh_coef();
+    *out = c;
+    return SPFM_OK;
+}
+
+void spfm_destroy(spfm_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    c->graphs.clear();
+    c->red.release();
+    if (c->owns) {
+        if (c->buf[0]) (void)hipFree(c->buf[0]);
+        if (c->buf[1]) (void)hipFree(c->buf[1]);
+    }
+    delete c;
+}
+
+spfm_status spfm_set_field(spfm_ctx* c, const void* src, int src_on_device) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    spfm_status st = copy_in(c->buf[c->cur], src, c->bytes(), src_on_device, c->stream);
+    if (st != SPFM_OK) return st;
+    c->nsteps = 0;
+    c->track.reset(0, 0.0);
+    return SPFM_OK;
+}
+
+spfm_status spfm_get_field(spfm_ctx* c, void* dst, int dst_on_device) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    return copy_out(dst, c->buf[c->cur], c->bytes(), dst_on_device, c->stream);
+}
+
+spfm_status spfm_field_ptr(spfm_ctx* c, void** d_ptr) {
+    if (!c || !d_ptr) return fail(SPFM_E_INVAL, "NULL argument");
+    *d_ptr = c->buf[c->cur];
+    return SPFM_OK;
+}
+
+spfm_status spfm_init_planar(spfm_ctx* c, const int32_t hkl[3], double offset) {
+    if (!c || !hkl) return fail(SPFM_E_INVAL, "NULL argument");
+    if (hkl[0] == 0 && hkl[1] == 0 && hkl[2] == 0) return fail(SPFM_E_INVAL, "hkl must not be zero");
+    if (!std::isfinite(offset)) return fail(SPFM_E_INVAL, "offset must be finite");
+    const Params& p = c->r.p;
+    const int h[3] = {hkl[0], hkl[1], hkl[2]};
+    hipError_t e = c->r.dtype == SPFM_F64
+                       ? launch_init_planar<double>((double*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx,
+                                                    p.lambda, h, offset, c->stream)
+                       : launch_init_planar<float>((float*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx,
+                                                   p.lambda, h, offset, c->stream);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "init launch: %s", hipGetErrorString(e));
+    c->nsteps = 0;
+    c->track.reset(1, slab_area(p.nx, p.ny, p.nz, p.dx, hkl));
+    return SPFM_OK;
+}
+
+spfm_status spfm_init_spheres(spfm_ctx* c, int32_t n, const double* centers, const double* radii) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!centers || !radii))) return fail(SPFM_E_INVAL, "bad sphere list");
+    std::vector<double> h((size_t)std::max(n, 1) * 4, 0.0);
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) h[4 * i + a] = centers[3 * i + a];
+        h[4 * i + 3] = radii[i];
+        for (int a = 0; a < 4; ++a)
+            if (!std::isfinite(h[4 * i + a])) return fail(SPFM_E_INVAL, "non-finite sphere %d", i);
+    }
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * h.size()));
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
+    const Params& p = c->r.p;
+    if (e == hipSuccess) {
+        e = c->r.dtype == SPFM_F64
+                ? launch_init_spheres<double>((double*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream)
+                : launch_init_spheres<float>((float*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream);
+    }
+    hipError_t se = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "sphere init: %s", hipGetErrorString(e));
+    if (se != hipSuccess) return fail(SPFM_E_HIP, "sphere init sync: %s", hipGetErrorString(se));
+    c->nsteps = 0;
+    c->track.reset(n == 1 ? 2 : 0, 0.0);
+    return SPFM_OK;
+}
+
+spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
+    Params p = c->r.p;
+    p.mu = mu;
+    const double dtm = stable_dt(p.stencil, p.coupling, p.u, p.gamma, p.lambda, p.Gamma, p.M, mu, p.dx, p.C_Gamma);
+    if (!c->r.allow_unstable && p.dt > dtm)
+        return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, dtm);
+    c->r.p = p;
+    c->r.dt_max = dtm;
+    c->refresh_coef();
+    return SPFM_OK;
+}
+
+spfm_status spfm_step(spfm_ctx* c, int64_t n) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    return run_steps(c, n);
+}
+
+spfm_status spfm_diagnostics(spfm_ctx* c, spfm_diag* out) {
+    if (!c || !out) return fail(SPFM_E_INVAL, "NULL argument");
+    spfm_status st = c->red.run(c->buf[c->cur], c->r.dtype, c->points(), c->stream);
+    if (st != SPFM_OK) return st;
+    c->track.fill(out, *c->red.h_out, c->r.p.dx, c->r.p.lambda, c->nsteps, c->r.p.dt);
+    if (out->diverged) return fail(SPFM_E_DIVERGED, "%d points are non-finite or |phi| > 2", out->diverged);
+    return SPFM_OK;
+}
+
+spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
+    if (!c || !o) return fail(SPFM_E_INVAL, "NULL argument");
+    const Params& p = c->r.p;
+    o->lambda = p.lambda; o->Gamma = p.Gamma; o->M = p.M; o->mu = p.mu; o->dt = p.dt; o->dx = p.dx;
+    o->C_Gamma = p.C_Gamma; o->eps = p.eps; o->tau = p.tau;
+    for (int i = 0; i < 3; ++i) o->gamma[i] = p.gamma[i];
+    o->dt_max = c->r.dt_max;
+    o->stencil = p.stencil; o->coupling = p.coupling; o->dtype = c->r.dtype; o->kernel = c->r.kernel;
+    return SPFM_OK;
+}
+
+// ---------------------------------------------------------------- batch ----
+
+void spfm_batch_destroy(spfm_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
+    b->graphs.clear();
+    b->red.release();
+    if (b->buf[0]) (void)hipFree(b->buf[0]);
+    if (b->buf[1]) (void)hipFree(b->buf[1]);
+    if (b->d_coef) (void)hipFree(b->d_coef);
+    if (b->d_offset) (void)hipFree(b->d_offset);
+    if (b->d_items) (void)hipFree(b->d_items);
+    delete b;
+}
+
+spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* lambda,
+                              const double* Gamma, const double* M, const double* mu, int stencil,
+                              const spfm_options* opt, spfm_batch** out) {
+    if (!out) return fail(SPFM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n <= 0 || !grids || !lambda || !Gamma || !M || !mu) return fail(SPFM_E_INVAL, "bad batch arrays");
+    spfm_options o;
+    if (opt) o = *opt; else std::memset(&o, 0, sizeof o);
+    if (o.dtype != SPFM_F32) return fail(SPFM_E_INVAL, "batches run in F32");
+    if (o.d_phi[0] || o.d_phi[1]) return fail(SPFM_E_INVAL, "batches allocate their own buffers");
+    if (o.C_Gamma > 0.0) return fail(SPFM_E_INVAL, "batches calibrate C_Gamma per grid");
+    if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
+    spfm_batch* b = new (std::nothrow) spfm_batch;
+    if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
+    b->n = n;
+    b->stencil = stencil;
+    b->coupling = o.coupling;
+    b->stream = (hipStream_t)o.stream;
+    b->r.resize(n);
+    b->track.resize(n);
+    b->offset.resize(n);
+    std::vector<StepCoef<float>> coef(n);
+    std::vector<TileItem> items;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        spfm_status st = resolve(&grids[i], lambda[i], Gamma[i], M[i], mu[i], stencil, &o, &b->r[i]);
+        if (st != SPFM_OK) {
+            spfm_batch_destroy(b);
+            char tmp[512];
+            std::snprintf(tmp, sizeof tmp, "grid %d: %s", i, g_err);
+            std::snprintf(g_err, sizeof g_err, "%s", tmp);
+            return st;
+        }
+        const Params& p = b->r[i].p;
+        coef[i] = make_coef<float>(p);
+        b->offset[i] = off;
+        const int64_t np = (int64_t)p.nx * p.ny * p.nz;
+        b->points += np;
+        off += (np + 63) / 64 * 64;   // keep every grid 256-byte aligned
+        for (int z0 = 0; z0 < p.nz; z0 += kTileZ)
+            for (int y0 = 0; y0 < p.ny; y0 += kTileY)
+                for (int x0 = 0; x0 < p.nx; x0 += kTileX) items.push_back(TileItem{i, x0, y0, z0});
+    }
+    if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
+    b->total = off;
+    b->nitems = (int)items.size();
+    const size_t bytes = (size_t)off * sizeof(float);
+    if (hipMalloc(&b->buf[0], bytes) != hipSuccess || hipMalloc(&b->buf[1], bytes) != hipSuccess ||
+        hipMalloc(&b->d_coef, sizeof(StepCoef<float>) * n) != hipSuccess ||
+        hipMalloc(&b->d_offset, sizeof(int64_t) * n) != hipSuccess ||
+        hipMalloc(&b->d_items, sizeof(TileItem) * items.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        spfm_batch_destroy(b);
+        return fail(SPFM_E_NOMEM, "device allocation failed");
+    }
+    spfm_status st = b->red.init();
+    if (st != SPFM_OK) { spfm_batch_destroy(b); return st; }
+    if (hipMemcpy(b->d_coef, coef.data(), sizeof(StepCoef<float>) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_offset, b->offset.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_items, items.data(), sizeof(TileItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->buf[0], 0, bytes) != hipSuccess || hipMemset(b->buf[1], 0, bytes) != hipSuccess) {
+        spfm_batch_destroy(b);
+        return fail(SPFM_E_HIP, "batch upload failed");
+    }
+    *out = b;
+    return SPFM_OK;
+}
+
+spfm_status spfm_batch_init_planar(spfm_batch* b, const int32_t* hkl, const double* offset) {
+    if (!b || !hkl || !offset) return fail(SPFM_E_INVAL, "NULL argument");
+    for (int i = 0; i < b->n; ++i) {
+        const int32_t* h = hkl + 3 * i;
+        if (h[0] == 0 && h[1] == 0 && h[2] == 0) return fail(SPFM_E_INVAL, "grid %d: hkl is zero", i);
+        if (!std::isfinite(offset[i])) return fail(SPFM_E_INVAL, "grid %d: offset not finite", i);
+    }
+    for (int i = 0; i < b->n; ++i) {
+        const Params& p = b->r[i].p;
+        const int h[3] = {hkl[3 * i], hkl[3 * i + 1], hkl[3 * i + 2]};
+        hipError_t e = launch_init_planar<float>(b->buf[b->cur] + b->offset[i], p.nx, p.ny, p.nz,
+                                                 p.dx, p.lambda, h, offset[i], b->stream);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "init launch: %s", hipGetErrorString(e));
+        b->track[i].reset(1, slab_area(p.nx, p.ny, p.nz, p.dx, hkl + 3 * i));
+    }
+    b->nsteps = 0;
+    return SPFM_OK;
+}
+
+spfm_status spfm_batch_set_field(spfm_batch* b, int32_t i, const void* src, int src_on_device) {
+    if (!b || i < 0 || i >= b->n) return fail(SPFM_E_INVAL, "bad batch index");
+    const Params& p = b->r[i].p;
+    const size_t bytes = (size_t)p.nx * p.ny * p.nz * sizeof(float);
+    spfm_status st = copy_in(b->buf[b->cur] + b->offset[i], src, bytes, src_on_device, b->stream);
+    if (st != SPFM_OK) return st;
+    b->track[i].reset(0, 0.0);
+    return SPFM_OK;
+}
+
+spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on_device) {
+    if (!b || i < 0 || i >= b->n) return fail(SPFM_E_INVAL, "bad batch index");
+    const Params& p = b->r[i].p;
+    const size_t bytes = (size_t)p.nx * p.ny * p.nz * sizeof(float);
+    return copy_out(dst, b->buf[b->cur] + b->offset[i], bytes, dst_on_device, b->stream);
+}
+
+spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
+    if (!b) return fail(SPFM_E_INVAL, "batch is NULL");
+    return run_steps(b, n);
+}
+
+spfm_status spfm_batch_diagnostics(spfm_batch* b, spfm_diag* out) {
+    if (!b || !out) return fail(SPFM_E_INVAL, "NULL argument");
+    int bad = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const Params& p = b->r[i].p;
+        spfm_status st = b->red.run(b->buf[b->cur] + b->offset[i], SPFM_F32,
+                                    (int64_t)p.nx * p.ny * p.nz, b->stream);
+        if (st != SPFM_OK) return st;
+        b->track[i].fill(&out[i], *b->red.h_out, p.dx, p.lambda, b->nsteps, p.dt);
+        bad += out[i].diverged;
+    }
+    if (bad) return fail(SPFM_E_DIVERGED, "%d points are non-finite or |phi| > 2", bad);
+    return SPFM_OK;
+}
+
+int64_t spfm_batch_points(const spfm_batch* b) { return b ? b->points : 0; }
+
+double spfm_calibrate_cgamma(double lambda_over_dx, int coupling) {
+    return calibrate_cgamma(lambda_over_dx, coupling);
+}
+
+double spfm_stable_dt(int stencil, int coupling, const double u[3], const double gamma[3],
+                      double lambda, double Gamma, double M, double mu, double dx, double C_Gamma) {
+    double g[3];
+    if (!gamma || (gamma[0] == 0.0 && gamma[1] == 0.0 && gamma[2] == 0.0)) default_gamma(stencil, g);
+    else for (int i = 0; i < 3; ++i) g[i] = gamma[i];
+    const double zero[3] = {1.0, 0.0, 0.0};
+    if (C_Gamma <= 0.0) C_Gamma = calibrate_cgamma(lambda / dx, coupling);
+    return stable_dt(stencil, coupling, u ? u : zero, g, lambda, Gamma, M, mu, dx, C_Gamma);
+}
+
+const char* spfm_status_string(spfm_status s) {
+    switch (s) {
+        case SPFM_OK: return "ok";
+        case SPFM_E_INVAL: return "invalid argument";
+        case SPFM_E_NOMEM: return "out of memory";
+        case SPFM_E_HIP: return "HIP runtime error";
+        case SPFM_E_UNSTABLE: return "time step above the explicit stability bound";
+        case SPFM_E_DIVERGED: return "field diverged";
+        case SPFM_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* spfm_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Internal declarations of the SPFM GPU library: step coefficients, the
+// per-point update shared by every step kernel, and the kernel launchers.
+//
+// Per-point update (forward Euler of Eq. 2 with the functional derivative of
+// Eq. 1).  With x = phi(1-phi), u = 1-2phi and shell weights
+// W_j = gamma_j nu_j / |r_j|^2:
+//
+//   d_t phi = A lambda^2 sum_k W_k (D_k - P_k) - 6 B x,
+//   A = 2M / (3 C_Gamma lambda^2),  B = 2 M mu / (3 lambda Gamma),
+//
+// D_k = phi(p+r_k) + phi(p-r_k) - 2 phi(p) is the second difference along
+// direction k and P_k = (|r_k|^2/lambda^2) g_k'(phi) is the second difference
+// the ideal profile of Eq. 3 would have there (Eq. 4-6).  Writing
+// a_k = tanh(beta_k/2), beta_k = 4 r_k.n / lambda, the derivative of Eq. 6
+// becomes  P_k = u y_k / (1 + y_k),  y_k = m_k x,  m_k = 2 cosh(beta_k) - 2,
+// so the TI coupling needs only m_k, which for TI_n is built from
+// E_i = exp(4 dx n_i / lambda) by hyperbolic addition formulas.  The sum over
+// each shell is accumulated as one fraction (one reciprocal per shell).
+// The CF control has P_k = (|r_k|^2 / lambda^2) (16/3) x u instead.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spfm {
+
+enum Coupling : int { kLocal = 0, kGlobal = 1, kCF = 2 };
+
+template <typename T>
+struct StepCoef {
+    int nx, ny, nz;
+    int pad;
+    T K[3];    // dt A lambda^2 W_j per shell
+    T kcf;     // CF: dt A (16/3) sum_k gamma_j nu_j
+    T b;       // dt 6 B
+    T kap2;    // LOCAL: 4 dx / (lambda ln 2), exponent scale for exp2
+    T eps;     // floor of the log arguments in psi
+    T tau2;    // LOCAL: |grad log2((1-phi)/phi)|^2 (central differences, per 2 dx)
+               // below tau2 -> normal (1,0,0)
+    T mg[13];  // GLOBAL: m_k per direction, shells 1|2|3 as in point_update
+};
+
+// psi' = log2((1-phi)/phi) with both arguments floored at eps; the interface
+// normal is the direction of grad psi' (psi = (lambda ln2 / 4) psi' is the
+// inverse of Eq. 3, linear in position on an ideal profile).
+// FP32 uses the native CDNA transcendental instructions (v_log_f32, v_exp_f32,
+// v_rcp_f32, v_rsq_f32; about 1 ulp); FP64 uses the full-precision library.
+__device__ __forceinline__ float psi2(float phi, float eps) {
+    return __builtin_amdgcn_logf(fmaxf(1.0f - phi, eps)) - __builtin_amdgcn_logf(fmaxf(phi, eps));
+}
+__device__ __forceinline__ double psi2(double phi, double eps) {
+    return log2(fmax(1.0 - phi, eps)) - log2(fmax(phi, eps));
+}
+__device__ __forceinline__ float fast_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
+__device__ __forceinline__ double fast_exp2(double v) { return exp2(v); }
+__device__ __forceinline__ float fast_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double fast_rsqrt(double v) { return rsqrt(v); }
+__device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double fast_rcp(double v) { return 1.0 / v; }
+
+// Running sum of y_k / (1 + y_k) kept as one fraction num/den.
+template <typename T>
+struct Frac {
+    T num, den;
+    __device__ __forceinline__ Frac() : num(T(0)), den(T(1)) {}
+    __device__ __forceinline__ void add(T y) {
+        num = fma(y, num + den, num);
+        den = fma(den, y, den);
+    }
+    __device__ __forceinline__ T value() const { return num * fast_rcp(den); }
+};
+
+// New value of phi at one point.  at(dx,dy,dz) returns phi at the offset
+// (dx,dy,dz in {-1,0,1}); grad(gx,gy,gz) sets the central differences of psi'
+// across the point (LOCAL only; called only where phi(1-phi) != 0).
+template <typename T, int S, int C, typename At, typename Grad>
+__device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k) {
+    const T p = at(0, 0, 0);
+    // Second differences summed per shell, formed from differences to the
+    // centre value (exact for nearby values, which keeps FP32 bulk regions clean).
+    T s1 = ((at(1, 0, 0) - p) + (at(-1, 0, 0) - p)) + ((at(0, 1, 0) - p) + (at(0, -1, 0) - p)) +
+           ((at(0, 0, 1) - p) + (at(0, 0, -1) - p));
+    T s2 = T(0), s3 = T(0);
+    if (S >= 18) {
+        s2 = (((at(1, 1, 0) - p) + (at(-1, -1, 0) - p)) + ((at(1, -1, 0) - p) + (at(-1, 1, 0) - p))) +
+             (((at(0, 1, 1) - p) + (at(0, -1, -1) - p)) + ((at(0, 1, -1) - p) + (at(0, -1, 1) - p))) +
+             (((at(1, 0, 1) - p) + (at(-1, 0, -1) - p)) + ((at(1, 0, -1) - p) + (at(-1, 0, 1) - p)));
+    }
+    if (S >= 26) {
+        s3 = (((at(1, 1, 1) - p) + (at(-1, -1, -1) - p)) + ((at(1, 1, -1) - p) + (at(-1, -1, 1) - p))) +
+             (((at(1, -1, 1) - p) + (at(-1, 1, -1) - p)) + ((at(-1, 1, 1) - p) + (at(1, -1, -1) - p)));
+    }
+    const T x = p * (T(1) - p);
+    const T u = T(1) - T(2) * p;
+    T upd = k.K[0] * s1;
+    if (S >= 18) upd = fma(k.K[1], s2, upd);
+    if (S >= 26) upd = fma(k.K[2], s3, upd);
+    if (C == kCF) {
+        upd = fma(-k.kcf, x * u, upd);
+    } else if (x != T(0)) {
+        // m_k = 2 cosh(beta_k) - 2 for the 13 directions.
+        T m1x, m1y, m1z;                        // shell 1: x, y, z
+        T m2[6];                                // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
+        T m3[4];                                // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
+        if (C == kLocal) {
+            T gx, gy, gz;
+            grad(gx, gy, gz);
+            T g2 = gx * gx + gy * gy + gz * gz;
+            if (!(g2 >= k.tau2)) { gx = T(1); gy = T(0); gz = T(0); g2 = T(1); }
+            const T sc = k.kap2 * fast_rsqrt(g2);
+            const T ex = fast_exp2(sc * gx), ey = fast_exp2(sc * gy), ez = fast_exp2(sc * gz);
+            const T r = fast_rcp(ex * ey * ez);
+            const T rx = r * ey * ez, ry = r * ex * ez, rz = r * ex * ey;
+            // c_i = 2cosh - 2 = (E-1)^2/E,  s_i = 2 sinh = E - 1/E
+            const T cx = (ex - T(1)) * (ex - T(1)) * rx, sx = ex - rx;
+            const T cy = (ey - T(1)) * (ey - T(1)) * ry, sy = ey - ry;
+            const T cz = (ez - T(1)) * (ez - T(1)) * rz, sz = ez - rz;
+            m1x = cx; m1y = cy; m1z = cz;
+            // 2cosh(a+-b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2
+            {
+                const T pc = cx * cy, ps = sx * sy, base = cx + cy;
+                m2[0] = fma(T(0.5), pc + ps, base);
+                m2[1] = fma(T(0.5), pc - ps, base);
+            }
+            {
+                const T pc = cy * cz, ps = sy * sz, base = cy + cz;
+                m2[2] = fma(T(0.5), pc + ps, base);
+                m2[3] = fma(T(0.5), pc - ps, base);
+            }
+            {
+                const T pc = cx * cz, ps = sx * sz, base = cx + cz;
+                m2[4] = fma(T(0.5), pc + ps, base);
+                m2[5] = fma(T(0.5), pc - ps, base);
+            }
+            if (S >= 26) {
+                // 2sinh(a+-b) = (s_a (c_b+2) +- (c_a+2) s_b)/2, then
+                // 2cosh(w+-z) - 2 = m_w + c_z + (m_w c_z +- s_w s_z)/2
+                const T hxy_p = T(0.5) * (sx * (cy + T(2)) + (cx + T(2)) * sy);
+                const T hxy_m = T(0.5) * (sx * (cy + T(2)) - (cx + T(2)) * sy);
+                {
+                    const T pc = m2[0] * cz, ps = hxy_p * sz, base = m2[0] + cz;
+                    m3[0] = fma(T(0.5), pc + ps, base);
+                    m3[1] = fma(T(0.5), pc - ps, base);
+                }
+                {
+                    const T pc = m2[1] * cz, ps = hxy_m * sz, base = m2[1] + cz;
+                    m3[2] = fma(T(0.5), pc + ps, base);
+                    m3[3] = fma(T(0.5), pc - ps, base);
+                }
+            }
+        } else {
+            m1x = k.mg[0]; m1y = k.mg[1]; m1z = k.mg[2];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) m2[i] = k.mg[3 + i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) m3[i] = k.mg[9 + i];
+        }
+        Frac<T> f1;
+        f1.add(m1x * x); f1.add(m1y * x); f1.add(m1z * x);
+        T q = k.K[0] * f1.value();
+        if (S >= 18) {
+            Frac<T> f2;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) f2.add(m2[i] * x);
+            q = fma(k.K[1], f2.value(), q);
+        }
+        if (S >= 26) {
+            Frac<T> f3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f3.add(m3[i] * x);
+            q = fma(k.K[2], f3.value(), q);
+        }
+        upd = fma(-u, q, upd);
+    }
+    upd = fma(-k.b, x, upd);
+    return p + upd;
+}
+
+// ---- launchers (step_kernels.hip, reduce.hip, init.hip) ----
+struct TileItem {   // one block of the batched step: grid index and tile origin
+    int inst;
+    int x0, y0, z0;
+};
+
+template <typename T>
+hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
+                             hipStream_t s);
+// Batched step: instance i reads buf_in + offset[i], writes buf_out + offset[i].
+hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
+                               const int64_t* d_offset, const TileItem* d_items, int nitems,
+                               int stencil, int coupling, hipStream_t s);
+constexpr int kTileX = 64;
+constexpr int kTileY = 4;
+constexpr int kTileZ = 32;
+
+struct ReduceOut {   // device result of the diagnostics reduction
+    double sum_phi, sum_x;
+    double phi_min, phi_max;
+    unsigned long long bad;
+};
+template <typename T>
+hipError_t launch_reduce(const T* phi, int64_t n, double* d_partials, ReduceOut* d_out,
+                         hipStream_t s);
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+constexpr int kPartialStride = 7;   // doubles per block partial: s1 c1 s2 c2 min max bad
+
+template <typename T>
+hipError_t launch_init_planar(T* phi, int nx, int ny, int nz, double dx, double lambda,
+                              const int hkl[3], double offset, hipStream_t s);
+template <typename T>
+hipError_t launch_init_spheres(T* phi, int nx, int ny, int nz, double dx, double lambda, int n,
+                               const double* d_spheres, hipStream_t s);
+
+}  // namespace spfm

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP kernels against the CPU oracle, element by element.
+
+FP64 path: max |dphi| <= 1e-12 (fields are O(1)).  FP32 path: max |dphi| <= 1e-5
+against the FP64 oracle started from the same FP32-rounded field.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import as_f32_input, noisy_field, slab111, sphere12, stable_dt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_05180_amd import spfm
+    spfm.load()
+    return spfm
+
+
+def run_pair(S, steps, *, dtype, kernel, stencil, coupling, phi0, lam, mu=0.01,
+             u=(1.0, 2.0, 0.0), dt=None):
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    shape = phi0.shape
+    p = oracle.params(shape, lam=lam, mu=mu, stencil=stencil, coupling=coupling, u=u, eps=eps)
+    p.dt = dt if dt else stable_dt(p)
+    if dtype == "f32":
+        phi0 = as_f32_input(phi0)
+    print(f"case shape={shape} steps={steps} {dtype} {kernel} S={stencil} {coupling} "
+          f"lam={lam} dt={p.dt:.4f}", flush=True)
+    ref = oracle.step(p, phi0, steps)
+    with S.Spfm(shape, lam=lam, mu=mu, stencil=stencil, dtype=dtype, coupling=coupling, u=u,
+                eps=eps, C_Gamma=p.C_Gamma, kernel=kernel, dt=p.dt) as s:
+        s.set_field(phi0)
+        s.step(steps)
+        got = s.get_field().astype(np.float64)
+    return float(np.abs(got - ref).max()), got, ref
+
+
+@pytest.mark.parametrize("kernel", ["plain", "tiled"])
+@pytest.mark.parametrize("stencil", [6, 18, 26])
+@pytest.mark.parametrize("coupling", ["local", "global", "cf"])
+def test_fp64_matches_oracle(S, kernel, stencil, coupling):
+    err, _, _ = run_pair(S, 40, dtype="f64", kernel=kernel, stencil=stencil, coupling=coupling,
+                         phi0=slab111(), lam=1.5)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("kernel", ["plain", "tiled"])
+@pytest.mark.parametrize("stencil", [6, 18, 26])
+@pytest.mark.parametrize("coupling", ["local", "global", "cf"])
+def test_fp32_matches_oracle(S, kernel, stencil, coupling):
+    err, _, _ = run_pair(S, 200, dtype="f32", kernel=kernel, stencil=stencil, coupling=coupling,
+                         phi0=slab111(), lam=1.5)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,steps,tol", [("f64", 40, 1e-12), ("f32", 300, 1e-5)])
+def test_grain_matches_oracle(S, dtype, steps, tol):
+    for kernel in ("plain", "tiled"):
+        err, _, _ = run_pair(S, steps, dtype=dtype, kernel=kernel, stencil=26, coupling="local",
+                             phi0=sphere12(), lam=2.0, mu=0.0)
+        assert err <= tol, (kernel, err)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("coupling", ["local", "global", "cf"])
+def test_noisy_field_short_window(S, dtype, tol, coupling):
+    phi0 = noisy_field((40, 21, 70), 3.0, 7)
+    for kernel in ("plain", "tiled"):
+        err, _, _ = run_pair(S, 5, dtype=dtype, kernel=kernel, stencil=26, coupling=coupling,
+                             phi0=phi0, lam=3.0, mu=0.03)
+        assert err <= tol, (kernel, err)
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (3, 5, 4), (7, 3, 130), (33, 4, 65), (70, 9, 3)])
+def test_small_and_ragged_grids(S, shape):
+    phi0 = noisy_field(shape, 1.5, 3)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        for kernel in ("plain", "tiled"):
+            err, _, _ = run_pair(S, 5, dtype=dtype, kernel=kernel, stencil=26,
+                                 coupling="local", phi0=phi0, lam=1.5)
+            assert err <= tol, (dtype, kernel, err)
+
+
+def test_planar32_fp64_full_run(S):
+    """32^3 periodic [100] slab, lambda = 4, mu = 0.05, 6 neighbours, 500 steps (FP64)."""
+    from paper_1910_05180_amd import inputs
+    w = inputs.planar32()
+    phi0 = oracle.init_planar(w.shape, w.hkl, w.offset, lam=w.lam)
+    for coupling in ("local", "global"):
+        err, got, ref = run_pair(S, w.steps, dtype="f64", kernel="tiled",
+                                 stencil=w.stencil, coupling=coupling, lam=w.lam, mu=w.mu,
+                                 u=(1, 0, 0), phi0=phi0, dt=w.dt)
+        assert err <= 1e-12
+        # the slab moves at v = -M mu / Gamma up to the forward-Euler error
+        A = oracle.slab_area(w.shape, w.hkl)
+        v = (oracle.phase_volume(got) - oracle.phase_volume(phi0)) / A / (w.steps * w.dt)
+        assert abs(v / (-w.mu) - 1) < 2e-3
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 2e-14), ("f32", 3e-7)])
+def test_one_step_travelling_wave_on_device(S, dtype, tol):
+    """The ideal profile at any orientation moves one step exactly as
+    phi + dt * (-(4 M mu/(lambda Gamma)) phi (1-phi)) at interior points."""
+    shape = (12, 14, 66)
+    lam, mu = 2.3, 0.07
+    n = np.array([0.36, 0.48, 0.8])
+    n /= np.linalg.norm(n)
+    z, y, x = np.meshgrid(*(np.arange(k) for k in shape), indexing="ij")
+    phi = 0.5 * (1 - np.tanh(2 * (x * n[0] + y * n[1] + z * n[2] - 20.3) / lam))
+    if dtype == "f32":
+        phi = as_f32_input(phi)
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    with S.Spfm(shape, lam=lam, mu=mu, stencil=26, dtype=dtype, coupling="local", eps=eps) as s:
+        s.set_field(phi)
+        s.step(1)
+        got = s.get_field().astype(np.float64)
+        dt = s.info()["dt"]
+    exact = phi + dt * (-(4 * mu / lam) * phi * (1 - phi))
+    inner = (slice(1, -1),) * 3
+    assert np.abs(got - exact)[inner].max() < tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_init_matches_oracle(S, dtype):
+    tol = 1e-14 if dtype == "f64" else 6e-8
+    shape = (24, 30, 40)
+    with S.Spfm(shape, lam=2.5, stencil=26, dtype=dtype) as s:
+        s.init_planar((1, -2, 3), 0.3)
+        got = s.get_field().astype(np.float64)
+        ref = oracle.init_planar(shape, (1, -2, 3), 0.3, lam=2.5)
+        assert np.abs(got - ref).max() < tol
+        c = [(5.0, 7.5, 20.0), (30.0, 22.0, 3.0)]
+        r = [6.0, 4.5]
+        s.init_spheres(c, r)
+        got = s.get_field().astype(np.float64)
+        ref = oracle.init_spheres(shape, c, r, lam=2.5)
+        assert np.abs(got - ref).max() < tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_diagnostics_match_exact_sums(S, dtype):
+    shape = (40, 33, 70)
+    lam = 3.0
+    phi0 = noisy_field(shape, lam, 5)
+    with S.Spfm(shape, lam=lam, stencil=26, dtype=dtype) as s:
+        s.set_field(phi0)
+        d = s.diagnostics()
+        f = s.get_field().astype(np.float64)
+    s1, s2 = oracle.exact_sums(f)
+    assert abs(d["sum_phi"] - s1) <= 1e-15 * abs(s1)
+    assert abs(d["sum_x"] - s2) <= 1e-15 * abs(s2)
+    assert d["phi_min"] == f.min() and d["phi_max"] == f.max()
+    assert d["diverged"] == 0
+    assert d["phase_volume"] == pytest.approx(s1)
+    assert d["interface_area"] == pytest.approx(4 / lam * s2)
+
+
+def test_diagnostics_position_and_velocity(S):
+    from paper_1910_05180_amd import inputs
+    w = inputs.planar32()
+    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=w.stencil, dtype="f64") as s:
+        s.init_planar(w.hkl, w.offset)
+        d0 = s.diagnostics()
+        assert d0["interface_position"] == 0.0 and math.isnan(d0["velocity"])
+        s.step(200)
+        d1 = s.diagnostics()
+        s.step(200)
+        d2 = s.diagnostics()
+    assert abs(d2["velocity"] / -w.mu - 1) < 2e-3
+    assert d2["step"] == 400 and d2["time"] == pytest.approx(40.0)
+
+
+def test_diverged_flag(S):
+    shape = (8, 8, 8)
+    phi = np.full(shape, 0.5)
+    phi[3, 4, 5] = 3.0
+    with S.Spfm(shape, lam=3.0, stencil=6, dtype="f64") as s:
+        s.set_field(phi)
+        with pytest.raises(S.SpfmError) as e:
+            s.diagnostics()
+        assert e.value.status == S.E_DIVERGED
+
+
+def test_steps_are_deterministic(S):
+    shape = (40, 20, 70)
+    phi0 = slab111(3.0)
+    shape = phi0.shape
+    out = []
+    for _ in range(2):
+        with S.Spfm(shape, lam=3.0, mu=0.02, stencil=26, dtype="f32") as s:
+            s.set_field(phi0)
+            s.step(50)   # crosses the graph-replay threshold
+            out.append(s.get_field())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_graph_replay_equals_direct_launches(S):
+    """Long runs replay captured graphs; the result equals single launches."""
+    import torch
+    shape = (33, 20, 64)
+    phi0 = slab111(3.0)
+    shape = phi0.shape
+    st = torch.cuda.Stream()
+    res = []
+    for chunk in (1, 77):
+        with torch.cuda.stream(st):
+            with S.Spfm(shape, lam=3.0, mu=0.02, stencil=26, dtype="f32") as s:
+                s.set_field(phi0)
+                for _ in range(77 // chunk):
+                    s.step(chunk)
+                res.append(s.get_field())
+    assert np.array_equal(res[0], res[1])

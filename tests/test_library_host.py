@@ -1,0 +1,74 @@
+"""CPU checks of the HIP library's boundary: it loads, exports every symbol the
+header declares, validates arguments before touching the GPU, and its host
+math (calibration, stability bound) agrees with the oracle."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1910_05180_amd import spfm
+    if not os.path.exists(spfm.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    spfm.load()
+    return spfm
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "spfm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spfm_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(S):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = S.load()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(stencil=7), -1), (dict(lam=-1.0), -1), (dict(Gamma=0.0), -1), (dict(M=0.0), -1),
+    (dict(dx=0.0), -1), (dict(dtype=5), -1), (dict(coupling=9), -1),
+    (dict(coupling="global", u=(0, 0, 0)), -1), (dict(lam=0.25), -1),
+    (dict(dt=1.0), -4), (dict(dt=1.0, lam=1.0, stencil=6), -4),
+    (dict(mu=float("nan")), -1), (dict(kernel=7), -1),
+])
+def test_create_rejects_bad_arguments_before_any_hip_call(S, kw, status):
+    st, msg = S.try_create((16, 16, 16), **kw)
+    assert st == status and msg
+
+
+def test_create_rejects_small_grid(S):
+    st, msg = S.try_create((2, 16, 16))
+    assert st == -1 and "3" in msg
+
+
+def test_status_strings(S):
+    L = S.load()
+    for st in range(-6, 1):
+        assert L.spfm_status_string(st)
+
+
+@pytest.mark.parametrize("lt", [0.35, 0.5, 1.0, 2.5, 4.0, 8.0, 30.0])
+def test_calibration_matches_oracle(S, orc, lt):
+    assert abs(S.calibrate_cgamma(lt) - orc.calibrate_cgamma(lt)) < 2e-13
+    assert S.calibrate_cgamma(lt, "cf") == pytest.approx(2.0 / 3.0)
+
+
+@pytest.mark.parametrize("stencil,coupling,lam,mu,u", [
+    (6, "global", 4.0, 0.05, (1, 0, 0)), (26, "local", 3.0, 0.1, (1, 0, 0)),
+    (18, "local", 5.0, -0.1, (1, 0, 0)), (26, "global", 2.0, 0.0, (1, 2, 0)),
+    (26, "cf", 4.0, 0.02, (1, 0, 0)), (6, "local", 1.0, 0.0, (1, 0, 0)),
+])
+def test_stable_dt_matches_oracle(S, orc, stencil, coupling, lam, mu, u):
+    p = orc.params((4, 4, 4), lam=lam, mu=mu, stencil=stencil, coupling=coupling, u=u)
+    ref = orc.stable_dt(p)
+    got = S.stable_dt(stencil, coupling, u, None, lam, 1.0, 1.0, mu, 1.0, p.C_Gamma)
+    assert abs(got / ref - 1) < 1e-5
