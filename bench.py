@@ -34,7 +34,20 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--only", default="", help="run only this leg: f32 | f64 (profiling)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="first run a plain copy of 2^26 floats (256 MiB read + 256 MiB written), "
+                         "the reference that scales hardware byte counters")
     return ap.parse_args()
+
+
+def copy_reference(torch):
+    n = 1 << 26
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
 def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup):
@@ -94,6 +107,8 @@ def main():
     npts = w.shape[0] * w.shape[1] * w.shape[2]
 
     out = {"metric": "GLUPS + % HBM peak, 256^3 FP32 26-nbr SPFM step vs FP64 plain"}
+    if args.copy_ref:
+        out["copy_reference"] = copy_reference(torch)
     f32 = f64 = None
     if args.only in ("", "f32"):
         wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",

@@ -55,7 +55,7 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     if (g->nx < 3 || g->ny < 3 || g->nz < 3)
         return fail(SPFM_E_INVAL, "grid edges must be >= 3 (got %d x %d x %d)", g->nx, g->ny, g->nz);
     if ((int64_t)g->nx * g->ny >= (int64_t)1 << 31 || (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40) ||
-        g->nz > 65535 || g->ny > 65535 * kTileY)
+        g->nz > 65535 || g->ny > 4 * 65535)
         return fail(SPFM_E_INVAL, "grid too large (nx*ny < 2^31, ny <= 262140, nz <= 65535)");
     if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SPFM_E_INVAL, "dx must be > 0");
     if (!(lambda > 0.0) || !(Gamma > 0.0) || !(M > 0.0) || !std::isfinite(lambda) ||
@@ -543,6 +543,12 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
                 for (int x0 = 0; x0 < p.nx; x0 += kTileX) items.push_back(TileItem{i, x0, y0, z0});
     }
     if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
+    {   // dispatch order: each XCD gets a contiguous run of tiles (see xcd_remap)
+        std::vector<TileItem> order(items.size());
+        const int nt = (int)items.size();
+        for (int s = 0; s < nt; ++s) order[s] = items[xcd_remap(s, nt)];
+        items.swap(order);
+    }
     b->total = off;
     b->nitems = (int)items.size();
     const size_t bytes = (size_t)off * sizeof(float);

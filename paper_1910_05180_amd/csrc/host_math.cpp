@@ -147,6 +147,7 @@ StepCoef<T> make_coef(const Params& p) {
     const double t = 8.0 * p.dx * p.tau / (p.lambda * M_LN2);
     k.tau2 = (T)(t * t);
     const double un = sqrt(p.u[0] * p.u[0] + p.u[1] * p.u[1] + p.u[2] * p.u[2]);
+    double msum[3] = {0.0, 0.0, 0.0}, mmax = 0.0;
     for (int d = 0; d < 13; ++d) {
         double m = 0.0;
         if (p.coupling == kGlobal && un > 0.0) {
@@ -155,7 +156,18 @@ StepCoef<T> make_coef(const Params& p) {
             m = 4.0 * h * h;                                      // 2 cosh(beta) - 2
         }
         k.mg[d] = (T)m;
+        msum[shell_of(d) - 1] += m;
+        if (shell_of(d) <= nsh) mmax = fmax(mmax, m);
     }
+    for (int j = 0; j < 3; ++j) k.msum[j] = (T)msum[j];
+    if (p.coupling == kLocal) {
+        // beta_k = 4 r_k.n / lambda <= 4 dx sqrt(j) / lambda for every unit n
+        const double h = sinh(2.0 * p.dx * sqrt((double)nsh) / p.lambda);
+        mmax = 4.0 * h * h;
+    }
+    // y_k / (1 + y_k) = y_k (1 - y_k + ...): equal to y_k within an ulp once y_k < 2^-p
+    const double ulp = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
+    k.xtail = (T)(mmax > 0.0 ? ulp / mmax : 0.0);
     return k;
 }
 

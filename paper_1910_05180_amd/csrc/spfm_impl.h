@@ -39,6 +39,9 @@ struct StepCoef {
     T tau2;    // LOCAL: |grad log2((1-phi)/phi)|^2 (central differences, per 2 dx)
                // below tau2 -> normal (1,0,0)
     T mg[13];  // GLOBAL: m_k per direction, shells 1|2|3 as in point_update
+    T msum[3]; // GLOBAL: sum of m_k per shell
+    T xtail;   // below this phi(1-phi) every y_k = m_k x is under one ulp of 1,
+               // so y_k / (1 + y_k) equals y_k to the working precision
 };
 
 // psi' = log2((1-phi)/phi) with both arguments floored at eps; the interface
@@ -71,26 +74,57 @@ struct Frac {
     __device__ __forceinline__ T value() const { return num * fast_rcp(den); }
 };
 
-// New value of phi at one point.  at(dx,dy,dz) returns phi at the offset
-// (dx,dy,dz in {-1,0,1}); grad(gx,gy,gz) sets the central differences of psi'
-// across the point (LOCAL only; called only where phi(1-phi) != 0).
-template <typename T, int S, int C, typename At, typename Grad>
-__device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k) {
-    const T p = at(0, 0, 0);
-    // Second differences summed per shell, formed from differences to the
-    // centre value (exact for nearby values, which keeps FP32 bulk regions clean).
-    T s1 = ((at(1, 0, 0) - p) + (at(-1, 0, 0) - p)) + ((at(0, 1, 0) - p) + (at(0, -1, 0) - p)) +
-           ((at(0, 0, 1) - p) + (at(0, 0, -1) - p));
-    T s2 = T(0), s3 = T(0);
+// sum_j K_j sum_{k in shell j} y_k / (1 + y_k) with y_k = m_k x, one fraction per shell.
+template <typename T, int S>
+__device__ __forceinline__ T shell_sums(T m1x, T m1y, T m1z, const T (&m2)[6], const T (&m3)[4], T x,
+                                        const StepCoef<T>& k) {
+    Frac<T> f1;
+    f1.add(m1x * x); f1.add(m1y * x); f1.add(m1z * x);
+    T q = k.K[0] * f1.value();
     if (S >= 18) {
-        s2 = (((at(1, 1, 0) - p) + (at(-1, -1, 0) - p)) + ((at(1, -1, 0) - p) + (at(-1, 1, 0) - p))) +
-             (((at(0, 1, 1) - p) + (at(0, -1, -1) - p)) + ((at(0, 1, -1) - p) + (at(0, -1, 1) - p))) +
-             (((at(1, 0, 1) - p) + (at(-1, 0, -1) - p)) + ((at(1, 0, -1) - p) + (at(-1, 0, 1) - p)));
+        Frac<T> f2;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) f2.add(m2[i] * x);
+        q = fma(k.K[1], f2.value(), q);
     }
     if (S >= 26) {
-        s3 = (((at(1, 1, 1) - p) + (at(-1, -1, -1) - p)) + ((at(1, 1, -1) - p) + (at(-1, -1, 1) - p))) +
-             (((at(1, -1, 1) - p) + (at(-1, 1, -1) - p)) + ((at(-1, 1, 1) - p) + (at(1, -1, -1) - p)));
+        Frac<T> f3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f3.add(m3[i] * x);
+        q = fma(k.K[2], f3.value(), q);
     }
+    return q;
+}
+
+// Shell sums of second differences s_j = sum_{k in shell j} (phi(p+r_k) + phi(p-r_k) - 2 phi(p))
+// from a neighbourhood accessor at(dx,dy,dz), dx,dy,dz in {-1,0,1}.  Shell 1 (the
+// largest weight) is formed from differences to the centre value, exact for
+// nearby values; shells 2 and 3 from sums of opposite neighbours.  Bulk regions
+// (all values equal) give exactly 0.
+template <typename T, int S, typename At>
+__device__ __forceinline__ void shell_laplacian(At at, T p, T& s1, T& s2, T& s3) {
+    s1 = ((at(1, 0, 0) - p) + (at(-1, 0, 0) - p)) + ((at(0, 1, 0) - p) + (at(0, -1, 0) - p)) +
+         ((at(0, 0, 1) - p) + (at(0, 0, -1) - p));
+    s2 = T(0);
+    s3 = T(0);
+    if (S >= 18) {
+        s2 = (((at(1, 1, 0) + at(-1, -1, 0)) + (at(1, -1, 0) + at(-1, 1, 0))) +
+              ((at(0, 1, 1) + at(0, -1, -1)) + (at(0, 1, -1) + at(0, -1, 1)))) +
+             ((at(1, 0, 1) + at(-1, 0, -1)) + (at(1, 0, -1) + at(-1, 0, 1)));
+        s2 = fma(T(-12), p, s2);
+    }
+    if (S >= 26) {
+        s3 = ((at(1, 1, 1) + at(-1, -1, -1)) + (at(1, 1, -1) + at(-1, -1, 1))) +
+             ((at(1, -1, 1) + at(-1, 1, -1)) + (at(-1, 1, 1) + at(1, -1, -1)));
+        s3 = fma(T(-8), p, s3);
+    }
+}
+
+// New value of phi at one point from its value p, the shell sums s1..s3 of
+// second differences and grad(gx,gy,gz), which sets the central differences of
+// psi' across the point (LOCAL only; called only where phi(1-phi) != 0).
+template <typename T, int S, int C, typename Grad>
+__device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const StepCoef<T>& k) {
     const T x = p * (T(1) - p);
     const T u = T(1) - T(2) * p;
     T upd = k.K[0] * s1;
@@ -99,10 +133,7 @@ __device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k
     if (C == kCF) {
         upd = fma(-k.kcf, x * u, upd);
     } else if (x != T(0)) {
-        // m_k = 2 cosh(beta_k) - 2 for the 13 directions.
-        T m1x, m1y, m1z;                        // shell 1: x, y, z
-        T m2[6];                                // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
-        T m3[4];                                // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
+        T q;
         if (C == kLocal) {
             T gx, gy, gz;
             grad(gx, gy, gz);
@@ -112,69 +143,83 @@ __device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k
             const T ex = fast_exp2(sc * gx), ey = fast_exp2(sc * gy), ez = fast_exp2(sc * gz);
             const T r = fast_rcp(ex * ey * ez);
             const T rx = r * ey * ez, ry = r * ex * ez, rz = r * ex * ey;
-            // c_i = 2cosh - 2 = (E-1)^2/E,  s_i = 2 sinh = E - 1/E
-            const T cx = (ex - T(1)) * (ex - T(1)) * rx, sx = ex - rx;
-            const T cy = (ey - T(1)) * (ey - T(1)) * ry, sy = ey - ry;
-            const T cz = (ez - T(1)) * (ez - T(1)) * rz, sz = ez - rz;
-            m1x = cx; m1y = cy; m1z = cz;
-            // 2cosh(a+-b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2
-            {
-                const T pc = cx * cy, ps = sx * sy, base = cx + cy;
-                m2[0] = fma(T(0.5), pc + ps, base);
-                m2[1] = fma(T(0.5), pc - ps, base);
-            }
-            {
-                const T pc = cy * cz, ps = sy * sz, base = cy + cz;
-                m2[2] = fma(T(0.5), pc + ps, base);
-                m2[3] = fma(T(0.5), pc - ps, base);
-            }
-            {
-                const T pc = cx * cz, ps = sx * sz, base = cx + cz;
-                m2[4] = fma(T(0.5), pc + ps, base);
-                m2[5] = fma(T(0.5), pc - ps, base);
-            }
-            if (S >= 26) {
-                // 2sinh(a+-b) = (s_a (c_b+2) +- (c_a+2) s_b)/2, then
-                // 2cosh(w+-z) - 2 = m_w + c_z + (m_w c_z +- s_w s_z)/2
-                const T hxy_p = T(0.5) * (sx * (cy + T(2)) + (cx + T(2)) * sy);
-                const T hxy_m = T(0.5) * (sx * (cy + T(2)) - (cx + T(2)) * sy);
+            // c_i = 2cosh(kappa n_i) - 2 = (E-1)^2/E
+            const T cx = (ex - T(1)) * (ex - T(1)) * rx;
+            const T cy = (ey - T(1)) * (ey - T(1)) * ry;
+            const T cz = (ez - T(1)) * (ez - T(1)) * rz;
+            if (fabs(x) < k.xtail) {
+                // y/(1+y) -> y: the per-shell sums of m_k in closed form,
+                // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2
+                const T c1 = cx + cy + cz;
+                const T c2 = fma(cx, cy, fma(cy, cz, cx * cz));
+                q = k.K[0] * c1;
+                if (S >= 18) q = fma(k.K[1], fma(T(4), c1, c2), q);
+                if (S >= 26) q = fma(k.K[2], fma(T(4), c1, fma(T(2), c2, cx * cy * cz)), q);
+                q *= x;
+            } else {
+                const T sx = ex - rx, sy = ey - ry, sz = ez - rz;   // 2 sinh
+                T m2[6];   // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
+                T m3[4];   // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
+                // 2cosh(a+-b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2
                 {
-                    const T pc = m2[0] * cz, ps = hxy_p * sz, base = m2[0] + cz;
-                    m3[0] = fma(T(0.5), pc + ps, base);
-                    m3[1] = fma(T(0.5), pc - ps, base);
+                    const T pc = cx * cy, ps = sx * sy, base = cx + cy;
+                    m2[0] = fma(T(0.5), pc + ps, base);
+                    m2[1] = fma(T(0.5), pc - ps, base);
                 }
                 {
-                    const T pc = m2[1] * cz, ps = hxy_m * sz, base = m2[1] + cz;
-                    m3[2] = fma(T(0.5), pc + ps, base);
-                    m3[3] = fma(T(0.5), pc - ps, base);
+                    const T pc = cy * cz, ps = sy * sz, base = cy + cz;
+                    m2[2] = fma(T(0.5), pc + ps, base);
+                    m2[3] = fma(T(0.5), pc - ps, base);
                 }
+                {
+                    const T pc = cx * cz, ps = sx * sz, base = cx + cz;
+                    m2[4] = fma(T(0.5), pc + ps, base);
+                    m2[5] = fma(T(0.5), pc - ps, base);
+                }
+                if (S >= 26) {
+                    // 2sinh(a+-b) = (s_a (c_b+2) +- (c_a+2) s_b)/2, then
+                    // 2cosh(w+-z) - 2 = m_w + c_z + (m_w c_z +- s_w s_z)/2
+                    const T hxy_p = T(0.5) * (sx * (cy + T(2)) + (cx + T(2)) * sy);
+                    const T hxy_m = T(0.5) * (sx * (cy + T(2)) - (cx + T(2)) * sy);
+                    {
+                        const T pc = m2[0] * cz, ps = hxy_p * sz, base = m2[0] + cz;
+                        m3[0] = fma(T(0.5), pc + ps, base);
+                        m3[1] = fma(T(0.5), pc - ps, base);
+                    }
+                    {
+                        const T pc = m2[1] * cz, ps = hxy_m * sz, base = m2[1] + cz;
+                        m3[2] = fma(T(0.5), pc + ps, base);
+                        m3[3] = fma(T(0.5), pc - ps, base);
+                    }
+                }
+                q = shell_sums<T, S>(cx, cy, cz, m2, m3, x, k);
             }
         } else {
-            m1x = k.mg[0]; m1y = k.mg[1]; m1z = k.mg[2];
+            if (fabs(x) < k.xtail) {
+                q = x * (k.K[0] * k.msum[0] + k.K[1] * k.msum[1] + k.K[2] * k.msum[2]);
+            } else {
+                T m2[6], m3[4];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) m2[i] = k.mg[3 + i];
+                for (int i = 0; i < 6; ++i) m2[i] = k.mg[3 + i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) m3[i] = k.mg[9 + i];
-        }
-        Frac<T> f1;
-        f1.add(m1x * x); f1.add(m1y * x); f1.add(m1z * x);
-        T q = k.K[0] * f1.value();
-        if (S >= 18) {
-            Frac<T> f2;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) f2.add(m2[i] * x);
-            q = fma(k.K[1], f2.value(), q);
-        }
-        if (S >= 26) {
-            Frac<T> f3;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) f3.add(m3[i] * x);
-            q = fma(k.K[2], f3.value(), q);
+                for (int i = 0; i < 4; ++i) m3[i] = k.mg[9 + i];
+                q = shell_sums<T, S>(k.mg[0], k.mg[1], k.mg[2], m2, m3, x, k);
+            }
         }
         upd = fma(-u, q, upd);
     }
     upd = fma(-k.b, x, upd);
     return p + upd;
+}
+
+// New value of phi at one point.  at(dx,dy,dz) returns phi at the offset
+// (dx,dy,dz in {-1,0,1}); grad as in point_core.
+template <typename T, int S, int C, typename At, typename Grad>
+__device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k) {
+    const T p = at(0, 0, 0);
+    T s1, s2, s3;
+    shell_laplacian<T, S>(at, p, s1, s2, s3);
+    return point_core<T, S, C>(p, s1, s2, s3, grad, k);
 }
 
 // ---- launchers (step_kernels.hip, reduce.hip, init.hip) ----
@@ -194,8 +239,18 @@ hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCo
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
                                int stencil, int coupling, hipStream_t s);
 constexpr int kTileX = 64;
-constexpr int kTileY = 4;
+constexpr int kTileY = 8;
 constexpr int kTileZ = 32;
+constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
+
+// Dispatch slot b -> logical tile: XCD (b mod 8) receives one contiguous run of
+// logical tiles (x fastest, then y, then z), so tiles that share halo rows and
+// columns are processed by the same XCD and meet in its L2.
+__host__ __device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    const int k = b % kNumXcd, i = b / kNumXcd;
+    return k < r ? k * (q + 1) + i : r * (q + 1) + (k - r) * q + i;
+}
 
 struct ReduceOut {   // device result of the diagnostics reduction
     double sum_phi, sum_x;

@@ -2,15 +2,12 @@
 //
 //  k_step_plain  one thread per point; the 27-point neighbourhood is read
 //                straight from global memory with periodic index wrap.
-//  k_step_tiled  a 256-thread block owns a 64 x 4 column of the grid and
-//                marches it along z over kTileZ planes.  Each plane of the
-//                tile plus a one-cell halo is staged in LDS (a ring of four
-//                planes: z-1, z, z+1 being read while z+2 is written), loaded
-//                with coalesced 64-wide rows one iteration ahead of its use so
-//                that the HBM latency hides behind the arithmetic.  For TI_n
-//                the log-ratio psi' of every staged cell is computed once and
-//                kept in a second LDS ring, so each point's normal costs three
-//                subtractions instead of six logarithms.
+//  k_step_tiled  a 512-thread block owns a 64 x 8 column of the grid and
+//                marches it along z over kTileZ planes (see tile_sweep): every
+//                plane is read from HBM once with coalesced rows, one plane ahead
+//                of its use, staged with its halo in LDS, and reduced by each
+//                thread to a few per-plane partial sums kept in registers.  For
+//                TI_n the log-ratio psi' of every staged cell is computed once.
 //  k_step_batched the tiled sweep over a flat list of (grid, tile) items that
 //                covers many independent grids in one launch.
 #include "spfm_impl.h"
@@ -45,8 +42,26 @@ __global__ __launch_bounds__(256) void k_step_plain(const T* __restrict__ in, T*
     out[((size_t)z * ny + y) * nx + x] = point_update<T, S, C>(at, grad, k);
 }
 
+// Per-column values a thread keeps for one plane q of its z-march.
+template <typename T>
+struct PlaneRegs {
+    T c;        // phi at the column
+    T fc;       // sum over the 4 in-plane face neighbours of (phi - c)
+    T dc;       // sum over the 4 in-plane diagonal neighbours of (phi - c)
+    T gx, gy;   // LOCAL: in-plane central differences of psi' at the column
+    T pc;       // LOCAL: psi' at the column
+};
+
 // One block sweeps the tile [x0, x0+kTileX) x [y0, y0+kTileY) x [z0, z0+kTileZ)
-// (clipped to the grid).  sphi / spsi: LDS rings of four halo planes.
+// (clipped to the grid).  Each plane of the tile plus a one-cell halo is loaded
+// once (coalesced rows, one plane ahead of its use) into a two-slot LDS ring,
+// together with psi' of every cell for TI_n.  Every thread reads its 3x3
+// in-plane neighbourhood of the newest plane once and keeps per-plane partial
+// sums for planes z-1, z, z+1 in registers; with them the 26-neighbour shell
+// sums of point z are
+//   s1 = fc(z) + e,  s2 = dc(z) + fc(z-1) + fc(z+1) + 4e,  s3 = dc(z-1) + dc(z+1) + 4e,
+//   e = (c(z-1) - c(z)) + (c(z+1) - c(z)),
+// all built from differences of nearby values.
 template <typename T, int S, int C>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0,
@@ -73,9 +88,14 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     }
     const int zend = min(z0 + kTileZ, nz);
 
-    auto stage = [&](int j, const T (&v)[NL]) {   // store plane j (relative) into the rings
-        T* dphi = sphi + (j & 3) * HP;
-        T* dpsi = spsi + (j & 3) * HP;
+    auto fetch = [&](int zz, T (&v)[NL]) {
+        const T* src = in + (size_t)wrap_once(zz, nz) * plane;
+#pragma unroll
+        for (int c = 0; c < NL; ++c) v[c] = lval[c] ? src[loff[c]] : T(0);
+    };
+    auto stage = [&](int slot, const T (&v)[NL]) {
+        T* dphi = sphi + slot * HP;
+        T* dpsi = spsi + slot * HP;
 #pragma unroll
         for (int c = 0; c < NL; ++c) {
             if (lval[c]) {
@@ -84,48 +104,73 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             }
         }
     };
-    auto fetch = [&](int zz, T (&v)[NL]) {
-        const T* src = in + (size_t)wrap_once(zz, nz) * plane;
-#pragma unroll
-        for (int c = 0; c < NL; ++c) v[c] = lval[c] ? src[loff[c]] : T(0);
-    };
-
-    // Prologue: planes z0-1, z0, z0+1 -> relative slots 0, 1, 2.
-    {
-        T v[NL];
-        fetch(z0 - 1, v); stage(0, v);
-        fetch(z0, v); stage(1, v);
-        fetch(z0 + 1, v); stage(2, v);
-    }
-    const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const int cc = (ty + 1) * HX + (tx + 1);
+    auto load = [&](int slot, PlaneRegs<T>& R) {
+        const T* P = sphi + slot * HP;
+        const T c = P[cc];
+        R.c = c;
+        R.fc = ((P[cc + 1] - c) + (P[cc - 1] - c)) + ((P[cc + HX] - c) + (P[cc - HX] - c));
+        if (S >= 18)
+            R.dc = ((P[cc + HX + 1] - c) + (P[cc - HX - 1] - c)) +
+                   ((P[cc + HX - 1] - c) + (P[cc - HX + 1] - c));
+        if (C == kLocal) {
+            const T* Q = spsi + slot * HP;
+            R.gx = Q[cc + 1] - Q[cc - 1];
+            R.gy = Q[cc + HX] - Q[cc - HX];
+            R.pc = Q[cc];
+        }
+    };
+    const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     T* dst = out + (size_t)(y0 + ty) * nx + (x0 + tx);
 
-    for (int z = z0; z < zend; ++z) {
-        const int j = z - z0 + 1;   // relative index of the centre plane
-        __syncthreads();
+    // Output plane z with planes z-1, z, z+1 in Rm, R0, Rp; Rp is filled here.
+    // Relative plane index r = z - z0 + 1 (z0 - 1 is r = 0); plane r sits in slot r & 1.
+    auto step = [&](int z, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, PlaneRegs<T>& Rp) {
+        const int r = z - z0 + 1;
+        __syncthreads();   // plane r+1 staged; every read of slot (r+2) & 1 done
         const bool more = z + 1 < zend;
         T pre[NL];
         if (more) fetch(z + 2, pre);
+        load((r + 1) & 1, Rp);
         if (active) {
-            const T* P0 = sphi + ((j - 1) & 3) * HP;
-            const T* P1 = sphi + (j & 3) * HP;
-            const T* P2 = sphi + ((j + 1) & 3) * HP;
-            auto at = [&](int dx, int dy, int dz) -> T {
-                const T* P = dz < 0 ? P0 : (dz > 0 ? P2 : P1);
-                return P[cc + dy * HX + dx];
-            };
+            const T p = R0.c;
+            const T e = (Rm.c - p) + (Rp.c - p);
+            const T s1 = R0.fc + e;
+            T s2 = T(0), s3 = T(0);
+            if (S >= 18) s2 = fma(T(4), e, R0.dc + (Rm.fc + Rp.fc));
+            if (S >= 26) s3 = fma(T(4), e, Rm.dc + Rp.dc);
             auto grad = [&](T& gx, T& gy, T& gz) {
-                const T* Q0 = spsi + ((j - 1) & 3) * HP;
-                const T* Q1 = spsi + (j & 3) * HP;
-                const T* Q2 = spsi + ((j + 1) & 3) * HP;
-                gx = Q1[cc + 1] - Q1[cc - 1];
-                gy = Q1[cc + HX] - Q1[cc - HX];
-                gz = Q2[cc] - Q0[cc];
+                gx = R0.gx;
+                gy = R0.gy;
+                gz = Rp.pc - Rm.pc;
             };
-            dst[(size_t)z * plane] = point_update<T, S, C>(at, grad, k);
+            dst[(size_t)z * plane] = point_core<T, S, C>(p, s1, s2, s3, grad, k);
         }
-        if (more) stage(j + 2, pre);
+        if (more) stage((r + 2) & 1, pre);
+    };
+
+    PlaneRegs<T> A{}, B{}, D{};
+    {
+        T v[NL];
+        fetch(z0 - 1, v);
+        stage(0, v);
+        fetch(z0, v);
+        stage(1, v);
+        __syncthreads();
+        load(0, A);
+        load(1, B);
+        fetch(z0 + 1, v);
+        __syncthreads();
+        stage(0, v);
+    }
+    // Unrolled by three so that the plane registers rotate without moves.
+    for (int z = z0; z < zend;) {
+        step(z, A, B, D);
+        if (++z >= zend) break;
+        step(z, B, D, A);
+        if (++z >= zend) break;
+        step(z, D, A, B);
+        ++z;
     }
 }
 
@@ -136,11 +181,13 @@ struct Smem {
 
 template <typename T, int S, int C>
 __global__ __launch_bounds__(kTileX* kTileY) void k_step_tiled(const T* __restrict__ in,
-                                                               T* __restrict__ out, StepCoef<T> k) {
-    __shared__ T sphi[4 * Smem<T>::HP];
-    __shared__ T spsi[C == kLocal ? 4 * Smem<T>::HP : 1];
-    tile_sweep<T, S, C>(in, out, k, blockIdx.x * kTileX, blockIdx.y * kTileY, blockIdx.z * kTileZ,
-                        sphi, spsi);
+                                                               T* __restrict__ out, StepCoef<T> k,
+                                                               int ntx, int nty, int ntiles) {
+    __shared__ T sphi[2 * Smem<T>::HP];
+    __shared__ T spsi[C == kLocal ? 2 * Smem<T>::HP : 1];
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    tile_sweep<T, S, C>(in, out, k, tx * kTileX, ty * kTileY, tz * kTileZ, sphi, spsi);
 }
 
 template <int S, int C>
@@ -148,8 +195,8 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_step_batched(
     const float* __restrict__ buf_in, float* __restrict__ buf_out,
     const StepCoef<float>* __restrict__ coef, const int64_t* __restrict__ offset,
     const TileItem* __restrict__ items) {
-    __shared__ float sphi[4 * Smem<float>::HP];
-    __shared__ float spsi[C == kLocal ? 4 * Smem<float>::HP : 1];
+    __shared__ float sphi[2 * Smem<float>::HP];
+    __shared__ float spsi[C == kLocal ? 2 * Smem<float>::HP : 1];
     const TileItem it = items[blockIdx.x];
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
@@ -182,9 +229,12 @@ struct PlainLaunch {
 template <typename T, int S, int C>
 struct TiledLaunch {
     static hipError_t run(const T* in, T* out, const StepCoef<T>& k, hipStream_t s) {
-        dim3 grid((k.nx + kTileX - 1) / kTileX, (k.ny + kTileY - 1) / kTileY,
-                  (k.nz + kTileZ - 1) / kTileZ);
-        hipLaunchKernelGGL((k_step_tiled<T, S, C>), grid, dim3(kTileX * kTileY), 0, s, in, out, k);
+        const int ntx = (k.nx + kTileX - 1) / kTileX, nty = (k.ny + kTileY - 1) / kTileY;
+        const int ntz = (k.nz + kTileZ - 1) / kTileZ;
+        const int64_t n = (int64_t)ntx * nty * ntz;
+        if (n > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)n), dim3(kTileX * kTileY), 0, s,
+                           in, out, k, ntx, nty, (int)n);
         return hipGetLastError();
     }
 };
