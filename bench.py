@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--only", default="", help="run only this leg: f32 | f64 (profiling)")
+    ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
+                    help="coupling of the timed legs (the headline is local, TI_n)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain copy of 2^26 floats (256 MiB read + 256 MiB written), "
                          "the reference that scales hardware byte counters")
@@ -50,13 +52,13 @@ def copy_reference(torch):
     return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
-def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup):
+def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local"):
     """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
     Returns (wall seconds, event milliseconds) of the timed region."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = spfm.Spfm(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx,
-                      stencil=w.stencil, dtype=dtype, coupling="local", kernel=kernel, dt=w.dt)
+                      stencil=w.stencil, dtype=dtype, coupling=coupling, kernel=kernel, dt=w.dt)
         s.init_spheres(w.centers, w.radii)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -111,12 +113,13 @@ def main():
         out["copy_reference"] = copy_reference(torch)
     f32 = f64 = None
     if args.only in ("", "f32"):
-        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
-                                   steps=args.steps, warmup=args.warmup)
+        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="auto",
+                                   steps=args.steps, warmup=args.warmup, coupling=args.coupling)
         f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
     if args.only in ("", "f64"):
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",
-                                      steps=args.fp64_steps, warmup=min(args.warmup, 5))
+                                      steps=args.fp64_steps, warmup=min(args.warmup, 5),
+                                      coupling=args.coupling)
         f64 = {"wall": wall64, "ev_ms": ev64, "diag": d64}
 
     if f32 is not None:

@@ -59,8 +59,11 @@ typedef enum { SPFM_F32 = 0, SPFM_F64 = 1 } spfm_dtype;
  * CF = continuum-field potential (no translational invariance). */
 typedef enum { SPFM_LOCAL = 0, SPFM_GLOBAL = 1, SPFM_CF = 2 } spfm_coupling;
 
-/* Kernel choice: AUTO = tiled; PLAIN = one thread per point reading its 27
- * neighbours from global memory; TILED = LDS-staged tiles marching along z. */
+/* Kernel choice: PLAIN = one thread per point reading its 27 neighbours from
+ * global memory; TILED = LDS-staged tiles marching along z; AUTO = TILED with
+ * the z-chunk per block chosen by timing candidates on the current field at
+ * the first spfm_step (that call synchronises the stream once).  Results do
+ * not depend on the z-chunk. */
 typedef enum { SPFM_KERNEL_AUTO = 0, SPFM_KERNEL_PLAIN = 1, SPFM_KERNEL_TILED = 2 } spfm_kernel;
 
 typedef struct {
@@ -110,6 +113,8 @@ typedef struct {
     double gamma[3];
     double dt_max;             /* explicit stability bound */
     int32_t stencil, coupling, dtype, kernel;
+    int32_t zchunk;            /* planes per block of the tiled kernel (chosen by timing
+                                  at the first spfm_step when kernel is AUTO) */
 } spfm_info;
 
 typedef struct spfm_ctx spfm_ctx;

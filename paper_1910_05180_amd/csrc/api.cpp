@@ -229,6 +229,10 @@ struct spfm_ctx {
     int64_t points() const { return (int64_t)r.p.nx * r.p.ny * r.p.nz; }
     size_t bytes() const { return (size_t)points() * elem_size(r.dtype); }
 
+    int zlen = kTileZ;        // planes per block of the tiled kernel
+    bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
+    bool tuned = false;
+
     hipError_t launch_one(int from) {
         const void* in = buf[from];
         void* out = buf[1 - from];
@@ -236,11 +240,11 @@ struct spfm_ctx {
         if (r.dtype == SPFM_F64) {
             return r.kernel == SPFM_KERNEL_PLAIN
                        ? launch_step_plain<double>((const double*)in, (double*)out, kd, S, C, stream)
-                       : launch_step_tiled<double>((const double*)in, (double*)out, kd, S, C, stream);
+                       : launch_step_tiled<double>((const double*)in, (double*)out, kd, S, C, zlen, stream);
         }
         return r.kernel == SPFM_KERNEL_PLAIN
                    ? launch_step_plain<float>((const float*)in, (float*)out, kf, S, C, stream)
-                   : launch_step_tiled<float>((const float*)in, (float*)out, kf, S, C, stream);
+                   : launch_step_tiled<float>((const float*)in, (float*)out, kf, S, C, zlen, stream);
     }
     void refresh_coef() {
         kf = make_coef<float>(r.p);
@@ -275,6 +279,50 @@ struct spfm_batch {
 };
 
 namespace {
+
+// Planes per block: the longest z-chunk (at most kTileZ) that still gives at
+// least 2048 blocks, i.e. two full rounds of 512-thread blocks on 256 CUs.
+int default_zlen(int nx, int ny, int nz) {
+    const int64_t cols = (int64_t)((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+    int z = kTileZ;
+    while (z > 8 && cols * ((nz + z - 1) / z) < 2048) z /= 2;
+    return z;
+}
+
+// SPFM_KERNEL_AUTO: time the tiled kernel for several z-chunk lengths on the
+// current field (reading the current buffer and writing the other one, which
+// the next step overwrites anyway) and keep the fastest.  The result of a step
+// does not depend on the chunk length.
+spfm_status autotune(spfm_ctx* c) {
+    c->tuned = true;
+    if (c->r.kernel != SPFM_KERNEL_TILED) return SPFM_OK;
+    const int cand[4] = {8, 16, 32, 64};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
+    float best = 1e30f;
+    int best_z = c->zlen;
+    spfm_status st = SPFM_OK;
+    for (int z : cand) {
+        if (z > 2 * c->r.p.nz && z != cand[0]) break;
+        c->zlen = z;
+        hipError_t e = c->launch_one(c->cur);   // warm-up
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+            if (i == 1) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = c->launch_one(c->cur);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
+        if (ms < best) { best = ms; best_z = z; }
+    }
+    c->zlen = best_z;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
 
 template <typename Obj>
 spfm_status run_steps(Obj* o, int64_t n) {
@@ -344,6 +392,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     if (!c) return fail(SPFM_E_NOMEM, "host allocation failed");
     c->r = r;
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
+    c->auto_kernel = !opt || opt->kernel == SPFM_KERNEL_AUTO;
+    c->zlen = default_zlen(r.p.nx, r.p.ny, r.p.nz);
     const size_t bytes = c->bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
@@ -461,6 +511,11 @@ spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
 
 spfm_status spfm_step(spfm_ctx* c, int64_t n) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    if (n > 0 && c->auto_kernel && !c->tuned) {
+        spfm_status st = autotune(c);
+        if (st != SPFM_OK) return st;
+        c->graphs.clear();
+    }
     return run_steps(c, n);
 }
 
@@ -481,6 +536,7 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     for (int i = 0; i < 3; ++i) o->gamma[i] = p.gamma[i];
     o->dt_max = c->r.dt_max;
     o->stencil = p.stencil; o->coupling = p.coupling; o->dtype = c->r.dtype; o->kernel = c->r.kernel;
+    o->zchunk = c->zlen;
     return SPFM_OK;
 }
 
@@ -540,7 +596,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         off += (np + 63) / 64 * 64;   // keep every grid 256-byte aligned
         for (int z0 = 0; z0 < p.nz; z0 += kTileZ)
             for (int y0 = 0; y0 < p.ny; y0 += kTileY)
-                for (int x0 = 0; x0 < p.nx; x0 += kTileX) items.push_back(TileItem{i, x0, y0, z0});
+                for (int x0 = 0; x0 < p.nx; x0 += kTileX) items.push_back(TileItem{i, x0, y0, z0, kTileZ});
     }
     if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
     {   // dispatch order: each XCD gets a contiguous run of tiles (see xcd_remap)

@@ -223,9 +223,10 @@ __device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k
 }
 
 // ---- launchers (step_kernels.hip, reduce.hip, init.hip) ----
-struct TileItem {   // one block of the batched step: grid index and tile origin
+struct TileItem {   // one block of the batched step: grid index, tile origin, planes
     int inst;
     int x0, y0, z0;
+    int zlen;
 };
 
 template <typename T>
@@ -233,14 +234,17 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
                              hipStream_t s);
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             hipStream_t s);
+                             int zlen, hipStream_t s);
 // Batched step: instance i reads buf_in + offset[i], writes buf_out + offset[i].
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
                                int stencil, int coupling, hipStream_t s);
+#ifndef SPFM_TILE_Y
+#define SPFM_TILE_Y 8
+#endif
 constexpr int kTileX = 64;
-constexpr int kTileY = 8;
-constexpr int kTileZ = 32;
+constexpr int kTileY = SPFM_TILE_Y;
+constexpr int kTileZ = 32;   // default planes per block (the z-chunk is a launch argument)
 constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
 
 // Dispatch slot b -> logical tile: XCD (b mod 8) receives one contiguous run of

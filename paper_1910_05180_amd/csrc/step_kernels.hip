@@ -3,7 +3,7 @@
 //  k_step_plain  one thread per point; the 27-point neighbourhood is read
 //                straight from global memory with periodic index wrap.
 //  k_step_tiled  a 512-thread block owns a 64 x 8 column of the grid and
-//                marches it along z over kTileZ planes (see tile_sweep): every
+//                marches it along z over zlen planes (see tile_sweep): every
 //                plane is read from HBM once with coalesced rows, one plane ahead
 //                of its use, staged with its halo in LDS, and reduced by each
 //                thread to a few per-plane partial sums kept in registers.  For
@@ -52,19 +52,20 @@ struct PlaneRegs {
     T pc;       // LOCAL: psi' at the column
 };
 
-// One block sweeps the tile [x0, x0+kTileX) x [y0, y0+kTileY) x [z0, z0+kTileZ)
-// (clipped to the grid).  Each plane of the tile plus a one-cell halo is loaded
-// once (coalesced rows, one plane ahead of its use) into a two-slot LDS ring,
-// together with psi' of every cell for TI_n.  Every thread reads its 3x3
-// in-plane neighbourhood of the newest plane once and keeps per-plane partial
-// sums for planes z-1, z, z+1 in registers; with them the 26-neighbour shell
-// sums of point z are
+// One block sweeps the tile [x0, x0+kTileX) x [y0, y0+kTileY) x [z0, z0+zlen)
+// (clipped to the grid).  Each plane of the tile plus a one-cell halo is read
+// from global memory once (coalesced rows) one iteration before it is staged
+// into a four-slot LDS ring, together with psi' of every cell for TI_n.  Every
+// thread reads its 3x3 in-plane neighbourhood of each plane once and keeps
+// per-plane partial sums in registers; with them the 26-neighbour shell sums of
+// point z are
 //   s1 = fc(z) + e,  s2 = dc(z) + fc(z-1) + fc(z+1) + 4e,  s3 = dc(z-1) + dc(z+1) + 4e,
 //   e = (c(z-1) - c(z)) + (c(z+1) - c(z)),
-// all built from differences of nearby values.
+// all built from differences of nearby values.  Two output planes are produced
+// per iteration (one barrier per two planes, two independent points per thread).
 template <typename T, int S, int C>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
-                                           const StepCoef<T>& k, int x0, int y0, int z0,
+                                           const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi) {
     constexpr int HX = kTileX + 2, HY = kTileY + 2, HP = HX * HY;
     constexpr int NT = kTileX * kTileY;
@@ -86,16 +87,19 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         gy %= ny; if (gy < 0) gy += ny;
         loff[c] = lval[c] ? gy * nx + gx : 0;
     }
-    const int zend = min(z0 + kTileZ, nz);
-
-    auto fetch = [&](int zz, T (&v)[NL]) {
-        const T* src = in + (size_t)wrap_once(zz, nz) * plane;
+    const int nout = min(zlen, nz - z0);   // output planes z0 .. z0+nout-1
+    const int last = nout + 1;             // relative index of the last plane needed
+    // Relative plane index r: plane z0 - 1 + r, held in LDS slot r & 3.
+    auto fetch = [&](int r, T (&v)[NL]) {
+        if (r > last) return;               // beyond the sweep: never loaded
+        const T* src = in + (size_t)wrap_once(z0 - 1 + r, nz) * plane;
 #pragma unroll
         for (int c = 0; c < NL; ++c) v[c] = lval[c] ? src[loff[c]] : T(0);
     };
-    auto stage = [&](int slot, const T (&v)[NL]) {
-        T* dphi = sphi + slot * HP;
-        T* dpsi = spsi + slot * HP;
+    auto stage = [&](int r, const T (&v)[NL]) {
+        if (r > last) return;
+        T* dphi = sphi + (r & 3) * HP;
+        T* dpsi = spsi + (r & 3) * HP;
 #pragma unroll
         for (int c = 0; c < NL; ++c) {
             if (lval[c]) {
@@ -105,8 +109,9 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         }
     };
     const int cc = (ty + 1) * HX + (tx + 1);
-    auto load = [&](int slot, PlaneRegs<T>& R) {
-        const T* P = sphi + slot * HP;
+    auto load = [&](int r, PlaneRegs<T>& R) {
+        if (r > last) return;
+        const T* P = sphi + (r & 3) * HP;
         const T c = P[cc];
         R.c = c;
         R.fc = ((P[cc + 1] - c) + (P[cc - 1] - c)) + ((P[cc + HX] - c) + (P[cc - HX] - c));
@@ -114,7 +119,7 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             R.dc = ((P[cc + HX + 1] - c) + (P[cc - HX - 1] - c)) +
                    ((P[cc + HX - 1] - c) + (P[cc - HX + 1] - c));
         if (C == kLocal) {
-            const T* Q = spsi + slot * HP;
+            const T* Q = spsi + (r & 3) * HP;
             R.gx = Q[cc + 1] - Q[cc - 1];
             R.gy = Q[cc + HX] - Q[cc - HX];
             R.pc = Q[cc];
@@ -122,55 +127,58 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     };
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     T* dst = out + (size_t)(y0 + ty) * nx + (x0 + tx);
-
-    // Output plane z with planes z-1, z, z+1 in Rm, R0, Rp; Rp is filled here.
-    // Relative plane index r = z - z0 + 1 (z0 - 1 is r = 0); plane r sits in slot r & 1.
-    auto step = [&](int z, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, PlaneRegs<T>& Rp) {
-        const int r = z - z0 + 1;
-        __syncthreads();   // plane r+1 staged; every read of slot (r+2) & 1 done
-        const bool more = z + 1 < zend;
-        T pre[NL];
-        if (more) fetch(z + 2, pre);
-        load((r + 1) & 1, Rp);
-        if (active) {
-            const T p = R0.c;
-            const T e = (Rm.c - p) + (Rp.c - p);
-            const T s1 = R0.fc + e;
-            T s2 = T(0), s3 = T(0);
-            if (S >= 18) s2 = fma(T(4), e, R0.dc + (Rm.fc + Rp.fc));
-            if (S >= 26) s3 = fma(T(4), e, Rm.dc + Rp.dc);
-            auto grad = [&](T& gx, T& gy, T& gz) {
-                gx = R0.gx;
-                gy = R0.gy;
-                gz = Rp.pc - Rm.pc;
-            };
-            dst[(size_t)z * plane] = point_core<T, S, C>(p, s1, s2, s3, grad, k);
-        }
-        if (more) stage((r + 2) & 1, pre);
+    auto point = [&](int r, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, const PlaneRegs<T>& Rp) {
+        if (!active || r > nout) return;
+        const T p = R0.c;
+        const T e = (Rm.c - p) + (Rp.c - p);
+        const T s1 = R0.fc + e;
+        T s2 = T(0), s3 = T(0);
+        if (S >= 18) s2 = fma(T(4), e, R0.dc + (Rm.fc + Rp.fc));
+        if (S >= 26) s3 = fma(T(4), e, Rm.dc + Rp.dc);
+        auto grad = [&](T& gx, T& gy, T& gz) {
+            gx = R0.gx;
+            gy = R0.gy;
+            gz = Rp.pc - Rm.pc;
+        };
+        dst[(size_t)(z0 - 1 + r) * plane] = point_core<T, S, C>(p, s1, s2, s3, grad, k);
     };
 
-    PlaneRegs<T> A{}, B{}, D{};
+    // Iteration producing planes r, r+1 with registers P0..P3 holding planes
+    // r-1 .. r+2 (P0, P1 already filled).  Planes r+3, r+4, requested two
+    // iterations earlier into the register set Q, are staged into the slots of
+    // planes r-1, r (last read an iteration ago), and planes r+7, r+8 are
+    // requested into Q; consecutive iterations alternate between two sets.
+    auto iter = [&](int r, PlaneRegs<T>& P0, PlaneRegs<T>& P1, PlaneRegs<T>& P2, PlaneRegs<T>& P3,
+                    T (&Q0)[NL], T (&Q1)[NL]) {
+        __syncthreads();
+        load(r + 1, P2);
+        load(r + 2, P3);
+        stage(r + 3, Q0);
+        stage(r + 4, Q1);
+        fetch(r + 7, Q0);
+        fetch(r + 8, Q1);
+        point(r, P0, P1, P2);
+        point(r + 1, P1, P2, P3);
+    };
+
+    PlaneRegs<T> A{}, B{}, D{}, E{};
+    T qa0[NL], qa1[NL], qb0[NL], qb1[NL];
     {
-        T v[NL];
-        fetch(z0 - 1, v);
-        stage(0, v);
-        fetch(z0, v);
-        stage(1, v);
+        // All prologue loads in flight at once: planes 0..3 are staged now,
+        // 4, 5 and 6, 7 are staged by the first two iterations.
+        T v0[NL], v1[NL], v2[NL], v3[NL];
+        fetch(0, v0); fetch(1, v1); fetch(2, v2); fetch(3, v3);
+        fetch(4, qa0); fetch(5, qa1); fetch(6, qb0); fetch(7, qb1);
+        stage(0, v0); stage(1, v1); stage(2, v2); stage(3, v3);
         __syncthreads();
         load(0, A);
         load(1, B);
-        fetch(z0 + 1, v);
-        __syncthreads();
-        stage(0, v);
     }
-    // Unrolled by three so that the plane registers rotate without moves.
-    for (int z = z0; z < zend;) {
-        step(z, A, B, D);
-        if (++z >= zend) break;
-        step(z, B, D, A);
-        if (++z >= zend) break;
-        step(z, D, A, B);
-        ++z;
+    // Unrolled by two so that the plane registers rotate without moves.
+    for (int r = 1; r <= nout; r += 4) {
+        iter(r, A, B, D, E, qa0, qa1);
+        if (r + 2 > nout) break;
+        iter(r + 2, D, E, A, B, qb0, qb1);
     }
 }
 
@@ -182,12 +190,13 @@ struct Smem {
 template <typename T, int S, int C>
 __global__ __launch_bounds__(kTileX* kTileY) void k_step_tiled(const T* __restrict__ in,
                                                                T* __restrict__ out, StepCoef<T> k,
-                                                               int ntx, int nty, int ntiles) {
-    __shared__ T sphi[2 * Smem<T>::HP];
-    __shared__ T spsi[C == kLocal ? 2 * Smem<T>::HP : 1];
+                                                               int ntx, int nty, int ntiles,
+                                                               int zlen) {
+    __shared__ T sphi[4 * Smem<T>::HP];
+    __shared__ T spsi[C == kLocal ? 4 * Smem<T>::HP : 1];
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    tile_sweep<T, S, C>(in, out, k, tx * kTileX, ty * kTileY, tz * kTileZ, sphi, spsi);
+    tile_sweep<T, S, C>(in, out, k, tx * kTileX, ty * kTileY, tz * zlen, zlen, sphi, spsi);
 }
 
 template <int S, int C>
@@ -195,12 +204,13 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_step_batched(
     const float* __restrict__ buf_in, float* __restrict__ buf_out,
     const StepCoef<float>* __restrict__ coef, const int64_t* __restrict__ offset,
     const TileItem* __restrict__ items) {
-    __shared__ float sphi[2 * Smem<float>::HP];
-    __shared__ float spsi[C == kLocal ? 2 * Smem<float>::HP : 1];
+    __shared__ float sphi[4 * Smem<float>::HP];
+    __shared__ float spsi[C == kLocal ? 4 * Smem<float>::HP : 1];
     const TileItem it = items[blockIdx.x];
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
-    tile_sweep<float, S, C>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, sphi, spsi);
+    tile_sweep<float, S, C>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, it.zlen, sphi,
+                            spsi);
 }
 
 template <typename T, template <typename, int, int> class Launch, typename... Args>
@@ -228,13 +238,14 @@ struct PlainLaunch {
 
 template <typename T, int S, int C>
 struct TiledLaunch {
-    static hipError_t run(const T* in, T* out, const StepCoef<T>& k, hipStream_t s) {
+    static hipError_t run(const T* in, T* out, const StepCoef<T>& k, int zlen, hipStream_t s) {
+        if (zlen < 1) return hipErrorInvalidValue;
         const int ntx = (k.nx + kTileX - 1) / kTileX, nty = (k.ny + kTileY - 1) / kTileY;
-        const int ntz = (k.nz + kTileZ - 1) / kTileZ;
+        const int ntz = (k.nz + zlen - 1) / zlen;
         const int64_t n = (int64_t)ntx * nty * ntz;
         if (n > 0x7fffffff) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)n), dim3(kTileX * kTileY), 0, s,
-                           in, out, k, ntx, nty, (int)n);
+                           in, out, k, ntx, nty, (int)n, zlen);
         return hipGetLastError();
     }
 };
@@ -260,8 +271,8 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             hipStream_t s) {
-    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, s);
+                             int zlen, hipStream_t s) {
+    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, zlen, s);
 }
 
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
@@ -276,8 +287,8 @@ template hipError_t launch_step_plain<float>(const float*, float*, const StepCoe
 template hipError_t launch_step_plain<double>(const double*, double*, const StepCoef<double>&, int,
                                               int, hipStream_t);
 template hipError_t launch_step_tiled<float>(const float*, float*, const StepCoef<float>&, int, int,
-                                             hipStream_t);
+                                             int, hipStream_t);
 template hipError_t launch_step_tiled<double>(const double*, double*, const StepCoef<double>&, int,
-                                              int, hipStream_t);
+                                              int, int, hipStream_t);
 
 }  // namespace spfm

@@ -57,7 +57,8 @@ class Info(ctypes.Structure):
                 ("lam", "Gamma", "M", "mu", "dt", "dx", "C_Gamma", "eps", "tau")] + \
                [("gamma", ctypes.c_double * 3), ("dt_max", ctypes.c_double),
                 ("stencil", ctypes.c_int32), ("coupling", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32)]
 
 
 class SpfmError(RuntimeError):
