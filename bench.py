@@ -72,6 +72,7 @@ def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="
         wall = time.perf_counter() - t0
         ev_ms = e0.elapsed_time(e1)
         d = s.diagnostics()
+        d["zchunk"] = s.info()["zchunk"]
         s.close()
     return wall, ev_ms, d
 
@@ -136,7 +137,8 @@ def main():
                                    "centre (ideal radial profile), lambda=4 dx, mu=0, "
                                    "Gamma=M=dx=1, dt=0.1, 26 neighbours, TI_n local normal, "
                                    "FP32 tiled kernel",
-                       "points": npts, "stencil": 26, "coupling": "local", "kernel": "tiled"},
+                       "points": npts, "stencil": 26, "coupling": args.coupling,
+                       "kernel": "tiled", "zchunk": f32["diag"]["zchunk"]},
             "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},

@@ -300,25 +300,32 @@ spfm_status autotune(spfm_ctx* c) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
-    float best = 1e30f;
-    int best_z = c->zlen;
+    float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
     spfm_status st = SPFM_OK;
-    for (int z : cand) {
-        if (z > 2 * c->r.p.nz && z != cand[0]) break;
-        c->zlen = z;
-        hipError_t e = c->launch_one(c->cur);   // warm-up
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
-            if (i == 1) e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess) e = c->launch_one(c->cur);
+    // Two sweeps over the candidates (the first also warms clocks and caches);
+    // each candidate: two untimed launches, then five timed ones.
+    for (int sweep = 0; sweep < 2 && st == SPFM_OK; ++sweep) {
+        for (int ci = 0; ci < 4; ++ci) {
+            const int z = cand[ci];
+            if (ci > 0 && z > 2 * c->r.p.nz) break;
+            c->zlen = z;
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < 7 && e == hipSuccess; ++i) {
+                if (i == 2) e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess) e = c->launch_one(c->cur);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
+            if (ms < best[ci]) best[ci] = ms;
         }
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
-        if (ms < best) { best = ms; best_z = z; }
     }
-    c->zlen = best_z;
+    int bi = 0;
+    for (int ci = 1; ci < 4; ++ci)
+        if (best[ci] < best[bi]) bi = ci;
+    c->zlen = cand[bi];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;

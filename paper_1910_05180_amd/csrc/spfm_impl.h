@@ -62,6 +62,11 @@ __device__ __forceinline__ double fast_rsqrt(double v) { return rsqrt(v); }
 __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double fast_rcp(double v) { return 1.0 / v; }
 
+// An empty statement with side effects: the compiler may not speculate the
+// block containing it, so a wave-uniform branch around that block stays a
+// branch instead of being turned into an unconditional computation and a select.
+__device__ __forceinline__ void keep_branch() { __asm__ volatile("" ::: "memory"); }
+
 // Running sum of y_k / (1 + y_k) kept as one fraction num/den.
 template <typename T>
 struct Frac {
@@ -147,16 +152,19 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             const T cx = (ex - T(1)) * (ex - T(1)) * rx;
             const T cy = (ey - T(1)) * (ey - T(1)) * ry;
             const T cz = (ez - T(1)) * (ez - T(1)) * rz;
-            if (fabs(x) < k.xtail) {
-                // y/(1+y) -> y: the per-shell sums of m_k in closed form,
-                // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2
-                const T c1 = cx + cy + cz;
-                const T c2 = fma(cx, cy, fma(cy, cz, cx * cz));
-                q = k.K[0] * c1;
-                if (S >= 18) q = fma(k.K[1], fma(T(4), c1, c2), q);
-                if (S >= 26) q = fma(k.K[2], fma(T(4), c1, fma(T(2), c2, cx * cy * cz)), q);
-                q *= x;
-            } else {
+            // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
+            // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
+            const T c1 = cx + cy + cz;
+            const T c2 = fma(cx, cy, fma(cy, cz, cx * cz));
+            q = k.K[0] * c1;
+            if (S >= 18) q = fma(k.K[1], fma(T(4), c1, c2), q);
+            if (S >= 26) q = fma(k.K[2], fma(T(4), c1, fma(T(2), c2, cx * cy * cz)), q);
+            q *= x;
+            // The full coupling only where some lane of the wave needs it; the vote
+            // keeps the branch wave-uniform, so tail-only waves skip it entirely.
+            const bool full = !(fabs(x) < k.xtail);
+            if (__ballot(full) != 0) {
+                keep_branch();
                 const T sx = ex - rx, sy = ey - ry, sz = ez - rz;   // 2 sinh
                 T m2[6];   // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
                 T m3[4];   // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
@@ -192,18 +200,21 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
                         m3[3] = fma(T(0.5), pc - ps, base);
                     }
                 }
-                q = shell_sums<T, S>(cx, cy, cz, m2, m3, x, k);
+                const T qf = shell_sums<T, S>(cx, cy, cz, m2, m3, x, k);
+                q = full ? qf : q;
             }
         } else {
-            if (fabs(x) < k.xtail) {
-                q = x * (k.K[0] * k.msum[0] + k.K[1] * k.msum[1] + k.K[2] * k.msum[2]);
-            } else {
+            q = x * (k.K[0] * k.msum[0] + k.K[1] * k.msum[1] + k.K[2] * k.msum[2]);
+            const bool full = !(fabs(x) < k.xtail);
+            if (__ballot(full) != 0) {
+                keep_branch();
                 T m2[6], m3[4];
 #pragma unroll
                 for (int i = 0; i < 6; ++i) m2[i] = k.mg[3 + i];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) m3[i] = k.mg[9 + i];
-                q = shell_sums<T, S>(k.mg[0], k.mg[1], k.mg[2], m2, m3, x, k);
+                const T qf = shell_sums<T, S>(k.mg[0], k.mg[1], k.mg[2], m2, m3, x, k);
+                q = full ? qf : q;
             }
         }
         upd = fma(-u, q, upd);

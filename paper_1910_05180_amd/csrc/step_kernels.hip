@@ -10,6 +10,8 @@
 //                TI_n the log-ratio psi' of every staged cell is computed once.
 //  k_step_batched the tiled sweep over a flat list of (grid, tile) items that
 //                covers many independent grids in one launch.
+#include <type_traits>
+
 #include "spfm_impl.h"
 
 namespace spfm {
@@ -54,7 +56,7 @@ struct PlaneRegs {
 
 // One block sweeps the tile [x0, x0+kTileX) x [y0, y0+kTileY) x [z0, z0+zlen)
 // (clipped to the grid).  Each plane of the tile plus a one-cell halo is read
-// from global memory once (coalesced rows) one iteration before it is staged
+// from global memory once (coalesced rows) two iterations before it is staged
 // into a four-slot LDS ring, together with psi' of every cell for TI_n.  Every
 // thread reads its 3x3 in-plane neighbourhood of each plane once and keeps
 // per-plane partial sums in registers; with them the 26-neighbour shell sums of
@@ -63,55 +65,57 @@ struct PlaneRegs {
 //   e = (c(z-1) - c(z)) + (c(z+1) - c(z)),
 // all built from differences of nearby values.  Two output planes are produced
 // per iteration (one barrier per two planes, two independent points per thread).
+// Planes are numbered relative to the sweep, r = 0 for z0 - 1; plane r lives in
+// LDS slot r & 3.  Iterations start at r = 1 (mod 4) and alternate parity, so the
+// slots each iteration touches are compile-time constants.
 template <typename T, int S, int C>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi) {
     constexpr int HX = kTileX + 2, HY = kTileY + 2, HP = HX * HY;
     constexpr int NT = kTileX * kTileY;
-    constexpr int NL = (HP + NT - 1) / NT;   // halo cells loaded per thread
+    static_assert(NT <= HP && HP <= 2 * NT, "the halo plane takes two load rounds");
     const int tid = threadIdx.x;
     const int tx = tid % kTileX, ty = tid / kTileX;
     const int nx = k.nx, ny = k.ny, nz = k.nz;
     const size_t plane = (size_t)nx * ny;
 
-    // In-plane offsets of this thread's halo cells (fixed along the sweep).
-    int loff[NL];
-    bool lval[NL];
-#pragma unroll
-    for (int c = 0; c < NL; ++c) {
-        const int cell = tid + c * NT;
-        lval[c] = cell < HP;
-        int gx = x0 - 1 + cell % HX, gy = y0 - 1 + cell / HX;
+    // In-plane offsets of this thread's two halo cells (fixed along the sweep);
+    // the first always exists, the second only for tid + NT < HP.
+    int loff0, loff1;
+    {
+        int gx = x0 - 1 + tid % HX, gy = y0 - 1 + tid / HX;
         gx %= nx; if (gx < 0) gx += nx;
         gy %= ny; if (gy < 0) gy += ny;
-        loff[c] = lval[c] ? gy * nx + gx : 0;
+        loff0 = gy * nx + gx;
+        const int c1 = tid + NT;
+        gx = x0 - 1 + c1 % HX; gy = y0 - 1 + c1 / HX;
+        gx %= nx; if (gx < 0) gx += nx;
+        gy %= ny; if (gy < 0) gy += ny;
+        loff1 = c1 < HP ? gy * nx + gx : 0;
     }
+    const bool has1 = tid + NT < HP;
     const int nout = min(zlen, nz - z0);   // output planes z0 .. z0+nout-1
     const int last = nout + 1;             // relative index of the last plane needed
-    // Relative plane index r: plane z0 - 1 + r, held in LDS slot r & 3.
-    auto fetch = [&](int r, T (&v)[NL]) {
-        if (r > last) return;               // beyond the sweep: never loaded
-        const T* src = in + (size_t)wrap_once(z0 - 1 + r, nz) * plane;
-#pragma unroll
-        for (int c = 0; c < NL; ++c) v[c] = lval[c] ? src[loff[c]] : T(0);
+
+    struct Pair { T v0, v1; };
+    auto fetch_at = [&](const T* src, Pair& v) {
+        v.v0 = src[loff0];
+        v.v1 = src[loff1];   // loff1 = 0 (a valid address) where the cell does not exist
     };
-    auto stage = [&](int r, const T (&v)[NL]) {
-        if (r > last) return;
-        T* dphi = sphi + (r & 3) * HP;
-        T* dpsi = spsi + (r & 3) * HP;
-#pragma unroll
-        for (int c = 0; c < NL; ++c) {
-            if (lval[c]) {
-                dphi[tid + c * NT] = v[c];
-                if (C == kLocal) dpsi[tid + c * NT] = psi2(v[c], k.eps);
-            }
+    auto stage_slot = [&](int slot, const Pair& v) {
+        T* dphi = sphi + slot * HP;
+        T* dpsi = spsi + slot * HP;
+        dphi[tid] = v.v0;
+        if (C == kLocal) dpsi[tid] = psi2(v.v0, k.eps);
+        if (has1) {
+            dphi[tid + NT] = v.v1;
+            if (C == kLocal) dpsi[tid + NT] = psi2(v.v1, k.eps);
         }
     };
     const int cc = (ty + 1) * HX + (tx + 1);
-    auto load = [&](int r, PlaneRegs<T>& R) {
-        if (r > last) return;
-        const T* P = sphi + (r & 3) * HP;
+    auto load_slot = [&](int slot, PlaneRegs<T>& R) {
+        const T* P = sphi + slot * HP;
         const T c = P[cc];
         R.c = c;
         R.fc = ((P[cc + 1] - c) + (P[cc - 1] - c)) + ((P[cc + HX] - c) + (P[cc - HX] - c));
@@ -119,16 +123,15 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             R.dc = ((P[cc + HX + 1] - c) + (P[cc - HX - 1] - c)) +
                    ((P[cc + HX - 1] - c) + (P[cc - HX + 1] - c));
         if (C == kLocal) {
-            const T* Q = spsi + (r & 3) * HP;
+            const T* Q = spsi + slot * HP;
             R.gx = Q[cc + 1] - Q[cc - 1];
             R.gy = Q[cc + HX] - Q[cc - HX];
             R.pc = Q[cc];
         }
     };
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
-    T* dst = out + (size_t)(y0 + ty) * nx + (x0 + tx);
-    auto point = [&](int r, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, const PlaneRegs<T>& Rp) {
-        if (!active || r > nout) return;
+    T* const dst0 = out + (size_t)(y0 + ty) * nx + (x0 + tx);
+    auto point = [&](T* dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, const PlaneRegs<T>& Rp) {
         const T p = R0.c;
         const T e = (Rm.c - p) + (Rp.c - p);
         const T s1 = R0.fc + e;
@@ -140,45 +143,71 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             gy = R0.gy;
             gz = Rp.pc - Rm.pc;
         };
-        dst[(size_t)(z0 - 1 + r) * plane] = point_core<T, S, C>(p, s1, s2, s3, grad, k);
+        const T v = point_core<T, S, C>(p, s1, s2, s3, grad, k);
+        if (active) *dst = v;
     };
+    auto plane_ptr = [&](int r) { return in + (size_t)wrap_once(z0 - 1 + r, nz) * plane; };
 
-    // Iteration producing planes r, r+1 with registers P0..P3 holding planes
-    // r-1 .. r+2 (P0, P1 already filled).  Planes r+3, r+4, requested two
-    // iterations earlier into the register set Q, are staged into the slots of
-    // planes r-1, r (last read an iteration ago), and planes r+7, r+8 are
-    // requested into Q; consecutive iterations alternate between two sets.
-    auto iter = [&](int r, PlaneRegs<T>& P0, PlaneRegs<T>& P1, PlaneRegs<T>& P2, PlaneRegs<T>& P3,
-                    T (&Q0)[NL], T (&Q1)[NL]) {
+    // Iteration producing planes r, r+1 (slots: parity 0 reads 2, 3 and
+    // writes 0, 1; parity 1 reads 0, 1 and writes 2, 3) with registers P0..P3
+    // holding planes r-1 .. r+2 (P0, P1 already filled).  Planes r+3, r+4,
+    // requested two iterations earlier into the set Q, are staged into the
+    // slots of planes r-1, r (last read an iteration ago), and planes r+7, r+8
+    // are requested into Q.  GUARD: near the end of the sweep, skip planes
+    // beyond it (steady iterations need no checks).
+    auto iter = [&](auto par, auto guard, int r, PlaneRegs<T>& P0, PlaneRegs<T>& P1,
+                    PlaneRegs<T>& P2, PlaneRegs<T>& P3, Pair& Q0, Pair& Q1) {
+        constexpr int rd = decltype(par)::value ? 0 : 2;
+        constexpr int wr = decltype(par)::value ? 2 : 0;
+        constexpr bool G = decltype(guard)::value;
         __syncthreads();
-        load(r + 1, P2);
-        load(r + 2, P3);
-        stage(r + 3, Q0);
-        stage(r + 4, Q1);
-        fetch(r + 7, Q0);
-        fetch(r + 8, Q1);
-        point(r, P0, P1, P2);
-        point(r + 1, P1, P2, P3);
+        if (!G || r + 1 <= last) load_slot(rd, P2);
+        if (!G || r + 2 <= last) load_slot(rd + 1, P3);
+        if (!G || r + 3 <= last) stage_slot(wr, Q0);
+        if (!G || r + 4 <= last) stage_slot(wr + 1, Q1);
+        if (!G || r + 7 <= last) fetch_at(plane_ptr(r + 7), Q0);
+        if (!G || r + 8 <= last) fetch_at(plane_ptr(r + 8), Q1);
+        T* dst = dst0 + (size_t)(z0 - 1 + r) * plane;
+        if (!G || r <= nout) point(dst, P0, P1, P2);
+        if (!G || r + 1 <= nout) point(dst + plane, P1, P2, P3);
     };
+    using P0t = std::integral_constant<int, 0>;
+    using P1t = std::integral_constant<int, 1>;
+    using Steady = std::false_type;
+    using Guarded = std::true_type;
 
     PlaneRegs<T> A{}, B{}, D{}, E{};
-    T qa0[NL], qa1[NL], qb0[NL], qb1[NL];
+    Pair qa0{}, qa1{}, qb0{}, qb1{};
     {
         // All prologue loads in flight at once: planes 0..3 are staged now,
         // 4, 5 and 6, 7 are staged by the first two iterations.
-        T v0[NL], v1[NL], v2[NL], v3[NL];
-        fetch(0, v0); fetch(1, v1); fetch(2, v2); fetch(3, v3);
-        fetch(4, qa0); fetch(5, qa1); fetch(6, qb0); fetch(7, qb1);
-        stage(0, v0); stage(1, v1); stage(2, v2); stage(3, v3);
+        Pair v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r <= last) fetch_at(plane_ptr(r), v[r]);
+        if (4 <= last) fetch_at(plane_ptr(4), qa0);
+        if (5 <= last) fetch_at(plane_ptr(5), qa1);
+        if (6 <= last) fetch_at(plane_ptr(6), qb0);
+        if (7 <= last) fetch_at(plane_ptr(7), qb1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r <= last) stage_slot(r, v[r]);
         __syncthreads();
-        load(0, A);
-        load(1, B);
+        load_slot(0, A);
+        load_slot(1, B);
     }
-    // Unrolled by two so that the plane registers rotate without moves.
-    for (int r = 1; r <= nout; r += 4) {
-        iter(r, A, B, D, E, qa0, qa1);
+    // Unrolled by two so that the plane registers rotate without moves.  The
+    // steady loop runs while every plane an iteration pair touches lies strictly
+    // inside the sweep (no wrap, no checks).
+    int r = 1;
+    for (; r + 10 <= nout; r += 4) {
+        iter(P0t{}, Steady{}, r, A, B, D, E, qa0, qa1);
+        iter(P1t{}, Steady{}, r + 2, D, E, A, B, qb0, qb1);
+    }
+    for (; r <= nout; r += 4) {
+        iter(P0t{}, Guarded{}, r, A, B, D, E, qa0, qa1);
         if (r + 2 > nout) break;
-        iter(r + 2, D, E, A, B, qb0, qb1);
+        iter(P1t{}, Guarded{}, r + 2, D, E, A, B, qb0, qb1);
     }
 }
 
@@ -187,8 +216,18 @@ struct Smem {
     static constexpr int HP = (kTileX + 2) * (kTileY + 2);
 };
 
+#ifndef SPFM_WAVES_F32
+#define SPFM_WAVES_F32 8
+#endif
+// Waves per SIMD the tiled kernels are compiled for: FP32 fits its working set
+// in 64 VGPRs (8 waves); FP64 needs about twice as many registers.
+template <typename T>
+struct WavesPerSimd {
+    static constexpr int value = sizeof(T) == 4 ? SPFM_WAVES_F32 : 4;
+};
+
 template <typename T, int S, int C>
-__global__ __launch_bounds__(kTileX* kTileY) void k_step_tiled(const T* __restrict__ in,
+__global__ __launch_bounds__(kTileX* kTileY, WavesPerSimd<T>::value) void k_step_tiled(const T* __restrict__ in,
                                                                T* __restrict__ out, StepCoef<T> k,
                                                                int ntx, int nty, int ntiles,
                                                                int zlen) {
@@ -200,7 +239,7 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_step_tiled(const T* __restri
 }
 
 template <int S, int C>
-__global__ __launch_bounds__(kTileX* kTileY) void k_step_batched(
+__global__ __launch_bounds__(kTileX* kTileY, WavesPerSimd<float>::value) void k_step_batched(
     const float* __restrict__ buf_in, float* __restrict__ buf_out,
     const StepCoef<float>* __restrict__ coef, const int64_t* __restrict__ offset,
     const TileItem* __restrict__ items) {
