@@ -23,6 +23,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ALG_BYTES_F32 = 8              # read phi^n + write phi^{n+1} per point per step
 ALG_BYTES_F64 = 16
+# FP32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-operations per second (one FP32 add, mul, fma, compare, select or
+# transcendental per lane per cycle).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic FP32 operations per point update of the TI_n 26-neighbour step on
+# the grain workload: 39 where phi(1-phi) = 0 (14% of points), 86 in the tail
+# branch (76%), 195 with the full coupling (10%), counted from the per-point
+# formulas (shell sums, normal, exponentials, coupling terms, update, psi').
+ALG_OPS_LOCAL26 = 0.14 * 39 + 0.76 * 86 + 0.10 * 195
+ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..64)
+# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (scale factors from the copy reference), 43928.2 and 81920.0
+# KiB; set to None whenever the kernel changes after the counters were taken.
+TRAFFIC_BYTES_LOCAL26 = (43928.2 * 2.0 + 81920.0) * 1024
 
 
 def parse():
@@ -33,7 +47,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=10)
-    ap.add_argument("--only", default="", help="run only this leg: f32 | f64 (profiling)")
+    ap.add_argument("--only", default="", help="run only this leg: f32 | f64 | batch | grains")
+    ap.add_argument("--side-steps", type=int, default=200,
+                    help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
                     help="coupling of the timed legs (the headline is local, TI_n)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -52,13 +68,14 @@ def copy_reference(torch):
     return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
-def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local"):
+def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0):
     """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
     Returns (wall seconds, event milliseconds) of the timed region."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = spfm.Spfm(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx,
-                      stencil=w.stencil, dtype=dtype, coupling=coupling, kernel=kernel, dt=w.dt)
+                      stencil=w.stencil, dtype=dtype, coupling=coupling, kernel=kernel, dt=w.dt,
+                      zchunk=zchunk)
         s.init_spheres(w.centers, w.radii)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -75,6 +92,45 @@ def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="
         d["zchunk"] = s.info()["zchunk"]
         s.close()
     return wall, ev_ms, d
+
+
+def batch_leg(spfm, torch, inputs, steps, warmup):
+    """FP32 TI_n 26-neighbour stepping of the 64 uneven periodic slabs, one launch
+    per step for all grids, captured in HIP graphs."""
+    ws = inputs.batch64()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = spfm.SpfmBatch([w.shape for w in ws], lam=[w.lam for w in ws], mu=[w.mu for w in ws],
+                           stencil=26, coupling="local")
+        b.init_planar([w.hkl for w in ws], [w.offset for w in ws])
+        b.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n = b.points
+        b.close()
+    return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "grids": len(ws), "points": n,
+            "steps": steps, "ms_per_step": wall * 1e3 / steps,
+            "kernel_ms_per_step": e0.elapsed_time(e1) / steps,
+            "pct_hbm_peak": 100.0 * ALG_BYTES_F32 * n / (e0.elapsed_time(e1) / steps * 1e-3) / 1e9
+            / HBM_PEAK_GBS}
+
+
+def grains_leg(spfm, torch, inputs, steps, warmup):
+    """FP32 TI_n 26-neighbour step on the 512^3 box with 300 grains (1 GiB ping-pong)."""
+    w = inputs.grains512()
+    wall, ev_ms, _ = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled", steps=steps,
+                               warmup=warmup, zchunk=ZCHUNK)
+    n = w.shape[0] * w.shape[1] * w.shape[2]
+    return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "points": n, "grains": len(w.radii),
+            "steps": steps, "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
+            "pct_hbm_peak": 100.0 * ALG_BYTES_F32 * n / (ev_ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def cpu_baseline(w, steps):
@@ -114,8 +170,9 @@ def main():
         out["copy_reference"] = copy_reference(torch)
     f32 = f64 = None
     if args.only in ("", "f32"):
-        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="auto",
-                                   steps=args.steps, warmup=args.warmup, coupling=args.coupling)
+        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
+                                   steps=args.steps, warmup=args.warmup, coupling=args.coupling,
+                                   zchunk=ZCHUNK)
         f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
     if args.only in ("", "f64"):
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",
@@ -129,6 +186,13 @@ def main():
         glups = npts * steps / f32["wall"] / 1e9
         kern_ms = f32["ev_ms"] / steps                  # average step-kernel duration
         achieved = ALG_BYTES_F32 * npts / (kern_ms * 1e-3) / 1e9
+        if args.coupling == "local":
+            alu = ALG_OPS_LOCAL26 * npts / (kern_ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                        "frac": alu / VALU_PEAK_TOPS, "traffic": TRAFFIC_BYTES_LOCAL26}
+        else:
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
         out.update({
             "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -140,8 +204,8 @@ def main():
                        "points": npts, "stencil": 26, "coupling": args.coupling,
                        "kernel": "tiled", "zchunk": f32["diag"]["zchunk"]},
             "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "hbm_achieved_gbs": achieved,
+            "roofline": roofline,
             "kernel_ms_per_step": kern_ms,
             "phi_range": [f32["diag"]["phi_min"], f32["diag"]["phi_max"]],
         })
@@ -154,6 +218,10 @@ def main():
                              (f64["ev_ms"] / s64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if f32 is not None:
             out["speedup_vs_fp64_plain"] = out["value"] / g64
+    if args.only in ("", "batch"):
+        out["batch64"] = batch_leg(spfm, torch, inputs, args.side_steps, 10)
+    if args.only in ("", "grains"):
+        out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -90,6 +90,8 @@ typedef struct {
                            nx*ny*nz elements of dtype; both NULL = library allocates */
     int32_t kernel;     /* spfm_kernel */
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
+    int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
+                           library (timed at the first step for AUTO, a size rule for TILED) */
 } spfm_options;
 
 typedef struct {

@@ -69,6 +69,7 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
         return fail(SPFM_E_INVAL, "unknown coupling %d", o.coupling);
     if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_TILED)
         return fail(SPFM_E_INVAL, "unknown kernel %d", o.kernel);
+    if (o.zchunk < 0 || o.zchunk > 4096) return fail(SPFM_E_INVAL, "zchunk must be in 0..4096");
     const double un = std::sqrt(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2]);
     if (o.coupling == SPFM_GLOBAL && !(un > 0.0 && std::isfinite(un)))
         return fail(SPFM_E_INVAL, "GLOBAL coupling needs a nonzero direction u");
@@ -399,8 +400,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     if (!c) return fail(SPFM_E_NOMEM, "host allocation failed");
     c->r = r;
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
-    c->auto_kernel = !opt || opt->kernel == SPFM_KERNEL_AUTO;
-    c->zlen = default_zlen(r.p.nx, r.p.ny, r.p.nz);
+    c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
+    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.p.nx, r.p.ny, r.p.nz);
     const size_t bytes = c->bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];

@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("gamma", ctypes.c_double * 3), ("C_Gamma", ctypes.c_double),
                 ("eps", ctypes.c_double), ("tau", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("d_phi", ctypes.c_void_p * 2),
-                ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -144,7 +145,7 @@ def _stream_handle(stream):
 
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
-             allow_unstable=False) -> Options:
+             allow_unstable=False, zchunk=0) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -157,6 +158,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.stream = _stream_handle(stream)
     o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.allow_unstable = 1 if allow_unstable else 0
+    o.zchunk = int(zchunk)
     return o
 
 
