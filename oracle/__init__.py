@@ -79,6 +79,9 @@ def lib():
                                                                ctypes.c_double, dp]
             L.orc_init_spheres.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
                                                                ctypes.c_int, dp, dp, dp]
+            L.orc_spheres_at.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                              ctypes.c_int, dp, dp, ctypes.c_long,
+                                                              ctypes.POINTER(ctypes.c_int), dp]
             L.orc_num_threads.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -194,6 +197,39 @@ def init_spheres(shape, centers, radii, *, dx=1.0, lam=4.0) -> np.ndarray:
     r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
     out = np.empty(shape, dtype=np.float64)
     lib().orc_init_spheres(nx, ny, nz, dx, lam, r.size, _dp(c), _dp(r), _dp(out))
+    return out
+
+
+def spheres_at(shape, centers, radii, xyz, *, dx=1.0, lam=4.0) -> np.ndarray:
+    """The init_spheres field of a box of `shape` at integer coordinates xyz (N x 3, x y z)."""
+    nz, ny, nx = shape
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    q = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    out = np.empty(q.shape[0])
+    lib().orc_spheres_at(nx, ny, nz, dx, lam, r.size, _dp(c), _dp(r), q.shape[0],
+                         q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out))
+    return out
+
+
+def cone_step(p: Params, shape, field_at, centres_xyz, nsteps: int) -> np.ndarray:
+    """Values after nsteps steps at the given points of a large periodic box, each
+    from its dependency cone: a point's value after K steps depends only on the
+    (2K+1)^3 box around it, so the oracle steps that crop (built by
+    field_at(xyz) with periodic coordinates) and keeps its centre."""
+    nz, ny, nx = shape
+    k = int(nsteps)
+    w = 2 * k + 1
+    off = np.arange(-k, k + 1)
+    dz, dy, dxx = np.meshgrid(off, off, off, indexing="ij")
+    out = np.empty(len(centres_xyz))
+    q = Params()
+    ctypes.pointer(q)[0] = p
+    q.nx = q.ny = q.nz = w
+    for i, (x, y, z) in enumerate(centres_xyz):
+        xyz = np.stack([(x + dxx) % nx, (y + dy) % ny, (z + dz) % nz], axis=-1).reshape(-1, 3)
+        crop = field_at(xyz).reshape(w, w, w)
+        out[i] = step(q, crop, k)[k, k, k] if k > 0 else crop[0, 0, 0]
     return out
 
 

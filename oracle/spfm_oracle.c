@@ -416,7 +416,9 @@ void orc_init_spheres(int nx, int ny, int nz, double dx, double lambda, int n,
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 double pos[3] = {x * dx, y * dx, z * dx};
-                double q = 1.0;
+                /* 1 - prod_i (1 - phi_i) accumulated as sum_i phi_i prod_{j<i} (1 - phi_j),
+                 * which keeps small tail values exact */
+                double acc = 0.0, prod = 1.0;
                 for (int i = 0; i < n; ++i) {
                     double r2 = 0.0;
                     for (int a = 0; a < 3; ++a) {
@@ -425,10 +427,36 @@ void orc_init_spheres(int nx, int ny, int nz, double dx, double lambda, int n,
                         r2 += d * d;
                     }
                     double v = 0.5 * (1.0 - tanh(2.0 * (sqrt(r2) - radii[i]) / lambda));
-                    q *= 1.0 - v;
+                    acc += prod * v;
+                    prod *= 1.0 - v;
                 }
-                phi[((long)z * ny + y) * nx + x] = 1.0 - q;
+                phi[((long)z * ny + y) * nx + x] = acc;
             }
+}
+
+/* The field of orc_init_spheres (box nx x ny x nz) evaluated at npts grid
+ * coordinates given as integer triples (x, y, z), for crops of large boxes. */
+void orc_spheres_at(int nx, int ny, int nz, double dx, double lambda, int n,
+                    const double *centers, const double *radii, long npts, const int *xyz,
+                    double *out) {
+    double L[3] = {nx * dx, ny * dx, nz * dx};
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < npts; ++q) {
+        double pos[3] = {xyz[3 * q] * dx, xyz[3 * q + 1] * dx, xyz[3 * q + 2] * dx};
+        double acc = 0.0, prod = 1.0;
+        for (int i = 0; i < n; ++i) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double d = pos[a] - centers[3 * i + a];
+                d -= L[a] * nearbyint(d / L[a]);
+                r2 += d * d;
+            }
+            double v = 0.5 * (1.0 - tanh(2.0 * (sqrt(r2) - radii[i]) / lambda));
+            acc += prod * v;
+            prod *= 1.0 - v;
+        }
+        out[q] = acc;
+    }
 }
 
 int orc_num_threads(void) {

@@ -68,6 +68,10 @@ void orc_init_planar(int nx, int ny, int nz, double dx, double lambda, const int
                      double offset, double *phi);
 void orc_init_spheres(int nx, int ny, int nz, double dx, double lambda, int n,
                       const double *centers, const double *radii, double *phi);
+/* The field of orc_init_spheres at npts integer grid coordinates xyz[3*q..3*q+2]. */
+void orc_spheres_at(int nx, int ny, int nz, double dx, double lambda, int n,
+                    const double *centers, const double *radii, long npts, const int *xyz,
+                    double *out);
 /* Threads the oracle runs on. */
 int orc_num_threads(void);
 

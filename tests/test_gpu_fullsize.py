@@ -1,0 +1,88 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(FP32 tiled kernel, 16 planes per block), on sampled outputs.
+
+The GPU builds its own initial field; the oracle builds its own at the
+dependency cone of each sampled point (a point's value after K steps depends
+only on the (2K+1)^3 box around it) and steps that crop.  The two initial
+fields differ only by the FP32 rounding of the GPU's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ZCHUNK = 16
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_05180_amd import spfm
+    spfm.load()
+    return spfm
+
+
+def sample_points(rng, shape, centers, radii, n, lam):
+    """Half uniform, half inside the interface bands of the grains."""
+    nz, ny, nx = shape
+    pts = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz)))
+           for _ in range(n // 2)]
+    while len(pts) < n:
+        i = int(rng.integers(len(radii)))
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        r = radii[i] + rng.uniform(-3 * lam, 3 * lam)
+        p = np.asarray(centers[i]) + r * v
+        pts.append((int(round(p[0])) % nx, int(round(p[1])) % ny, int(round(p[2])) % nz))
+    return pts
+
+
+def run_grains(S, w, steps, nsamples, seed):
+    rng = np.random.default_rng(seed)
+    print(f"full size {w.shape} grains={len(w.radii)} steps={steps}", flush=True)
+    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f32", coupling="local",
+                kernel="tiled", zchunk=ZCHUNK, dt=w.dt) as s:
+        assert s.info()["zchunk"] == ZCHUNK
+        s.init_spheres(w.centers, w.radii)
+        s.step(steps)
+        got = s.get_field()
+    pts = sample_points(rng, w.shape, w.centers, w.radii, nsamples, w.lam)
+    p = oracle.params((3, 3, 3), lam=w.lam, mu=w.mu, dt=w.dt, stencil=26, coupling="local",
+                      eps=1e-30)
+    field_at = lambda xyz: oracle.spheres_at(w.shape, w.centers, w.radii, xyz, lam=w.lam)
+    ref = oracle.cone_step(p, w.shape, field_at, pts, steps)
+    g = np.array([got[z, y, x] for x, y, z in pts], dtype=np.float64)
+    interface = (ref > 1e-3) & (ref < 1 - 1e-3)
+    assert interface.sum() > nsamples // 4
+    return float(np.abs(g - ref).max())
+
+
+def test_grain256_bench_configuration(S):
+    from paper_1910_05180_amd import inputs
+    err = run_grains(S, inputs.sphere256(mu=0.02), 6, 2000, 11)
+    assert err <= 1e-5
+
+
+def test_grains512_bench_configuration(S):
+    from paper_1910_05180_amd import inputs
+    err = run_grains(S, inputs.grains512(), 3, 1000, 12)
+    assert err <= 1e-5
+
+
+def test_grain256_fp64_plain_one_step_everywhere(S):
+    """The FP64 plain kernel of the metric, one step, every point of 256^3."""
+    from paper_1910_05180_amd import inputs
+    w = inputs.sphere256(mu=0.02)
+    phi0 = oracle.init_spheres(w.shape, w.centers, w.radii, lam=w.lam)
+    p = oracle.params(w.shape, lam=w.lam, mu=w.mu, dt=w.dt, stencil=26, coupling="local",
+                      eps=1e-300)
+    ref = oracle.step(p, phi0, 1)
+    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f64", coupling="local",
+                kernel="plain", dt=w.dt, eps=1e-300) as s:
+        s.set_field(phi0)
+        s.step(1)
+        got = s.get_field()
+    assert np.abs(got - ref).max() <= 1e-12
