@@ -33,10 +33,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # formulas (shell sums, normal, exponentials, coupling terms, update, psi').
 ALG_OPS_LOCAL26 = 0.14 * 39 + 0.76 * 86 + 0.10 * 195
 ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..64)
-# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0 (scale factors from the copy reference), 43928.2 and 81920.0
-# KiB; set to None whenever the kernel changes after the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = (43928.2 * 2.0 + 81920.0) * 1024
+# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the factors the same counters give for the copy
+# reference; None whenever the kernel has changed since the counters were taken.
+TRAFFIC_BYTES_LOCAL26 = None
 
 
 def parse():
@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=10)
-    ap.add_argument("--only", default="", help="run only this leg: f32 | f64 | batch | grains")
+    ap.add_argument("--only", default="",
+                    help="run only this leg: f32 | f64 | batch | grains | temporal")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -68,14 +69,15 @@ def copy_reference(torch):
     return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
-def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0):
+def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0,
+              tsteps=0):
     """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
     Returns (wall seconds, event milliseconds) of the timed region."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = spfm.Spfm(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx,
                       stencil=w.stencil, dtype=dtype, coupling=coupling, kernel=kernel, dt=w.dt,
-                      zchunk=zchunk)
+                      zchunk=zchunk, tsteps=tsteps)
         s.init_spheres(w.centers, w.radii)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -122,15 +124,22 @@ def batch_leg(spfm, torch, inputs, steps, warmup):
             / HBM_PEAK_GBS}
 
 
-def grains_leg(spfm, torch, inputs, steps, warmup):
-    """FP32 TI_n 26-neighbour step on the 512^3 box with 300 grains (1 GiB ping-pong)."""
+def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0):
+    """FP32 TI_n 26-neighbour step on the 512^3 box with 300 grains (1 GiB
+    ping-pong); with tsteps > 1 the temporally blocked kernel fuses that many
+    steps per pass over the field (z-chunk 32)."""
     w = inputs.grains512()
+    zc = 32 if tsteps > 1 else ZCHUNK
+    steps -= steps % max(tsteps, 1)
     wall, ev_ms, _ = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled", steps=steps,
-                               warmup=warmup, zchunk=ZCHUNK)
+                               warmup=warmup, zchunk=zc, tsteps=tsteps)
     n = w.shape[0] * w.shape[1] * w.shape[2]
+    bytes_per_point = ALG_BYTES_F32 / max(tsteps, 1)
     return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "points": n, "grains": len(w.radii),
-            "steps": steps, "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
-            "pct_hbm_peak": 100.0 * ALG_BYTES_F32 * n / (ev_ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "steps": steps, "tsteps": max(tsteps, 1), "zchunk": zc,
+            "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
+            "pct_hbm_peak": 100.0 * bytes_per_point * n / (ev_ms / steps * 1e-3) / 1e9
+            / HBM_PEAK_GBS}
 
 
 def cpu_baseline(w, steps):
@@ -222,6 +231,8 @@ def main():
         out["batch64"] = batch_leg(spfm, torch, inputs, args.side_steps, 10)
     if args.only in ("", "grains"):
         out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
+    if args.only in ("", "temporal"):
+        out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

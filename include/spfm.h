@@ -92,6 +92,10 @@ typedef struct {
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
                            library (timed at the first step for AUTO, a size rule for TILED) */
+    int32_t tsteps;     /* temporal blocking: steps fused into one pass over the field, 0 or 1 =
+                           none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
+                           equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
+                           n / tsteps fused launches and n % tsteps single steps */
 } spfm_options;
 
 typedef struct {
@@ -117,6 +121,7 @@ typedef struct {
     int32_t stencil, coupling, dtype, kernel;
     int32_t zchunk;            /* planes per block of the tiled kernel (chosen by timing
                                   at the first spfm_step when kernel is AUTO) */
+    int32_t tsteps;            /* steps per fused launch (1 = no temporal blocking) */
 } spfm_info;
 
 typedef struct spfm_ctx spfm_ctx;
@@ -126,7 +131,8 @@ typedef struct spfm_batch spfm_batch;
  * lambda: interface width (Eq. 3), Gamma: interface energy, M: kinetic
  * coefficient, mu: driving force (Eq. 1-2); stencil: 6, 18 or 26.
  * Returns SPFM_E_INVAL for non-positive lambda, Gamma, M or dx, an unknown
- * stencil, coupling or dtype, a grid edge below 3, a zero GLOBAL direction,
+ * stencil, coupling or dtype, a grid edge below 3, a grid too large (one
+ * z-plane of 2^31 bytes or more, ny > 262140 or nz > 65535), a zero GLOBAL direction,
  * F32 with lambda < 0.3 dx, or exactly one of d_phi given;
  * SPFM_E_UNSTABLE when dt exceeds the explicit bound (unless allow_unstable).
  * Argument checks happen before any HIP call.  The field is zero until set. */
@@ -168,7 +174,7 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * captures the launches of n steps in one HIP graph.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
  * eps, tau, allow_unstable) apply to every grid; each grid gets its own
- * lambda, Gamma, M, mu; d_phi must be NULL. */
+ * lambda, Gamma, M, mu; d_phi must be NULL and tsteps <= 1. */
 spfm_status spfm_batch_create(int32_t n, const spfm_grid *grids, const double *lambda,
                               const double *Gamma, const double *M, const double *mu,
                               int stencil, const spfm_options *opt, spfm_batch **out);

@@ -43,6 +43,7 @@ constexpr int kGraphSteps = 16;
 struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
+    int tsteps;   // steps per launch (temporal blocking), 1 = one step
     double dt_max;
 };
 
@@ -54,9 +55,6 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     if (opt) o = *opt; else std::memset(&o, 0, sizeof o);
     if (g->nx < 3 || g->ny < 3 || g->nz < 3)
         return fail(SPFM_E_INVAL, "grid edges must be >= 3 (got %d x %d x %d)", g->nx, g->ny, g->nz);
-    if ((int64_t)g->nx * g->ny >= (int64_t)1 << 31 || (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40) ||
-        g->nz > 65535 || g->ny > 4 * 65535)
-        return fail(SPFM_E_INVAL, "grid too large (nx*ny < 2^31, ny <= 262140, nz <= 65535)");
     if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SPFM_E_INVAL, "dx must be > 0");
     if (!(lambda > 0.0) || !(Gamma > 0.0) || !(M > 0.0) || !std::isfinite(lambda) ||
         !std::isfinite(Gamma) || !std::isfinite(M))
@@ -65,11 +63,21 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     if (stencil != 6 && stencil != 18 && stencil != 26)
         return fail(SPFM_E_INVAL, "stencil must be 6, 18 or 26 (got %d)", stencil);
     if (o.dtype != SPFM_F32 && o.dtype != SPFM_F64) return fail(SPFM_E_INVAL, "unknown dtype %d", o.dtype);
+    // The tiled kernels address one z-plane through a buffer descriptor with
+    // 32-bit byte offsets.
+    const int64_t esize = o.dtype == SPFM_F64 ? 8 : 4;
+    if ((int64_t)g->nx * g->ny * esize >= (int64_t)1 << 31 ||
+        (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40) || g->nz > 65535 || g->ny > 4 * 65535)
+        return fail(SPFM_E_INVAL,
+                    "grid too large (nx*ny*element size < 2^31 bytes, ny <= 262140, nz <= 65535)");
     if (o.coupling != SPFM_LOCAL && o.coupling != SPFM_GLOBAL && o.coupling != SPFM_CF)
         return fail(SPFM_E_INVAL, "unknown coupling %d", o.coupling);
     if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_TILED)
         return fail(SPFM_E_INVAL, "unknown kernel %d", o.kernel);
     if (o.zchunk < 0 || o.zchunk > 4096) return fail(SPFM_E_INVAL, "zchunk must be in 0..4096");
+    if (o.tsteps < 0 || o.tsteps > 4) return fail(SPFM_E_INVAL, "tsteps must be in 0..4");
+    if (o.tsteps > 1 && (o.dtype != SPFM_F32 || o.kernel == SPFM_KERNEL_PLAIN))
+        return fail(SPFM_E_INVAL, "tsteps > 1 needs dtype F32 and the tiled kernel");
     const double un = std::sqrt(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2]);
     if (o.coupling == SPFM_GLOBAL && !(un > 0.0 && std::isfinite(un)))
         return fail(SPFM_E_INVAL, "GLOBAL coupling needs a nonzero direction u");
@@ -101,6 +109,7 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     r->dtype = o.dtype;
     r->kernel = o.kernel == SPFM_KERNEL_AUTO ? SPFM_KERNEL_TILED : o.kernel;
     r->allow_unstable = o.allow_unstable;
+    r->tsteps = o.tsteps > 1 ? o.tsteps : 1;
     r->dt_max = stable_dt(stencil, o.coupling, p.u, p.gamma, lambda, Gamma, M, mu, g->dx, p.C_Gamma);
     if (!o.allow_unstable && p.dt > r->dt_max)
         return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, r->dt_max);
@@ -234,6 +243,14 @@ struct spfm_ctx {
     bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
     bool tuned = false;
 
+    // Steps per launch of launch_unit.
+    int unit() const { return r.tsteps; }
+    // r.tsteps steps from buf[from] into buf[1 - from] in one launch.
+    hipError_t launch_unit(int from) {
+        if (r.tsteps == 1) return launch_one(from);
+        return launch_step_temporal((const float*)buf[from], (float*)buf[1 - from], kf, r.p.stencil,
+                                    r.p.coupling, r.tsteps, zlen, stream);
+    }
     hipError_t launch_one(int from) {
         const void* in = buf[from];
         void* out = buf[1 - from];
@@ -273,6 +290,8 @@ struct spfm_batch {
     std::vector<Tracker> track;
     GraphCache graphs;
 
+    int unit() const { return 1; }
+    hipError_t launch_unit(int from) { return launch_one(from); }
     hipError_t launch_one(int from) {
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
                                    stencil, coupling, stream);
@@ -313,7 +332,7 @@ spfm_status autotune(spfm_ctx* c) {
             hipError_t e = hipSuccess;
             for (int i = 0; i < 7 && e == hipSuccess; ++i) {
                 if (i == 2) e = hipEventRecord(e0, c->stream);
-                if (e == hipSuccess) e = c->launch_one(c->cur);
+                if (e == hipSuccess) e = c->launch_unit(c->cur);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -336,13 +355,15 @@ template <typename Obj>
 spfm_status run_steps(Obj* o, int64_t n) {
     if (n < 0) return fail(SPFM_E_INVAL, "negative step count");
     int64_t left = n;
-    if (o->stream != nullptr && n >= 2 * kGraphSteps) {
+    const int u = o->unit();   // steps per unit launch
+    const int64_t per_graph = (int64_t)kGraphSteps * u;
+    if (o->stream != nullptr && n >= 2 * per_graph) {
         for (int from = 0; from < 2; ++from) {
             if (o->graphs.exec[from]) continue;
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(o->stream, hipStreamCaptureModeRelaxed));
             hipError_t le = hipSuccess;
-            for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) le = o->launch_one((from + s) & 1);
+            for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) le = o->launch_unit((from + s) & 1);
             hipError_t ce = hipStreamEndCapture(o->stream, &g);
             if (le != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
@@ -356,17 +377,19 @@ spfm_status run_steps(Obj* o, int64_t n) {
                 return fail(SPFM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
             }
         }
-        while (left >= kGraphSteps) {
+        while (left >= per_graph) {
             HIP_TRY(hipGraphLaunch(o->graphs.exec[o->cur], o->stream));
-            left -= kGraphSteps;   // kGraphSteps is even: the current buffer is unchanged
-            o->nsteps += kGraphSteps;
+            left -= per_graph;   // kGraphSteps launches (even): the current buffer is unchanged
+            o->nsteps += per_graph;
         }
     }
-    for (; left > 0; --left) {
-        hipError_t e = o->launch_one(o->cur);
+    // Remaining steps: whole units, then single steps.
+    for (; left > 0; left -= (left >= u ? u : 1)) {
+        const bool whole = left >= u;
+        hipError_t e = whole ? o->launch_unit(o->cur) : o->launch_one(o->cur);
         if (e != hipSuccess) return fail(SPFM_E_HIP, "step launch: %s", hipGetErrorString(e));
         o->cur ^= 1;
-        o->nsteps += 1;
+        o->nsteps += whole ? u : 1;
     }
     return SPFM_OK;
 }
@@ -545,6 +568,7 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     o->dt_max = c->r.dt_max;
     o->stencil = p.stencil; o->coupling = p.coupling; o->dtype = c->r.dtype; o->kernel = c->r.kernel;
     o->zchunk = c->zlen;
+    o->tsteps = c->r.tsteps;
     return SPFM_OK;
 }
 
@@ -575,6 +599,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.d_phi[0] || o.d_phi[1]) return fail(SPFM_E_INVAL, "batches allocate their own buffers");
     if (o.C_Gamma > 0.0) return fail(SPFM_E_INVAL, "batches calibrate C_Gamma per grid");
     if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
+    if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
     spfm_batch* b = new (std::nothrow) spfm_batch;
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;

@@ -62,6 +62,27 @@ __device__ __forceinline__ double fast_rsqrt(double v) { return rsqrt(v); }
 __device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double fast_rcp(double v) { return 1.0 / v; }
 
+// Raw buffer access to one z-plane: the descriptor (base, size in bytes) lives
+// in scalar registers and every lane supplies a 32-bit byte offset, so no
+// 64-bit address arithmetic runs on the vector unit.  Dword 3 selects the
+// 32-bit data format that gfx9 raw buffer instructions expect.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, float*) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off, double*) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+
 // An empty statement with side effects: the compiler may not speculate the
 // block containing it, so a wave-uniform branch around that block stays a
 // branch instead of being turned into an unconditional computation and a select.
@@ -143,7 +164,16 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             T gx, gy, gz;
             grad(gx, gy, gz);
             T g2 = gx * gx + gy * gy + gz * gz;
-            if (!(g2 >= k.tau2)) { gx = T(1); gy = T(0); gz = T(0); g2 = T(1); }
+            // Fallback normal (1,0,0) where |grad psi'| is below tau; rare, so
+            // waves without such a lane skip the selects.
+            const bool flat = !(g2 >= k.tau2);
+            if (__ballot(flat) != 0) {
+                keep_branch();
+                gx = flat ? T(1) : gx;
+                gy = flat ? T(0) : gy;
+                gz = flat ? T(0) : gz;
+                g2 = flat ? T(1) : g2;
+            }
             const T sc = k.kap2 * fast_rsqrt(g2);
             const T ex = fast_exp2(sc * gx), ey = fast_exp2(sc * gy), ez = fast_exp2(sc * gz);
             const T r = fast_rcp(ex * ey * ez);
@@ -246,6 +276,9 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              int zlen, hipStream_t s);
+// TB = tsteps (2..4) steps per launch, FP32 (temporal.hip).
+hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<float>& k, int stencil,
+                                int coupling, int tsteps, int zlen, hipStream_t s);
 // Batched step: instance i reads buf_in + offset[i], writes buf_out + offset[i].
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
@@ -253,8 +286,12 @@ hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCo
 #ifndef SPFM_TILE_Y
 #define SPFM_TILE_Y 8
 #endif
+#ifndef SPFM_WAVE_X
+#define SPFM_WAVE_X 16
+#endif
 constexpr int kTileX = 64;
 constexpr int kTileY = SPFM_TILE_Y;
+constexpr int kWaveX = SPFM_WAVE_X;   // each wave computes a kWaveX x (64/kWaveX) patch
 constexpr int kTileZ = 32;   // default planes per block (the z-chunk is a launch argument)
 constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
 

@@ -72,66 +72,81 @@ template <typename T, int S, int C>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi) {
-    constexpr int HX = kTileX + 2, HY = kTileY + 2, HP = HX * HY;
+    // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
+    // wave computes a kWaveX x (64 / kWaveX) patch of the tile; LX = 80 puts the
+    // rows of a patch in distinct LDS banks.
+    constexpr int HX = kTileX + 2, HY = kTileY + 2, NC = HX * HY;
+    constexpr int LX = 80, HP = LX * HY;
     constexpr int NT = kTileX * kTileY;
-    static_assert(NT <= HP && HP <= 2 * NT, "the halo plane takes two load rounds");
+    constexpr int WX = kWaveX, WY = 64 / kWaveX;
+    static_assert(NT <= NC && NC <= 2 * NT, "the halo plane takes two load rounds");
+    static_assert(kTileX % WX == 0 && kTileY % WY == 0 && LX >= HX, "wave patches tile the block");
     const int tid = threadIdx.x;
-    const int tx = tid % kTileX, ty = tid / kTileX;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int tx = (wave % (kTileX / WX)) * WX + lane % WX;
+    const int ty = (wave / (kTileX / WX)) * WY + lane / WX;
     const int nx = k.nx, ny = k.ny, nz = k.nz;
     const size_t plane = (size_t)nx * ny;
+    const int plane_bytes = (int)(plane * sizeof(T));   // < 2^31, checked at create
 
-    // In-plane offsets of this thread's two halo cells (fixed along the sweep);
-    // the first always exists, the second only for tid + NT < HP.
-    int loff0, loff1;
+    // In-plane byte offsets (fixed along the sweep) and LDS positions of this
+    // thread's two halo cells; cells are numbered row by row so that loads are
+    // coalesced.  The first always exists, the second only for tid + NT < NC.
+    int loff0, loff1, soff0, soff1;
     {
         int gx = x0 - 1 + tid % HX, gy = y0 - 1 + tid / HX;
+        soff0 = (tid / HX) * LX + tid % HX;
         gx %= nx; if (gx < 0) gx += nx;
         gy %= ny; if (gy < 0) gy += ny;
-        loff0 = gy * nx + gx;
+        loff0 = (gy * nx + gx) * (int)sizeof(T);
         const int c1 = tid + NT;
+        soff1 = (c1 / HX) * LX + c1 % HX;
         gx = x0 - 1 + c1 % HX; gy = y0 - 1 + c1 / HX;
         gx %= nx; if (gx < 0) gx += nx;
         gy %= ny; if (gy < 0) gy += ny;
-        loff1 = c1 < HP ? gy * nx + gx : 0;
+        loff1 = c1 < NC ? (gy * nx + gx) * (int)sizeof(T) : 0;
     }
-    const bool has1 = tid + NT < HP;
+    const bool has1 = tid + NT < NC;
     const int nout = min(zlen, nz - z0);   // output planes z0 .. z0+nout-1
     const int last = nout + 1;             // relative index of the last plane needed
 
     struct Pair { T v0, v1; };
-    auto fetch_at = [&](const T* src, Pair& v) {
-        v.v0 = src[loff0];
-        v.v1 = src[loff1];   // loff1 = 0 (a valid address) where the cell does not exist
+    auto fetch_at = [&](__amdgpu_buffer_rsrc_t src, Pair& v) {
+        v.v0 = buf_load(src, loff0, (T*)nullptr);
+        v.v1 = buf_load(src, loff1, (T*)nullptr);   // loff1 = 0 where the cell does not exist
     };
     auto stage_slot = [&](int slot, const Pair& v) {
         T* dphi = sphi + slot * HP;
         T* dpsi = spsi + slot * HP;
-        dphi[tid] = v.v0;
-        if (C == kLocal) dpsi[tid] = psi2(v.v0, k.eps);
+        dphi[soff0] = v.v0;
+        if (C == kLocal) dpsi[soff0] = psi2(v.v0, k.eps);
         if (has1) {
-            dphi[tid + NT] = v.v1;
-            if (C == kLocal) dpsi[tid + NT] = psi2(v.v1, k.eps);
+            dphi[soff1] = v.v1;
+            if (C == kLocal) dpsi[soff1] = psi2(v.v1, k.eps);
         }
     };
-    const int cc = (ty + 1) * HX + (tx + 1);
+    // The 3 x 3 neighbourhood of this thread's point, from the corner cell b:
+    // every offset lies within 2 LX + 2 < 256 elements of b, so a slot needs one
+    // base address for all its paired LDS reads.
+    const int b = ty * LX + tx;
     auto load_slot = [&](int slot, PlaneRegs<T>& R) {
-        const T* P = sphi + slot * HP;
-        const T c = P[cc];
+        const T* P = sphi + slot * HP + b;
+        const T c = P[LX + 1];
         R.c = c;
-        R.fc = ((P[cc + 1] - c) + (P[cc - 1] - c)) + ((P[cc + HX] - c) + (P[cc - HX] - c));
+        R.fc = ((P[LX + 2] - c) + (P[LX] - c)) + ((P[2 * LX + 1] - c) + (P[1] - c));
         if (S >= 18)
-            R.dc = ((P[cc + HX + 1] - c) + (P[cc - HX - 1] - c)) +
-                   ((P[cc + HX - 1] - c) + (P[cc - HX + 1] - c));
+            R.dc = ((P[2 * LX + 2] - c) + (P[0] - c)) + ((P[2 * LX] - c) + (P[2] - c));
         if (C == kLocal) {
-            const T* Q = spsi + slot * HP;
-            R.gx = Q[cc + 1] - Q[cc - 1];
-            R.gy = Q[cc + HX] - Q[cc - HX];
-            R.pc = Q[cc];
+            const T* Q = spsi + slot * HP + b;
+            R.gx = Q[LX + 2] - Q[LX];
+            R.gy = Q[2 * LX + 1] - Q[1];
+            R.pc = Q[LX + 1];
         }
     };
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
-    T* const dst0 = out + (size_t)(y0 + ty) * nx + (x0 + tx);
-    auto point = [&](T* dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0, const PlaneRegs<T>& Rp) {
+    const int dst_off = ((y0 + ty) * nx + (x0 + tx)) * (int)sizeof(T);
+    auto point = [&](__amdgpu_buffer_rsrc_t dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
+                     const PlaneRegs<T>& Rp) {
         const T p = R0.c;
         const T e = (Rm.c - p) + (Rp.c - p);
         const T s1 = R0.fc + e;
@@ -144,9 +159,13 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             gz = Rp.pc - Rm.pc;
         };
         const T v = point_core<T, S, C>(p, s1, s2, s3, grad, k);
-        if (active) *dst = v;
+        if (active) buf_store(v, dst, dst_off);
     };
-    auto plane_ptr = [&](int r) { return in + (size_t)wrap_once(z0 - 1 + r, nz) * plane; };
+    // Descriptors of input plane r (relative numbering) and output plane z.
+    auto plane_in = [&](int r) {
+        return plane_rsrc(in + (size_t)wrap_once(z0 - 1 + r, nz) * plane, plane_bytes);
+    };
+    auto plane_out = [&](int z) { return plane_rsrc(out + (size_t)z * plane, plane_bytes); };
 
     // Iteration producing planes r, r+1 (slots: parity 0 reads 2, 3 and
     // writes 0, 1; parity 1 reads 0, 1 and writes 2, 3) with registers P0..P3
@@ -165,11 +184,10 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         if (!G || r + 2 <= last) load_slot(rd + 1, P3);
         if (!G || r + 3 <= last) stage_slot(wr, Q0);
         if (!G || r + 4 <= last) stage_slot(wr + 1, Q1);
-        if (!G || r + 7 <= last) fetch_at(plane_ptr(r + 7), Q0);
-        if (!G || r + 8 <= last) fetch_at(plane_ptr(r + 8), Q1);
-        T* dst = dst0 + (size_t)(z0 - 1 + r) * plane;
-        if (!G || r <= nout) point(dst, P0, P1, P2);
-        if (!G || r + 1 <= nout) point(dst + plane, P1, P2, P3);
+        if (!G || r + 7 <= last) fetch_at(plane_in(r + 7), Q0);
+        if (!G || r + 8 <= last) fetch_at(plane_in(r + 8), Q1);
+        if (!G || r <= nout) point(plane_out(z0 - 1 + r), P0, P1, P2);
+        if (!G || r + 1 <= nout) point(plane_out(z0 + r), P1, P2, P3);
     };
     using P0t = std::integral_constant<int, 0>;
     using P1t = std::integral_constant<int, 1>;
@@ -184,11 +202,11 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         Pair v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (r <= last) fetch_at(plane_ptr(r), v[r]);
-        if (4 <= last) fetch_at(plane_ptr(4), qa0);
-        if (5 <= last) fetch_at(plane_ptr(5), qa1);
-        if (6 <= last) fetch_at(plane_ptr(6), qb0);
-        if (7 <= last) fetch_at(plane_ptr(7), qb1);
+            if (r <= last) fetch_at(plane_in(r), v[r]);
+        if (4 <= last) fetch_at(plane_in(4), qa0);
+        if (5 <= last) fetch_at(plane_in(5), qa1);
+        if (6 <= last) fetch_at(plane_in(6), qb0);
+        if (7 <= last) fetch_at(plane_in(7), qb1);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (r <= last) stage_slot(r, v[r]);
@@ -213,11 +231,11 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
 
 template <typename T>
 struct Smem {
-    static constexpr int HP = (kTileX + 2) * (kTileY + 2);
+    static constexpr int HP = 80 * (kTileY + 2);   // LDS row stride 80 (see tile_sweep)
 };
 
 #ifndef SPFM_WAVES_F32
-#define SPFM_WAVES_F32 8
+#define SPFM_WAVES_F32 6
 #endif
 // Waves per SIMD the tiled kernels are compiled for: FP32 fits its working set
 // in 64 VGPRs (8 waves); FP64 needs about twice as many registers.

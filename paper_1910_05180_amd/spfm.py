@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("eps", ctypes.c_double), ("tau", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("d_phi", ctypes.c_void_p * 2),
                 ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -59,7 +59,7 @@ class Info(ctypes.Structure):
                [("gamma", ctypes.c_double * 3), ("dt_max", ctypes.c_double),
                 ("stencil", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32)]
 
 
 class SpfmError(RuntimeError):
@@ -145,7 +145,7 @@ def _stream_handle(stream):
 
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
-             allow_unstable=False, zchunk=0) -> Options:
+             allow_unstable=False, zchunk=0, tsteps=0) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -159,6 +159,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.allow_unstable = 1 if allow_unstable else 0
     o.zchunk = int(zchunk)
+    o.tsteps = int(tsteps)
     return o
 
 

@@ -39,6 +39,8 @@ def test_exports_every_declared_symbol(S):
     (dict(coupling="global", u=(0, 0, 0)), -1), (dict(lam=0.25), -1),
     (dict(dt=1.0), -4), (dict(dt=1.0, lam=1.0, stencil=6), -4),
     (dict(mu=float("nan")), -1), (dict(kernel=7), -1),
+    (dict(tsteps=5), -1), (dict(tsteps=-1), -1), (dict(tsteps=2, dtype="f64"), -1),
+    (dict(tsteps=2, kernel="plain"), -1),
 ])
 def test_create_rejects_bad_arguments_before_any_hip_call(S, kw, status):
     st, msg = S.try_create((16, 16, 16), **kw)
@@ -72,3 +74,11 @@ def test_stable_dt_matches_oracle(S, orc, stencil, coupling, lam, mu, u):
     ref = orc.stable_dt(p)
     got = S.stable_dt(stencil, coupling, u, None, lam, 1.0, 1.0, mu, 1.0, p.C_Gamma)
     assert abs(got / ref - 1) < 1e-5
+
+
+def test_create_rejects_planes_beyond_32_bit_byte_offsets(S):
+    # one z-plane must stay below 2^31 bytes: 2^29 FP32 or 2^28 FP64 points
+    st, msg = S.try_create((3, 16384, 32768))
+    assert st == -1 and "2^31" in msg
+    st, msg = S.try_create((3, 16384, 16384), dtype="f64")
+    assert st == -1 and "2^31" in msg
