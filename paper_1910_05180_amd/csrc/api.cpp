@@ -301,11 +301,12 @@ struct spfm_batch {
 namespace {
 
 // Planes per block: the longest z-chunk (at most kTileZ) that still gives at
-// least 2048 blocks, i.e. two full rounds of 512-thread blocks on 256 CUs.
-int default_zlen(int nx, int ny, int nz) {
-    const int64_t cols = (int64_t)((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+// least 2^20 threads (two full rounds of 512-thread blocks on 256 CUs) for
+// tiles tx x kTileY.
+int default_zlen(int nx, int ny, int nz, int tx) {
+    const int64_t cols = (int64_t)((nx + tx - 1) / tx) * ((ny + kTileY - 1) / kTileY);
     int z = kTileZ;
-    while (z > 8 && cols * ((nz + z - 1) / z) < 2048) z /= 2;
+    while (z > 8 && cols * ((nz + z - 1) / z) * tx * kTileY < ((int64_t)1 << 20)) z /= 2;
     return z;
 }
 
@@ -424,7 +425,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     c->r = r;
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
-    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.p.nx, r.p.ny, r.p.nz);
+    const int tx = r.tsteps > 1 ? 64 : tile_x(r.dtype == SPFM_F32, r.p.coupling);   // temporal: 64 x 8
+    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.p.nx, r.p.ny, r.p.nz, tx);
     const size_t bytes = c->bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
@@ -627,12 +629,14 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         const int64_t np = (int64_t)p.nx * p.ny * p.nz;
         b->points += np;
         off += (np + 63) / 64 * 64;   // keep every grid 256-byte aligned
+        const int tx = tile_x(true, o.coupling);
         for (int z0 = 0; z0 < p.nz; z0 += kTileZ)
             for (int y0 = 0; y0 < p.ny; y0 += kTileY)
-                for (int x0 = 0; x0 < p.nx; x0 += kTileX) items.push_back(TileItem{i, x0, y0, z0, kTileZ});
+                for (int x0 = 0; x0 < p.nx; x0 += tx) items.push_back(TileItem{i, x0, y0, z0, kTileZ});
     }
     if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
-    {   // dispatch order: each XCD gets a contiguous run of tiles (see xcd_remap)
+    {   // dispatch order: each XCD gets a contiguous run of tiles (see xcd_remap); the
+        // slabs of a batch spread their interfaces evenly, so no dealing is needed
         std::vector<TileItem> order(items.size());
         const int nt = (int)items.size();
         for (int s = 0; s < nt; ++s) order[s] = items[xcd_remap(s, nt)];

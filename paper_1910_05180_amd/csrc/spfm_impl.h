@@ -283,15 +283,18 @@ hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<floa
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
                                int stencil, int coupling, hipStream_t s);
-#ifndef SPFM_TILE_Y
-#define SPFM_TILE_Y 8
-#endif
-#ifndef SPFM_WAVE_X
-#define SPFM_WAVE_X 16
-#endif
-constexpr int kTileX = 64;
-constexpr int kTileY = SPFM_TILE_Y;
-constexpr int kWaveX = SPFM_WAVE_X;   // each wave computes a kWaveX x (64/kWaveX) patch
+// Tiles of the single-step tiled kernels: a block marches one tile column
+// kTileX x kTileY along z, each of its waves computing a 16 x 4 patch.  FP32
+// TI_n uses 16 x 8 columns (two waves): its full-coupling branch makes the
+// work of a wave uneven from plane to plane, and a block of few waves loses
+// little at its barriers while the SIMD runs waves of other blocks.  The other
+// kernels use 64 x 8 columns (eight waves), whose halo is relatively smaller.
+constexpr int tile_x(bool f32, int coupling) { return f32 && coupling == kLocal ? 16 : 64; }
+constexpr int kTileY = 8;
+constexpr int kWaveX = 16;
+// LDS row stride of a staged halo plane: 80 for 64-wide tiles puts the four
+// rows of a 16 x 4 wave patch in distinct LDS banks.
+constexpr int lds_row(int tx) { return tx == 64 ? 80 : tx + 2; }
 constexpr int kTileZ = 32;   // default planes per block (the z-chunk is a launch argument)
 constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
 
@@ -302,6 +305,20 @@ __host__ __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int q = n / kNumXcd, r = n % kNumXcd;
     const int k = b % kNumXcd, i = b / kNumXcd;
     return k < r ? k * (q + 1) + i : r * (q + 1) + (k - r) * q + i;
+}
+
+// Dispatch slot b -> logical tile with the tiles dealt to the XCDs in runs of
+// `run` consecutive tiles, round robin: XCD k processes runs k, k + 8, ... in
+// order.  Each run keeps its halo sharing inside one L2, and work that is
+// concentrated in space (an interface) is spread over all XCDs.  The last
+// incomplete round falls back to xcd_remap; run <= 0 selects xcd_remap for all.
+__host__ __device__ __forceinline__ int xcd_deal(int b, int n, int run) {
+    if (run <= 0) return xcd_remap(b, n);
+    const int round = kNumXcd * run;
+    const int full = (n / round) * round;
+    if (b >= full) return full + xcd_remap(b - full, n - full);
+    const int k = b % kNumXcd, i = b / kNumXcd;
+    return ((i / run) * kNumXcd + k) * run + i % run;
 }
 
 struct ReduceOut {   // device result of the diagnostics reduction

@@ -54,7 +54,7 @@ struct PlaneRegs {
     T pc;       // LOCAL: psi' at the column
 };
 
-// One block sweeps the tile [x0, x0+kTileX) x [y0, y0+kTileY) x [z0, z0+zlen)
+// One block sweeps the tile [x0, x0+TX) x [y0, y0+kTileY) x [z0, z0+zlen)
 // (clipped to the grid).  Each plane of the tile plus a one-cell halo is read
 // from global memory once (coalesced rows) two iterations before it is staged
 // into a four-slot LDS ring, together with psi' of every cell for TI_n.  Every
@@ -73,18 +73,18 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi) {
     // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
-    // wave computes a kWaveX x (64 / kWaveX) patch of the tile; LX = 80 puts the
-    // rows of a patch in distinct LDS banks.
-    constexpr int HX = kTileX + 2, HY = kTileY + 2, NC = HX * HY;
-    constexpr int LX = 80, HP = LX * HY;
-    constexpr int NT = kTileX * kTileY;
+    // wave computes a kWaveX x (64 / kWaveX) patch of the tile.
+    constexpr int TX = tile_x(sizeof(T) == 4, C);
+    constexpr int HX = TX + 2, HY = kTileY + 2, NC = HX * HY;
+    constexpr int LX = lds_row(TX), HP = LX * HY;
+    constexpr int NT = TX * kTileY;
     constexpr int WX = kWaveX, WY = 64 / kWaveX;
     static_assert(NT <= NC && NC <= 2 * NT, "the halo plane takes two load rounds");
-    static_assert(kTileX % WX == 0 && kTileY % WY == 0 && LX >= HX, "wave patches tile the block");
+    static_assert(TX % WX == 0 && kTileY % WY == 0 && LX >= HX, "wave patches tile the block");
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int tx = (wave % (kTileX / WX)) * WX + lane % WX;
-    const int ty = (wave / (kTileX / WX)) * WY + lane / WX;
+    const int tx = (wave % (TX / WX)) * WX + lane % WX;
+    const int ty = (wave / (TX / WX)) * WY + lane / WX;
     const int nx = k.nx, ny = k.ny, nz = k.nz;
     const size_t plane = (size_t)nx * ny;
     const int plane_bytes = (int)(plane * sizeof(T));   // < 2^31, checked at create
@@ -229,9 +229,11 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     }
 }
 
-template <typename T>
+template <typename T, int C>
 struct Smem {
-    static constexpr int HP = 80 * (kTileY + 2);   // LDS row stride 80 (see tile_sweep)
+    static constexpr int TX = tile_x(sizeof(T) == 4, C);
+    static constexpr int NT = TX * kTileY;                    // threads per block
+    static constexpr int HP = lds_row(TX) * (kTileY + 2);     // one staged plane
 };
 
 #ifndef SPFM_WAVES_F32
@@ -245,24 +247,24 @@ struct WavesPerSimd {
 };
 
 template <typename T, int S, int C>
-__global__ __launch_bounds__(kTileX* kTileY, WavesPerSimd<T>::value) void k_step_tiled(const T* __restrict__ in,
+__global__ __launch_bounds__((Smem<T, C>::NT), WavesPerSimd<T>::value) void k_step_tiled(const T* __restrict__ in,
                                                                T* __restrict__ out, StepCoef<T> k,
                                                                int ntx, int nty, int ntiles,
-                                                               int zlen) {
-    __shared__ T sphi[4 * Smem<T>::HP];
-    __shared__ T spsi[C == kLocal ? 4 * Smem<T>::HP : 1];
-    const int t = xcd_remap(blockIdx.x, ntiles);
+                                                               int zlen, int run) {
+    __shared__ T sphi[4 * Smem<T, C>::HP];
+    __shared__ T spsi[C == kLocal ? 4 * Smem<T, C>::HP : 1];
+    const int t = xcd_deal(blockIdx.x, ntiles, run);
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    tile_sweep<T, S, C>(in, out, k, tx * kTileX, ty * kTileY, tz * zlen, zlen, sphi, spsi);
+    tile_sweep<T, S, C>(in, out, k, tx * Smem<T, C>::TX, ty * kTileY, tz * zlen, zlen, sphi, spsi);
 }
 
 template <int S, int C>
-__global__ __launch_bounds__(kTileX* kTileY, WavesPerSimd<float>::value) void k_step_batched(
+__global__ __launch_bounds__((Smem<float, C>::NT), WavesPerSimd<float>::value) void k_step_batched(
     const float* __restrict__ buf_in, float* __restrict__ buf_out,
     const StepCoef<float>* __restrict__ coef, const int64_t* __restrict__ offset,
     const TileItem* __restrict__ items) {
-    __shared__ float sphi[4 * Smem<float>::HP];
-    __shared__ float spsi[C == kLocal ? 4 * Smem<float>::HP : 1];
+    __shared__ float sphi[4 * Smem<float, C>::HP];
+    __shared__ float spsi[C == kLocal ? 4 * Smem<float, C>::HP : 1];
     const TileItem it = items[blockIdx.x];
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
@@ -297,12 +299,14 @@ template <typename T, int S, int C>
 struct TiledLaunch {
     static hipError_t run(const T* in, T* out, const StepCoef<T>& k, int zlen, hipStream_t s) {
         if (zlen < 1) return hipErrorInvalidValue;
-        const int ntx = (k.nx + kTileX - 1) / kTileX, nty = (k.ny + kTileY - 1) / kTileY;
+        constexpr int TX = Smem<T, C>::TX;
+        const int ntx = (k.nx + TX - 1) / TX, nty = (k.ny + kTileY - 1) / kTileY;
         const int ntz = (k.nz + zlen - 1) / zlen;
         const int64_t n = (int64_t)ntx * nty * ntz;
         if (n > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)n), dim3(kTileX * kTileY), 0, s,
-                           in, out, k, ntx, nty, (int)n, zlen);
+        // One row of tiles per run: every XCD gets every eighth row.
+        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)n), dim3(Smem<T, C>::NT), 0, s,
+                           in, out, k, ntx, nty, (int)n, zlen, ntx);
         return hipGetLastError();
     }
 };
@@ -312,7 +316,7 @@ struct BatchedLaunch {
     static hipError_t run(const float* in, float* out, const StepCoef<float>* coef,
                           const int64_t* offset, const TileItem* items, int nitems, hipStream_t s) {
         if (nitems <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_step_batched<S, C>), dim3(nitems), dim3(kTileX * kTileY), 0, s, in,
+        hipLaunchKernelGGL((k_step_batched<S, C>), dim3(nitems), dim3(Smem<float, C>::NT), 0, s, in,
                            out, coef, offset, items);
         return hipGetLastError();
     }

@@ -30,10 +30,13 @@ namespace spfm {
 
 namespace {
 
+// Output tile of the temporally blocked kernel (one 512-thread block).
+constexpr int kTTileX = 64, kTTileY = 8;
+
 template <int TB>
 struct TLevels {
-    static constexpr int W(int l) { return kTileX + 2 * (TB - l); }
-    static constexpr int H(int l) { return kTileY + 2 * (TB - l); }
+    static constexpr int W(int l) { return kTTileX + 2 * (TB - l); }
+    static constexpr int H(int l) { return kTTileY + 2 * (TB - l); }
     static constexpr int N(int l) { return W(l) * H(l); }
     // Start of level l's four-plane ring in the LDS arrays (levels 0..TB-1).
     static constexpr int ring(int l) {
@@ -42,7 +45,7 @@ struct TLevels {
         return o;
     }
     static constexpr int total = ring(TB);
-    static constexpr int R0 = (N(0) + kTileX * kTileY - 1) / (kTileX * kTileY);   // staged cells per thread
+    static constexpr int R0 = (N(0) + kTTileX * kTTileY - 1) / (kTTileX * kTTileY);   // staged cells per thread
 };
 
 __device__ __forceinline__ int wrap_mod(int i, int n) {
@@ -51,18 +54,18 @@ __device__ __forceinline__ int wrap_mod(int i, int n) {
 }
 
 template <int TB, int S, int C>
-__global__ __launch_bounds__(kTileX* kTileY) void k_step_temporal(const float* __restrict__ in,
+__global__ __launch_bounds__(kTTileX* kTTileY) void k_step_temporal(const float* __restrict__ in,
                                                                    float* __restrict__ out,
                                                                    StepCoef<float> k, int ntx, int nty,
                                                                    int ntiles, int zlen) {
     using L = TLevels<TB>;
-    constexpr int NT = kTileX * kTileY;
+    constexpr int NT = kTTileX * kTTileY;
     constexpr int R0 = L::R0;
     __shared__ float sphi[L::total];
     __shared__ float spsi[C == kLocal ? L::total : 1];
 
     const int t = xcd_remap(blockIdx.x, ntiles);
-    const int x0 = (t % ntx) * kTileX, y0 = ((t / ntx) % nty) * kTileY, z0 = (t / (ntx * nty)) * zlen;
+    const int x0 = (t % ntx) * kTTileX, y0 = ((t / ntx) % nty) * kTTileY, z0 = (t / (ntx * nty)) * zlen;
     const int nx = k.nx, ny = k.ny, nz = k.nz;
     const size_t plane = (size_t)nx * ny;
     const int plane_bytes = (int)(plane * sizeof(float));   // < 2^31, checked at create
@@ -170,11 +173,11 @@ __global__ __launch_bounds__(kTileX* kTileY) void k_step_temporal(const float* _
 
 template <int TB, int S, int C>
 hipError_t run_temporal(const float* in, float* out, const StepCoef<float>& k, int zlen, hipStream_t s) {
-    const int ntx = (k.nx + kTileX - 1) / kTileX, nty = (k.ny + kTileY - 1) / kTileY;
+    const int ntx = (k.nx + kTTileX - 1) / kTTileX, nty = (k.ny + kTTileY - 1) / kTTileY;
     const int ntz = (k.nz + zlen - 1) / zlen;
     const int64_t n = (int64_t)ntx * nty * ntz;
     if (n > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step_temporal<TB, S, C>), dim3((unsigned)n), dim3(kTileX * kTileY), 0, s, in,
+    hipLaunchKernelGGL((k_step_temporal<TB, S, C>), dim3((unsigned)n), dim3(kTTileX * kTTileY), 0, s, in,
                        out, k, ntx, nty, (int)n, zlen);
     return hipGetLastError();
 }
