@@ -36,7 +36,7 @@ ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..6
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the factors the same counters give for the copy
 # reference; None whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = None
+TRAFFIC_BYTES_LOCAL26 = (43340.0 * 2.0 + 70743.9) * 1024
 
 
 def parse():
@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
                     help="run only this leg: f32 | f64 | batch | grains | temporal")
     ap.add_argument("--side-steps", type=int, default=200,
