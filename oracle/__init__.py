@@ -82,6 +82,13 @@ def lib():
             L.orc_spheres_at.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
                                                               ctypes.c_int, dp, dp, ctypes.c_long,
                                                               ctypes.POINTER(ctypes.c_int), dp]
+            L.orc_wall_value.argtypes = [ctypes.c_double, ctypes.c_double]
+            L.orc_wall_value.restype = ctypes.c_double
+            L.orc_fill_walls.argtypes = [pp, ctypes.c_int, dp, dp]
+            L.orc_step_walls.argtypes = [pp, ctypes.c_int, dp, dp, ctypes.c_long]
+            L.orc_step_walls.restype = ctypes.c_int
+            L.orc_init_front.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, dp,
+                                                              ctypes.c_double, dp]
             L.orc_num_threads.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -235,6 +242,86 @@ def cone_step(p: Params, shape, field_at, centres_xyz, nsteps: int) -> np.ndarra
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Walls with a contact angle (Sec. 2.4, Eq. 7).  A walled axis d (bit d of
+# `walls`) has one ghost layer at each end; sin_alpha[2d] and [2d+1] belong to
+# the low and high face of axis d and are n . e of the front normal n the wall
+# imposes, e the outward normal of the face.
+# ---------------------------------------------------------------------------
+def wall_value(phi_in: float, a: float) -> float:
+    return lib().orc_wall_value(float(phi_in), float(a))
+
+
+def front(shape, n, offset=0.0, *, dx=1.0, lam=4.0) -> np.ndarray:
+    """Single planar front of Eq. 3 with normal n (into phase 0) through the box
+    centre shifted by offset along n, on the points of `shape`."""
+    nz, ny, nx = shape
+    out = np.empty(shape, dtype=np.float64)
+    nv = np.ascontiguousarray(n, dtype=np.float64)
+    lib().orc_init_front(nx, ny, nz, dx, lam, _dp(nv), float(offset), _dp(out))
+    return out
+
+
+def front_sin_alpha(n):
+    """The six face values that hold a planar front of normal n exactly."""
+    v = np.asarray(n, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    return [-v[0], v[0], -v[1], v[1], -v[2], v[2]]
+
+
+def padded_shape(shape, walls: int):
+    nz, ny, nx = shape
+    return (nz + 2 * ((walls >> 2) & 1), ny + 2 * ((walls >> 1) & 1), nx + 2 * (walls & 1))
+
+
+def interior(phi_padded: np.ndarray, walls: int) -> np.ndarray:
+    gz, gy, gx = (walls >> 2) & 1, (walls >> 1) & 1, walls & 1
+    nz, ny, nx = phi_padded.shape
+    return phi_padded[gz:nz - gz, gy:ny - gy, gx:nx - gx]
+
+
+def pad(phi: np.ndarray, walls: int) -> np.ndarray:
+    """Copy of phi with zero ghost layers on the walled axes."""
+    out = np.zeros(padded_shape(phi.shape, walls))
+    interior(out, walls)[...] = phi
+    return out
+
+
+def _padded_params(p: Params, walls: int) -> Params:
+    q = Params()
+    ctypes.memmove(ctypes.byref(q), ctypes.byref(p), ctypes.sizeof(Params))
+    q.nz, q.ny, q.nx = padded_shape((p.nz, p.ny, p.nx), walls)
+    return q
+
+
+def fill_walls(p: Params, phi_padded: np.ndarray, walls: int, sin_alpha) -> np.ndarray:
+    """Fill the ghost layers of phi_padded in place; p holds the interior shape."""
+    q = _padded_params(p, walls)
+    _check(q, phi_padded)
+    sa = np.ascontiguousarray(sin_alpha, dtype=np.float64)
+    lib().orc_fill_walls(ctypes.byref(q), int(walls), _dp(sa), _dp(phi_padded))
+    return phi_padded
+
+
+def step_walls(p: Params, phi: np.ndarray, walls: int, sin_alpha, nsteps: int,
+               padded: bool = False) -> np.ndarray:
+    """nsteps forward-Euler steps of the interior field phi (shape of p) between
+    contact-angle walls; returns the interior (or the filled padded field)."""
+    q = _padded_params(p, walls)
+    work = pad(np.asarray(phi, dtype=np.float64), walls)
+    sa = np.ascontiguousarray(sin_alpha, dtype=np.float64)
+    if lib().orc_step_walls(ctypes.byref(q), int(walls), _dp(sa), _dp(work), int(nsteps)) != 0:
+        raise MemoryError("oracle step allocation failed")
+    return work if padded else interior(work, walls).copy()
+
+
+def rate_walls(p: Params, phi: np.ndarray, walls: int, sin_alpha) -> np.ndarray:
+    """d phi / dt of Eq. 2 at the interior points, with the walls filled."""
+    q = _padded_params(p, walls)
+    work = fill_walls(p, pad(np.asarray(phi, dtype=np.float64), walls), walls, sin_alpha)
+    return interior(rate(q, work), walls).copy()
 
 
 # ---------------------------------------------------------------------------

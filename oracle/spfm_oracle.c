@@ -459,6 +459,78 @@ void orc_spheres_at(int nx, int ny, int nz, double dx, double lambda, int n,
     }
 }
 
+/* ---- Walls with a contact angle (Sec. 2.4, Eq. 7) ----
+ * A walled axis carries one ghost layer at each end: the padded field has
+ * nx + 2 (ny + 2, nz + 2) points along a walled axis, interior index i at
+ * padded index i + 1.  Eq. 7 sets a ghost point b from its inward neighbour
+ * b + r by the tanh addition law of the ideal profile (Eq. 3), shifting the
+ * profile by |r| sin(alpha): phi_b = (1 - a) phi_{b+r} / (1 - a (2 phi_{b+r} - 1)),
+ * a = tanh(2 |r| sin(alpha) / lambda).  For a planar front of normal n (into
+ * phi = 0) the exact ghost value needs sin(alpha) = n . e, e the outward
+ * normal of the wall: that is the meaning of sin_alpha[] below. */
+double orc_wall_value(double phi_in, double a) {
+    return (1.0 - a) * phi_in / (1.0 - a * (2.0 * phi_in - 1.0));
+}
+
+/* Reading: the paper states Eq. 7 for a face.  Edge and corner ghosts (needed
+ * by the 18- and 26-neighbour stencils) are filled by applying Eq. 7 axis after
+ * axis, x, then y, then z, each fill spanning the whole padded extent of the
+ * other axes: a corner ghost is the interior value shifted by the sum of the
+ * shifts of its walls, exact for the ideal front. */
+void orc_fill_walls(const orc_params *p, int walls, const double sin_alpha[6], double *phi) {
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int d = 0; d < 3; ++d) {
+        if (!(walls & (1 << d))) continue;
+        const double a_lo = tanh(2.0 * p->dx * sin_alpha[2 * d] / p->lambda);
+        const double a_hi = tanh(2.0 * p->dx * sin_alpha[2 * d + 1] / p->lambda);
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int j = 0; j < n[d1]; ++j)
+            for (int k = 0; k < n[d2]; ++k) {
+                int c[3];
+                c[d1] = j;
+                c[d2] = k;
+                c[d] = 1;
+                const double in_lo = phi[lin(p, c[0], c[1], c[2])];
+                c[d] = 0;
+                phi[lin(p, c[0], c[1], c[2])] = orc_wall_value(in_lo, a_lo);
+                c[d] = n[d] - 2;
+                const double in_hi = phi[lin(p, c[0], c[1], c[2])];
+                c[d] = n[d] - 1;
+                phi[lin(p, c[0], c[1], c[2])] = orc_wall_value(in_hi, a_hi);
+            }
+    }
+}
+
+/* nsteps of: fill the walls of the padded field, then one forward-Euler step
+ * of every point (the ghost values it produces are overwritten by the next
+ * fill).  p holds the padded dimensions. */
+int orc_step_walls(const orc_params *p, int walls, const double sin_alpha[6], double *phi,
+                   long nsteps) {
+    for (long s = 0; s < nsteps; ++s) {
+        orc_fill_walls(p, walls, sin_alpha, phi);
+        if (orc_step(p, phi, 1) != 0) return -1;
+    }
+    orc_fill_walls(p, walls, sin_alpha, phi);
+    return 0;
+}
+
+/* One planar front of Eq. 3, phi = (1 - tanh(2 s / lambda)) / 2 with
+ * s = dx (x, y, z) . n/|n| - c and c = the box centre (nx, ny, nz) dx / 2
+ * projected on n/|n|, plus offset: phase 1 behind the front, n into phase 0. */
+void orc_init_front(int nx, int ny, int nz, double dx, double lambda, const double n[3],
+                    double offset, double *phi) {
+    double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double nv[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
+    double c = 0.5 * dx * (nx * nv[0] + ny * nv[1] + nz * nv[2]) + offset;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double s = dx * (x * nv[0] + y * nv[1] + z * nv[2]) - c;
+                phi[((long)z * ny + y) * nx + x] = 0.5 * (1.0 - tanh(2.0 * s / lambda));
+            }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

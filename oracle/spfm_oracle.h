@@ -73,6 +73,19 @@ void orc_spheres_at(int nx, int ny, int nz, double dx, double lambda, int n,
                     const double *centers, const double *radii, long npts, const int *xyz,
                     double *out);
 /* Threads the oracle runs on. */
+/* Eq. 7 for one ghost point: the ideal profile through phi_in shifted by the
+ * length whose tanh(2 shift / lambda) is a. */
+double orc_wall_value(double phi_in, double a);
+/* Fill the ghost layers of a padded field; p holds the padded dimensions,
+ * walls bit d marks axis d walled, sin_alpha[2d], [2d+1] are the low and high
+ * faces of axis d (n . e_outward of the imposed front normal). */
+void orc_fill_walls(const orc_params *p, int walls, const double sin_alpha[6], double *phi);
+/* nsteps of (fill, forward-Euler step) on a padded field, then a final fill. */
+int orc_step_walls(const orc_params *p, int walls, const double sin_alpha[6], double *phi,
+                   long nsteps);
+/* Single planar front of Eq. 3 (not periodic). */
+void orc_init_front(int nx, int ny, int nz, double dx, double lambda, const double n[3],
+                    double offset, double *phi);
 int orc_num_threads(void);
 
 #ifdef __cplusplus
