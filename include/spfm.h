@@ -16,7 +16,10 @@
  * fixed direction (TI_<hkl> model) or the locally measured interface normal
  * (TI_n model, Tab. 2); the continuum-field model (CF, potential
  * 8 phi^2 (1-phi)^2 / 3 per direction) is available as a control.
- * Time integration is forward Euler; the grid is periodic on all faces.
+ * Time integration is forward Euler; the grid is periodic on every axis that
+ * has no walls.  Walls (Sec. 2.4) hold a contact angle by Eq. 7: one ghost
+ * layer beyond each walled end takes, before every step, the value of its
+ * inward neighbour moved along the ideal profile by dx sin(alpha).
  *
  * Conventions.
  *   Field layout: phi[(z*ny + y)*nx + x], x fastest, dtype float or double.
@@ -86,8 +89,9 @@ typedef struct {
                            selects 1e-30 (F32) or 1e-300 (F64) */
     double tau;         /* |grad psi| below tau -> normal (1,0,0); <= 0 selects 1e-3 */
     void *stream;       /* hipStream_t to order work on; NULL = the null stream */
-    void *d_phi[2];     /* optional caller-owned device ping-pong buffers of
-                           nx*ny*nz elements of dtype; both NULL = library allocates */
+    void *d_phi[2];     /* optional caller-owned device ping-pong buffers of the stored
+                           field, (nx+2wx)*(ny+2wy)*(nz+2wz) elements of dtype with wd = 1
+                           for a walled axis, else 0; both NULL = library allocates */
     int32_t kernel;     /* spfm_kernel */
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
@@ -96,6 +100,13 @@ typedef struct {
                            none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
                            equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
                            n / tsteps fused launches and n % tsteps single steps */
+    int32_t walls;      /* bit d (d = 0, 1, 2 for x, y, z): contact-angle walls at both ends of
+                           axis d instead of periodic wrap (not with tsteps > 1, not in batches) */
+    double wall_sin[6]; /* faces -x, +x, -y, +y, -z, +z: sin(alpha) of Eq. 7, in [-1, 1]: a ghost
+                           is its inward neighbour moved by dx sin(alpha) along the profile
+                           coordinate (towards phi = 0 for > 0).  A planar front of normal n
+                           (into phi = 0) is held exactly by sin(alpha) = n . e, e the outward
+                           normal of the face.  Unused for unwalled axes */
 } spfm_options;
 
 typedef struct {
@@ -122,17 +133,20 @@ typedef struct {
     int32_t zchunk;            /* planes per block of the tiled kernel (chosen by timing
                                   at the first spfm_step when kernel is AUTO) */
     int32_t tsteps;            /* steps per fused launch (1 = no temporal blocking) */
+    int32_t walls;             /* walled axes (bit mask) */
 } spfm_info;
 
 typedef struct spfm_ctx spfm_ctx;
 typedef struct spfm_batch spfm_batch;
 
-/* Create a context for one periodic grid (Sec. 2.1 statement of the problem).
+/* Create a context for one grid (Sec. 2.1 statement of the problem).
  * lambda: interface width (Eq. 3), Gamma: interface energy, M: kinetic
  * coefficient, mu: driving force (Eq. 1-2); stencil: 6, 18 or 26.
  * Returns SPFM_E_INVAL for non-positive lambda, Gamma, M or dx, an unknown
  * stencil, coupling or dtype, a grid edge below 3, a grid too large (one
- * z-plane of 2^31 bytes or more, ny > 262140 or nz > 65535), a zero GLOBAL direction,
+ * stored z-plane of 2^31 bytes or more, ny > 262140 or nz > 65535), a walls mask
+ * outside 0..7 or |wall_sin| > 1 on a walled axis, walls with tsteps > 1,
+ * a zero GLOBAL direction,
  * F32 with lambda < 0.3 dx, or exactly one of d_phi given;
  * SPFM_E_UNSTABLE when dt exceeds the explicit bound (unless allow_unstable).
  * Argument checks happen before any HIP call.  The field is zero until set. */
@@ -141,12 +155,15 @@ spfm_status spfm_create(const spfm_grid *grid, double lambda, double Gamma, doub
 /* Free the context and the buffers it allocated.  NULL is a no-op. */
 void spfm_destroy(spfm_ctx *ctx);
 
-/* Copy nx*ny*nz values of the context dtype into the current field.  Resets
- * the step counter and the interface reference (position becomes NaN). */
+/* Copy nx*ny*nz values of the context dtype into the current field (the
+ * grid points; with walls, the interior of the stored field).  Resets the step
+ * counter and the interface reference (position becomes NaN). */
 spfm_status spfm_set_field(spfm_ctx *ctx, const void *src, int src_on_device);
-/* Copy the current field out (synchronises when dst is host memory). */
+/* Copy the nx*ny*nz grid values out (synchronises when dst is host memory). */
 spfm_status spfm_get_field(spfm_ctx *ctx, void *dst, int dst_on_device);
-/* Device pointer of the current field (valid until the next spfm_step). */
+/* Device pointer of the current stored field (valid until the next spfm_step):
+ * with walls it includes the ghost layers, which hold the values of the last
+ * fill (before the last step) and are otherwise undefined. */
 spfm_status spfm_field_ptr(spfm_ctx *ctx, void **d_ptr);
 
 /* Eq. 3 initial fields, computed on the device.
@@ -160,6 +177,15 @@ spfm_status spfm_field_ptr(spfm_ctx *ctx, void **d_ptr);
 spfm_status spfm_init_planar(spfm_ctx *ctx, const int32_t hkl[3], double offset);
 spfm_status spfm_init_spheres(spfm_ctx *ctx, int32_t n, const double *centers,
                               const double *radii);
+/* Eq. 3 single planar front (not periodic): phi = (1 - tanh(2 s / lambda)) / 2,
+ * s = p . n/|n| - c, c = the box centre (nx, ny, nz) dx / 2 projected on n/|n|
+ * plus offset; phase 1 behind the front, n points into phase 0.  Every axis
+ * along which n has a nonzero component must be walled (SPFM_E_INVAL
+ * otherwise).  Resets the step counter; interface_position is then the
+ * front's displacement along n (phase volume change over the front area,
+ * taken as the box cross-section across the axis of the largest |n_d|,
+ * divided by |n_d|/|n|). */
+spfm_status spfm_init_front(spfm_ctx *ctx, const double n[3], double offset);
 
 /* Change the driving force (re-checks the stability bound). */
 spfm_status spfm_set_mu(spfm_ctx *ctx, double mu);

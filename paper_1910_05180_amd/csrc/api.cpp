@@ -44,6 +44,9 @@ struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
     int tsteps;   // steps per launch (temporal blocking), 1 = one step
+    int walls;    // bit d: contact-angle walls on axis d
+    double wall_sin[6];
+    int sx, sy, sz;   // stored dims: the grid plus one ghost layer per end of a walled axis
     double dt_max;
 };
 
@@ -63,13 +66,21 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     if (stencil != 6 && stencil != 18 && stencil != 26)
         return fail(SPFM_E_INVAL, "stencil must be 6, 18 or 26 (got %d)", stencil);
     if (o.dtype != SPFM_F32 && o.dtype != SPFM_F64) return fail(SPFM_E_INVAL, "unknown dtype %d", o.dtype);
-    // The tiled kernels address one z-plane through a buffer descriptor with
-    // 32-bit byte offsets.
+    if (o.walls < 0 || o.walls > 7) return fail(SPFM_E_INVAL, "walls must be a mask of axes (0..7)");
+    for (int f = 0; f < 6; ++f)
+        if ((o.walls >> (f / 2)) & 1)
+            if (!(std::fabs(o.wall_sin[f]) <= 1.0))
+                return fail(SPFM_E_INVAL, "wall_sin[%d] must be in [-1, 1]", f);
+    if (o.walls && o.tsteps > 1) return fail(SPFM_E_INVAL, "walls need one step per launch (tsteps <= 1)");
+    // Stored dims.  The tiled kernels address one z-plane through a buffer
+    // descriptor with 32-bit byte offsets.
+    const int sx = g->nx + 2 * (o.walls & 1), sy = g->ny + 2 * ((o.walls >> 1) & 1),
+              sz = g->nz + 2 * ((o.walls >> 2) & 1);
     const int64_t esize = o.dtype == SPFM_F64 ? 8 : 4;
-    if ((int64_t)g->nx * g->ny * esize >= (int64_t)1 << 31 ||
-        (int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40) || g->nz > 65535 || g->ny > 4 * 65535)
+    if ((int64_t)sx * sy * esize >= (int64_t)1 << 31 || (int64_t)sx * sy * sz > ((int64_t)1 << 40) ||
+        sz > 65535 || sy > 4 * 65535)
         return fail(SPFM_E_INVAL,
-                    "grid too large (nx*ny*element size < 2^31 bytes, ny <= 262140, nz <= 65535)");
+                    "grid too large (one stored z-plane < 2^31 bytes, ny <= 262140, nz <= 65535)");
     if (o.coupling != SPFM_LOCAL && o.coupling != SPFM_GLOBAL && o.coupling != SPFM_CF)
         return fail(SPFM_E_INVAL, "unknown coupling %d", o.coupling);
     if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_TILED)
@@ -110,6 +121,9 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     r->kernel = o.kernel == SPFM_KERNEL_AUTO ? SPFM_KERNEL_TILED : o.kernel;
     r->allow_unstable = o.allow_unstable;
     r->tsteps = o.tsteps > 1 ? o.tsteps : 1;
+    r->walls = o.walls;
+    for (int f = 0; f < 6; ++f) r->wall_sin[f] = ((o.walls >> (f / 2)) & 1) ? o.wall_sin[f] : 0.0;
+    r->sx = sx; r->sy = sy; r->sz = sz;
     r->dt_max = stable_dt(stencil, o.coupling, p.u, p.gamma, lambda, Gamma, M, mu, g->dx, p.C_Gamma);
     if (!o.allow_unstable && p.dt > r->dt_max)
         return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, r->dt_max);
@@ -236,8 +250,45 @@ struct spfm_ctx {
     Tracker track;
     GraphCache graphs;
 
+    WallCoef<float> wf;
+    WallCoef<double> wd;
+    int64_t nghost = 0;
+
+    // Grid points (the interior when there are walls) and the stored field.
     int64_t points() const { return (int64_t)r.p.nx * r.p.ny * r.p.nz; }
     size_t bytes() const { return (size_t)points() * elem_size(r.dtype); }
+    size_t stored_bytes() const { return (size_t)r.sx * r.sy * r.sz * elem_size(r.dtype); }
+    int gx() const { return r.walls & 1; }
+    int gy() const { return (r.walls >> 1) & 1; }
+    int gz() const { return (r.walls >> 2) & 1; }
+    // Copy between a dense grid-shaped array and the interior of a stored field.
+    hipError_t to_interior(void* stored, const void* dense) {
+        const Params& p = r.p;
+        return r.dtype == SPFM_F64
+                   ? launch_box_copy<double>((double*)stored, r.sx, r.sy, gx(), gy(), gz(),
+                                             (const double*)dense, p.nx, p.ny, 0, 0, 0, p.nx, p.ny,
+                                             p.nz, stream)
+                   : launch_box_copy<float>((float*)stored, r.sx, r.sy, gx(), gy(), gz(),
+                                            (const float*)dense, p.nx, p.ny, 0, 0, 0, p.nx, p.ny,
+                                            p.nz, stream);
+    }
+    hipError_t from_interior(void* dense, const void* stored) {
+        const Params& p = r.p;
+        return r.dtype == SPFM_F64
+                   ? launch_box_copy<double>((double*)dense, p.nx, p.ny, 0, 0, 0,
+                                             (const double*)stored, r.sx, r.sy, gx(), gy(), gz(),
+                                             p.nx, p.ny, p.nz, stream)
+                   : launch_box_copy<float>((float*)dense, p.nx, p.ny, 0, 0, 0, (const float*)stored,
+                                            r.sx, r.sy, gx(), gy(), gz(), p.nx, p.ny, p.nz, stream);
+    }
+    // A grid-dense array of the current field: the live buffer itself, or (with
+    // walls) its interior packed into the other buffer, which the next step
+    // overwrites anyway.
+    hipError_t dense_field(const void** out) {
+        if (!r.walls) { *out = buf[cur]; return hipSuccess; }
+        *out = buf[1 - cur];
+        return from_interior(buf[1 - cur], buf[cur]);
+    }
 
     int zlen = kTileZ;        // planes per block of the tiled kernel
     bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
@@ -255,6 +306,12 @@ struct spfm_ctx {
         const void* in = buf[from];
         void* out = buf[1 - from];
         const int S = r.p.stencil, C = r.p.coupling;
+        if (r.walls) {   // ghost layers of the input from Eq. 7, then the step on the stored grid
+            const hipError_t e = r.dtype == SPFM_F64
+                                     ? launch_fill_walls<double>((double*)buf[from], wd, nghost, stream)
+                                     : launch_fill_walls<float>((float*)buf[from], wf, nghost, stream);
+            if (e != hipSuccess) return e;
+        }
         if (r.dtype == SPFM_F64) {
             return r.kernel == SPFM_KERNEL_PLAIN
                        ? launch_step_plain<double>((const double*)in, (double*)out, kd, S, C, stream)
@@ -267,6 +324,28 @@ struct spfm_ctx {
     void refresh_coef() {
         kf = make_coef<float>(r.p);
         kd = make_coef<double>(r.p);
+        kf.nx = kd.nx = r.sx;   // the kernels sweep the stored grid
+        kf.ny = kd.ny = r.sy;
+        kf.nz = kd.nz = r.sz;
+        wf.sx = wd.sx = r.sx;
+        wf.sy = wd.sy = r.sy;
+        wf.sz = wd.sz = r.sz;
+        wf.walls = wd.walls = r.walls;
+        // Composed Eq. 7 coefficient of every ghost class: the shifts of the
+        // walls crossed from the ghost to its interior point add up.
+        for (int cz = -1; cz <= 1; ++cz)
+            for (int cy = -1; cy <= 1; ++cy)
+                for (int cx = -1; cx <= 1; ++cx) {
+                    const int c[3] = {cx, cy, cz};
+                    double sh = 0.0;
+                    for (int d = 0; d < 3; ++d)
+                        if (c[d] != 0) sh += r.wall_sin[2 * d + (c[d] > 0 ? 1 : 0)];
+                    const double a = std::tanh(2.0 * r.p.dx * sh / r.p.lambda);
+                    const int i = (cx + 1) + 3 * (cy + 1) + 9 * (cz + 1);
+                    wf.a[i] = (float)a;
+                    wd.a[i] = a;
+                }
+        nghost = wall_ghosts(r.sx, r.sy, r.sz, r.walls);
         graphs.clear();
     }
 };
@@ -426,8 +505,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
     const int tx = r.tsteps > 1 ? 64 : tile_x(r.dtype == SPFM_F32, r.p.coupling);   // temporal: 64 x 8
-    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.p.nx, r.p.ny, r.p.nz, tx);
-    const size_t bytes = c->bytes();
+    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.sx, r.sy, r.sz, tx);
+    const size_t bytes = c->stored_bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
         c->buf[1] = opt->d_phi[1];
@@ -465,8 +544,11 @@ void spfm_destroy(spfm_ctx* c) {
 
 spfm_status spfm_set_field(spfm_ctx* c, const void* src, int src_on_device) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
-    spfm_status st = copy_in(c->buf[c->cur], src, c->bytes(), src_on_device, c->stream);
+    // With walls the grid-shaped input goes through the other buffer into the interior.
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
+    spfm_status st = copy_in(dst, src, c->bytes(), src_on_device, c->stream);
     if (st != SPFM_OK) return st;
+    if (c->r.walls) HIP_TRY(c->to_interior(c->buf[c->cur], dst));
     c->nsteps = 0;
     c->track.reset(0, 0.0);
     return SPFM_OK;
@@ -474,7 +556,9 @@ spfm_status spfm_set_field(spfm_ctx* c, const void* src, int src_on_device) {
 
 spfm_status spfm_get_field(spfm_ctx* c, void* dst, int dst_on_device) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
-    return copy_out(dst, c->buf[c->cur], c->bytes(), dst_on_device, c->stream);
+    const void* src = nullptr;
+    HIP_TRY(c->dense_field(&src));
+    return copy_out(dst, src, c->bytes(), dst_on_device, c->stream);
 }
 
 spfm_status spfm_field_ptr(spfm_ctx* c, void** d_ptr) {
@@ -489,11 +573,13 @@ spfm_status spfm_init_planar(spfm_ctx* c, const int32_t hkl[3], double offset) {
     if (!std::isfinite(offset)) return fail(SPFM_E_INVAL, "offset must be finite");
     const Params& p = c->r.p;
     const int h[3] = {hkl[0], hkl[1], hkl[2]};
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
     hipError_t e = c->r.dtype == SPFM_F64
-                       ? launch_init_planar<double>((double*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx,
+                       ? launch_init_planar<double>((double*)dst, p.nx, p.ny, p.nz, p.dx,
                                                     p.lambda, h, offset, c->stream)
-                       : launch_init_planar<float>((float*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx,
+                       : launch_init_planar<float>((float*)dst, p.nx, p.ny, p.nz, p.dx,
                                                    p.lambda, h, offset, c->stream);
+    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
     if (e != hipSuccess) return fail(SPFM_E_HIP, "init launch: %s", hipGetErrorString(e));
     c->nsteps = 0;
     c->track.reset(1, slab_area(p.nx, p.ny, p.nz, p.dx, hkl));
@@ -514,17 +600,49 @@ spfm_status spfm_init_spheres(spfm_ctx* c, int32_t n, const double* centers, con
     HIP_TRY(hipMalloc(&d, sizeof(double) * h.size()));
     hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
     const Params& p = c->r.p;
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
     if (e == hipSuccess) {
         e = c->r.dtype == SPFM_F64
-                ? launch_init_spheres<double>((double*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream)
-                : launch_init_spheres<float>((float*)c->buf[c->cur], p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream);
+                ? launch_init_spheres<double>((double*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream)
+                : launch_init_spheres<float>((float*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream);
     }
+    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
     hipError_t se = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(SPFM_E_HIP, "sphere init: %s", hipGetErrorString(e));
     if (se != hipSuccess) return fail(SPFM_E_HIP, "sphere init sync: %s", hipGetErrorString(se));
     c->nsteps = 0;
     c->track.reset(n == 1 ? 2 : 0, 0.0);
+    return SPFM_OK;
+}
+
+spfm_status spfm_init_front(spfm_ctx* c, const double n[3], double offset) {
+    if (!c || !n) return fail(SPFM_E_INVAL, "NULL argument");
+    const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(nn > 0.0) || !std::isfinite(nn)) return fail(SPFM_E_INVAL, "n must be finite and nonzero");
+    if (!std::isfinite(offset)) return fail(SPFM_E_INVAL, "offset must be finite");
+    for (int d = 0; d < 3; ++d)
+        if (n[d] != 0.0 && !((c->r.walls >> d) & 1))
+            return fail(SPFM_E_INVAL, "a front varying along axis %d needs walls on that axis", d);
+    const Params& p = c->r.p;
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
+    hipError_t e = c->r.dtype == SPFM_F64
+                       ? launch_init_front<double>((double*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda,
+                                                   n, offset, c->stream)
+                       : launch_init_front<float>((float*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n,
+                                                  offset, c->stream);
+    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "front init: %s", hipGetErrorString(e));
+    // Position along n: the phase volume change over the front's area, the box
+    // cross-section normal to the axis the front crosses (largest |n_d|)
+    // divided by that component.
+    int d = 0;
+    for (int k = 1; k < 3; ++k)
+        if (std::fabs(n[k]) > std::fabs(n[d])) d = k;
+    const int ext[3] = {p.nx, p.ny, p.nz};
+    const double area = (double)ext[(d + 1) % 3] * ext[(d + 2) % 3] * p.dx * p.dx / (std::fabs(n[d]) / nn);
+    c->nsteps = 0;
+    c->track.reset(1, area);
     return SPFM_OK;
 }
 
@@ -554,7 +672,9 @@ spfm_status spfm_step(spfm_ctx* c, int64_t n) {
 
 spfm_status spfm_diagnostics(spfm_ctx* c, spfm_diag* out) {
     if (!c || !out) return fail(SPFM_E_INVAL, "NULL argument");
-    spfm_status st = c->red.run(c->buf[c->cur], c->r.dtype, c->points(), c->stream);
+    const void* field = nullptr;
+    HIP_TRY(c->dense_field(&field));
+    spfm_status st = c->red.run(field, c->r.dtype, c->points(), c->stream);
     if (st != SPFM_OK) return st;
     c->track.fill(out, *c->red.h_out, c->r.p.dx, c->r.p.lambda, c->nsteps, c->r.p.dt);
     if (out->diverged) return fail(SPFM_E_DIVERGED, "%d points are non-finite or |phi| > 2", out->diverged);
@@ -571,6 +691,7 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     o->stencil = p.stencil; o->coupling = p.coupling; o->dtype = c->r.dtype; o->kernel = c->r.kernel;
     o->zchunk = c->zlen;
     o->tsteps = c->r.tsteps;
+    o->walls = c->r.walls;
     return SPFM_OK;
 }
 
@@ -602,6 +723,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.C_Gamma > 0.0) return fail(SPFM_E_INVAL, "batches calibrate C_Gamma per grid");
     if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
     if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
+    if (o.walls) return fail(SPFM_E_INVAL, "batches are periodic (walls = 0)");
     spfm_batch* b = new (std::nothrow) spfm_batch;
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;

@@ -263,7 +263,18 @@ __device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k
     return point_core<T, S, C>(p, s1, s2, s3, grad, k);
 }
 
-// ---- launchers (step_kernels.hip, reduce.hip, init.hip) ----
+// Contact-angle walls (walls.hip): stored dims, the walled axes (bit d = axis d)
+// and the composed Eq. 7 coefficient for every ghost class (cx, cy, cz in
+// {-1, 0, 1}: below the low wall, inside, above the high wall), at index
+// (cx + 1) + 3 (cy + 1) + 9 (cz + 1).
+template <typename T>
+struct WallCoef {
+    int sx, sy, sz;
+    int walls;
+    T a[27];
+};
+
+// ---- launchers (step_kernels.hip, reduce.hip, init.hip, walls.hip) ----
 struct TileItem {   // one block of the batched step: grid index, tile origin, planes
     int inst;
     int x0, y0, z0;
@@ -320,6 +331,18 @@ __host__ __device__ __forceinline__ int xcd_deal(int b, int n, int run) {
     const int k = b % kNumXcd, i = b / kNumXcd;
     return ((i / run) * kNumXcd + k) * run + i % run;
 }
+
+// Number of ghost points of a padded field (the threads of one fill).
+int64_t wall_ghosts(int sx, int sy, int sz, int walls);
+template <typename T>
+hipError_t launch_fill_walls(T* phi, const WallCoef<T>& w, int64_t nghost, hipStream_t s);
+template <typename T>
+hipError_t launch_box_copy(T* dst, int dnx, int dny, int dx0, int dy0, int dz0, const T* src,
+                           int snx, int sny, int sx0, int sy0, int sz0, int bx, int by, int bz,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_init_front(T* phi, int nx, int ny, int nz, double dx, double lambda,
+                             const double n[3], double offset, hipStream_t s);
 
 struct ReduceOut {   // device result of the diagnostics reduction
     double sum_phi, sum_x;

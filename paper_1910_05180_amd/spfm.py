@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("eps", ctypes.c_double), ("tau", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("d_phi", ctypes.c_void_p * 2),
                 ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
+                ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6)]
 
 
 class Diag(ctypes.Structure):
@@ -59,7 +60,8 @@ class Info(ctypes.Structure):
                [("gamma", ctypes.c_double * 3), ("dt_max", ctypes.c_double),
                 ("stencil", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
+                ("walls", ctypes.c_int32)]
 
 
 class SpfmError(RuntimeError):
@@ -92,6 +94,7 @@ def load():
         "spfm_field_ptr": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
         "spfm_init_planar": ([vp, ip, d], ctypes.c_int),
         "spfm_init_spheres": ([vp, i32, dp, dp], ctypes.c_int),
+        "spfm_init_front": ([vp, dp, d], ctypes.c_int),
         "spfm_set_mu": ([vp, d], ctypes.c_int),
         "spfm_step": ([vp, i64], ctypes.c_int),
         "spfm_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
@@ -145,7 +148,7 @@ def _stream_handle(stream):
 
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
-             allow_unstable=False, zchunk=0, tsteps=0) -> Options:
+             allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -160,7 +163,24 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.allow_unstable = 1 if allow_unstable else 0
     o.zchunk = int(zchunk)
     o.tsteps = int(tsteps)
+    o.walls = _walls_mask(walls)
+    o.wall_sin[:] = [float(v) for v in wall_sin] if wall_sin is not None else [0.0] * 6
     return o
+
+
+def _walls_mask(walls) -> int:
+    """Walled axes as a bit mask: an int, or a string of axis letters ("xyz", "yz")."""
+    if isinstance(walls, str):
+        return sum(1 << "xyz".index(a) for a in set(walls))
+    return int(walls)
+
+
+def front_wall_sin(n):
+    """Face values (-x, +x, -y, +y, -z, +z) of wall_sin that hold a planar front
+    of normal n (into phase 0) exactly: n . e over the outward face normals."""
+    v = np.asarray(n, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    return (-v[0], v[0], -v[1], v[1], -v[2], v[2])
 
 
 def _np_dtype(code: int):
@@ -180,9 +200,12 @@ class Spfm:
         self.np_dtype = _np_dtype(self._opts.dtype)
         self._buffers = None
         torch = _torch()
+        w = self._opts.walls
+        self.stored_shape = (nz + 2 * ((w >> 2) & 1), ny + 2 * ((w >> 1) & 1), nx + 2 * (w & 1))
         if torch_buffers and torch is not None and torch.cuda.is_available():
             tdt = torch.float64 if self._opts.dtype == F64 else torch.float32
-            self._buffers = [torch.zeros(self.shape, dtype=tdt, device="cuda") for _ in range(2)]
+            self._buffers = [torch.zeros(self.stored_shape, dtype=tdt, device="cuda")
+                             for _ in range(2)]
             self._opts.d_phi[0] = self._buffers[0].data_ptr()
             self._opts.d_phi[1] = self._buffers[1].data_ptr()
         g = Grid(nx, ny, nz, float(dx))
@@ -242,6 +265,11 @@ class Spfm:
         assert c.shape[0] == r.size
         dp = ctypes.POINTER(ctypes.c_double)
         _check(load().spfm_init_spheres(self._h, r.size, c.ctypes.data_as(dp), r.ctypes.data_as(dp)))
+
+    def init_front(self, n, offset: float = 0.0):
+        v = np.ascontiguousarray(n, dtype=np.float64).reshape(3)
+        _check(load().spfm_init_front(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      float(offset)))
 
     # -- stepping --
     def set_mu(self, mu: float):

@@ -41,6 +41,8 @@ def test_exports_every_declared_symbol(S):
     (dict(mu=float("nan")), -1), (dict(kernel=7), -1),
     (dict(tsteps=5), -1), (dict(tsteps=-1), -1), (dict(tsteps=2, dtype="f64"), -1),
     (dict(tsteps=2, kernel="plain"), -1),
+    (dict(walls=8), -1), (dict(walls=-1), -1), (dict(walls=2, wall_sin=(0, 0, 1.5, 0, 0, 0)), -1),
+    (dict(walls=4, wall_sin=(0, 0, 0, 0, 0, float("nan"))), -1), (dict(walls=1, tsteps=2), -1),
 ])
 def test_create_rejects_bad_arguments_before_any_hip_call(S, kw, status):
     st, msg = S.try_create((16, 16, 16), **kw)
@@ -81,4 +83,18 @@ def test_create_rejects_planes_beyond_32_bit_byte_offsets(S):
     st, msg = S.try_create((3, 16384, 32768))
     assert st == -1 and "2^31" in msg
     st, msg = S.try_create((3, 16384, 16384), dtype="f64")
+    assert st == -1 and "2^31" in msg
+
+
+def test_walls_on_other_axes_ignore_their_faces(S):
+    """wall_sin of an unwalled axis is not looked at (here a NaN on the x faces
+    with only z walled); validation then fails only for the dt bound."""
+    st, msg = S.try_create((16, 16, 16), walls=4, wall_sin=(float("nan"), 2.0, 0, 0, 0.1, -0.1),
+                           dt=1.0)
+    assert st == -4
+
+
+def test_walled_planes_count_their_ghosts(S):
+    # a stored x-y plane of (2^14 + 2) x 2^15 FP32 values is 2^31 + 2^18 bytes
+    st, msg = S.try_create((3, 16384, 32768 - 2), walls=1)
     assert st == -1 and "2^31" in msg
