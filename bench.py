@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal")
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -142,6 +142,47 @@ def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0):
             / HBM_PEAK_GBS}
 
 
+def walls_leg(spfm, torch, warm=400, steps=1600):
+    """The orientation study of the paper's Sec. 3.3 on its 120 x 10 x 10 grid:
+    planar fronts rotated about [001] (0, 15, 30, 45 degrees) and [011] (15, 30,
+    45 degrees) between contact-angle walls (Eq. 7) that hold their
+    orientation, TI_n, 26 neighbours, lambda = 4 dx, mu = mu0 cos(theta),
+    mu0 = 0.05, dt = 0.05, FP32.  Reports the aggregate step rate and the
+    largest relative error of the front's x-velocity against -M mu0 / Gamma."""
+    import math
+    shape, mu0, dt = (10, 10, 120), 0.05, 0.05
+    runs = [("001", d) for d in (0, 15, 30, 45)] + [("011", d) for d in (15, 30, 45)]
+    total_ms, worst, errs = 0.0, 0.0, {}
+    for axis, deg in runs:
+        th = math.radians(deg)
+        n = (math.cos(th), math.sin(th), 0.0) if axis == "001" else \
+            (math.cos(th), math.sin(th) / math.sqrt(2.0), math.sin(th) / math.sqrt(2.0))
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm(shape, lam=4.0, mu=mu0 * n[0], stencil=26, coupling="local", dt=dt,
+                          walls=7, wall_sin=spfm.front_wall_sin(n), stream=stream)
+            s.init_front(n, 20.0)
+            s.step(warm)
+            d0 = s.diagnostics()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            d1 = s.diagnostics()
+            total_ms += e0.elapsed_time(e1)
+            s.close()
+        vx = (d1["interface_position"] - d0["interface_position"]) / (d1["time"] - d0["time"]) / n[0]
+        err = vx / (-mu0) - 1.0
+        errs[f"{axis}:{deg}"] = err
+        worst = max(worst, abs(err))
+    pts = shape[0] * shape[1] * shape[2]
+    return {"value": pts * steps * len(runs) / (total_ms * 1e-3) / 1e9, "unit": "GLUPS",
+            "grid": "120x10x10 + ghost layers", "orientations": len(runs), "steps": steps,
+            "us_per_step": total_ms * 1e3 / (steps * len(runs)),
+            "max_rel_velocity_error": worst, "rel_velocity_error": errs}
+
+
 def cpu_baseline(w, steps):
     import numpy as np
 
@@ -233,6 +274,8 @@ def main():
         out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
     if args.only in ("", "temporal"):
         out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
+    if args.only in ("", "walls"):
+        out["orientation120_walls"] = walls_leg(spfm, torch)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
