@@ -26,6 +26,8 @@ _lib = None
 
 LOCAL, GLOBAL, CF = 0, 1, 2
 COUPLINGS = {"local": LOCAL, "global": GLOBAL, "cf": CF}
+H3, H5, HABEL = 0, 1, 2
+INTERPS = {"h3": H3, "h5": H5, "habel": HABEL}
 
 
 def build() -> str:
@@ -44,6 +46,7 @@ class Params(ctypes.Structure):
         ("C_Gamma", ctypes.c_double), ("stencil", ctypes.c_int), ("coupling", ctypes.c_int),
         ("u", ctypes.c_double * 3), ("gamma", ctypes.c_double * 3),
         ("eps", ctypes.c_double), ("tau", ctypes.c_double),
+        ("interp", ctypes.c_int),
     ]
 
 
@@ -82,6 +85,9 @@ def lib():
             L.orc_spheres_at.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double,
                                                               ctypes.c_int, dp, dp, ctypes.c_long,
                                                               ctypes.POINTER(ctypes.c_int), dp]
+            for f in (L.orc_interp, L.orc_interp_prime):
+                f.argtypes = [ctypes.c_int, ctypes.c_double]
+                f.restype = ctypes.c_double
             L.orc_wall_value.argtypes = [ctypes.c_double, ctypes.c_double]
             L.orc_wall_value.restype = ctypes.c_double
             L.orc_fill_walls.argtypes = [pp, ctypes.c_int, dp, dp]
@@ -107,7 +113,7 @@ def default_gamma(stencil: int):
 
 def params(shape, *, dx=1.0, lam=4.0, Gamma=1.0, M=1.0, mu=0.0, dt=0.1, stencil=26,
            coupling="local", u=(1.0, 0.0, 0.0), gamma=None, C_Gamma=None, eps=1e-12,
-           tau=1e-3) -> Params:
+           tau=1e-3, interp="h3") -> Params:
     nz, ny, nx = shape
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -120,6 +126,7 @@ def params(shape, *, dx=1.0, lam=4.0, Gamma=1.0, M=1.0, mu=0.0, dt=0.1, stencil=
         C_Gamma = 2.0 / 3.0 if p.coupling == CF else calibrate_cgamma(lam / dx)
     p.C_Gamma = C_Gamma
     p.eps, p.tau = eps, tau
+    p.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
     return p
 
 
@@ -250,6 +257,17 @@ def num_threads() -> int:
 # the low and high face of axis d and are n . e of the front normal n the wall
 # imposes, e the outward normal of the face.
 # ---------------------------------------------------------------------------
+def interp(which, phi: float) -> float:
+    """Interpolation function h of Tab. 2 ("h3", "h5", "habel")."""
+    w = INTERPS[which] if isinstance(which, str) else int(which)
+    return lib().orc_interp(w, float(phi))
+
+
+def interp_prime(which, phi: float) -> float:
+    w = INTERPS[which] if isinstance(which, str) else int(which)
+    return lib().orc_interp_prime(w, float(phi))
+
+
 def wall_value(phi_in: float, a: float) -> float:
     return lib().orc_wall_value(float(phi_in), float(a))
 

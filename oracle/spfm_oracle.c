@@ -158,11 +158,35 @@ static double coupling_a(const orc_params *p, const int r[3], const double n[3])
     return tanh(2.0 * rn / p->lambda);
 }
 
+/* Interpolation functions of Tab. 2: h3 = phi^2 (3 - 2 phi) (all models),
+ * h5 = phi^3 (10 - 15 phi + 6 phi^2) and h_Abel = phi^2 / (phi^2 + (1-phi)^2)
+ * (CF comparisons, Sec. 3.1).  Written as printed; their derivatives below are
+ * the textbook derivatives of these expressions. */
+static double interp_h(int which, double phi) {
+    switch (which) {
+        case ORC_H5: return phi * phi * phi * (10.0 - 15.0 * phi + 6.0 * phi * phi);
+        case ORC_HABEL: return phi * phi / (phi * phi + (1.0 - phi) * (1.0 - phi));
+        default: return phi * phi * (3.0 - 2.0 * phi);
+    }
+}
+static double interp_h_prime(int which, double phi) {
+    switch (which) {
+        case ORC_H5: return 30.0 * phi * phi * (1.0 - phi) * (1.0 - phi);
+        case ORC_HABEL: {
+            double d = phi * phi + (1.0 - phi) * (1.0 - phi);
+            return 2.0 * phi * (1.0 - phi) / (d * d);
+        }
+        default: return 6.0 * phi * (1.0 - phi);
+    }
+}
+double orc_interp(int which, double phi) { return interp_h(which, phi); }
+double orc_interp_prime(int which, double phi) { return interp_h_prime(which, phi); }
+
 /* d phi_p / dt from Eq. 2 with the functional derivative of Eq. 1:
  *   delta_phi F = Gamma/(C_Gamma lambda) sum_k gamma_j nu_j [ g_k'(phi_p)
- *                 - lambda^2 (phi_{p+r} - 2 phi_p + phi_{p-r}) / |r|^2 ] + mu h3'(phi_p),
+ *                 - lambda^2 (phi_{p+r} - 2 phi_p + phi_{p-r}) / |r|^2 ] + mu h'(phi_p),
  *   d_t phi = -(2M / (3 lambda Gamma)) delta_phi F,
- * with h3 = phi^2 (3 - 2 phi), h3' = 6 phi (1-phi).  The sign of the gradient
+ * with h the interpolation function of the model (h3 unless chosen otherwise).  The sign of the gradient
  * term is that of the variational derivative of the forward-difference energy
  * of Eq. 1 (and of Eq. 4); the printed definition of the backward difference
  * carries the opposite sign. */
@@ -188,7 +212,7 @@ static double rate_at(const orc_params *p, const double *phi, int x, int y, int 
         }
         s += w * (gp - lap);
     }
-    double dF = p->Gamma / (p->C_Gamma * p->lambda) * s + p->mu * 6.0 * phi0 * (1.0 - phi0);
+    double dF = p->Gamma / (p->C_Gamma * p->lambda) * s + p->mu * interp_h_prime(p->interp, phi0);
     return -2.0 * p->M / (3.0 * p->lambda * p->Gamma) * dF;
 }
 
@@ -236,7 +260,7 @@ static void acc_add(acc_t *a, double v) {
 }
 
 /* Eq. 1: F = sum_p f_p dx^3 with
- * f_p = Gamma/(C_Gamma lambda) sum_k gamma_j nu_j (lambda^2/2 (d_k^+ phi)^2 + g_k(phi_p)) + mu h3(phi_p). */
+ * f_p = Gamma/(C_Gamma lambda) sum_k gamma_j nu_j (lambda^2/2 (d_k^+ phi)^2 + g_k(phi_p)) + mu h(phi_p). */
 double orc_energy(const orc_params *p, const double *phi, int with_mu) {
     acc_t *plane = (acc_t *)calloc((size_t)p->nz, sizeof(acc_t));
     if (!plane) return NAN;
@@ -264,7 +288,7 @@ double orc_energy(const orc_params *p, const double *phi, int with_mu) {
                     s += w * (0.5 * p->lambda * p->lambda * d * d + g);
                 }
                 double f = p->Gamma / (p->C_Gamma * p->lambda) * s;
-                if (with_mu) f += p->mu * phi0 * phi0 * (3.0 - 2.0 * phi0);
+                if (with_mu) f += p->mu * interp_h(p->interp, phi0);
                 acc_add(&a, f);
             }
         plane[z] = a;
@@ -358,7 +382,10 @@ double orc_stable_dt(const orc_params *p) {
         }
     double A = 2.0 * p->M / (3.0 * p->C_Gamma * p->lambda * p->lambda);
     double B = 2.0 * p->M * p->mu / (3.0 * p->lambda * p->Gamma);
-    return 2.0 / (A * p->lambda * p->lambda * smax + A * pmax + 6.0 * fabs(B));
+    /* the driving term's slope at the bulk states is mu h''(0) = mu h''(1) up to sign:
+     * 6 for h3, 0 for h5, 2 for h_Abel */
+    double hpp = p->interp == ORC_H5 ? 0.0 : (p->interp == ORC_HABEL ? 2.0 : 6.0);
+    return 2.0 / (A * p->lambda * p->lambda * smax + A * pmax + hpp * fabs(B));
 }
 
 static long gcd_l(long a, long b) {

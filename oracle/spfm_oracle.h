@@ -22,6 +22,7 @@ extern "C" {
 #endif
 
 enum { ORC_LOCAL = 0, ORC_GLOBAL = 1, ORC_CF = 2 };
+enum { ORC_H3 = 0, ORC_H5 = 1, ORC_HABEL = 2 };
 
 typedef struct {
     int nx, ny, nz;   /* grid points along x, y, z */
@@ -38,6 +39,7 @@ typedef struct {
     double gamma[3];  /* shell weights gamma_1..3 (Eq. 1) */
     double eps;       /* floor of phi and 1-phi inside the normal estimator */
     double tau;       /* |grad psi| below tau -> fallback normal (1,0,0) */
+    int interp;       /* interpolation function of the driving force: ORC_H3, ORC_H5, ORC_HABEL (Tab. 2) */
 } orc_params;
 
 /* Tab. 1: direction k (0..12) as an integer vector; returns its shell 1..3. */
@@ -56,6 +58,9 @@ void orc_rate(const orc_params *p, const double *phi, double *rate);
 void orc_rate_points(const orc_params *p, const double *phi, long npts, const long *idx, double *rate);
 /* nsteps forward-Euler steps, in place.  Returns 0, or -1 on allocation failure. */
 int orc_step(const orc_params *p, double *phi, long nsteps);
+/* Interpolation function h of Tab. 2 and its derivative. */
+double orc_interp(int which, double phi);
+double orc_interp_prime(int which, double phi);
 /* Total free energy of Eq. 1 (with_mu = 0 gives the interface energy F_int). */
 double orc_energy(const orc_params *p, const double *phi, int with_mu);
 /* Interface energy calibration C_Gamma for lambda/dx (reading: discrete energy
