@@ -107,6 +107,11 @@ typedef struct {
                            coordinate (towards phi = 0 for > 0).  A planar front of normal n
                            (into phi = 0) is held exactly by sin(alpha) = n . e, e the outward
                            normal of the face.  Unused for unwalled axes */
+    int32_t interp;     /* interpolation function h of the driving force mu h(phi) (Tab. 2):
+                           0 = h3 = phi^2 (3 - 2 phi) (default; the TI models' choice),
+                           1 = h5 = phi^3 (10 - 15 phi + 6 phi^2),
+                           2 = h_Abel = phi^2 / (phi^2 + (1 - phi)^2); 1 and 2 only with
+                           coupling CF (the comparisons of Sec. 3.1), else SPFM_E_INVAL */
 } spfm_options;
 
 typedef struct {
@@ -134,6 +139,7 @@ typedef struct {
                                   at the first spfm_step when kernel is AUTO) */
     int32_t tsteps;            /* steps per fused launch (1 = no temporal blocking) */
     int32_t walls;             /* walled axes (bit mask) */
+    int32_t interp;            /* interpolation function (spfm_options.interp) */
 } spfm_info;
 
 typedef struct spfm_ctx spfm_ctx;
@@ -215,7 +221,8 @@ spfm_status spfm_batch_diagnostics(spfm_batch *b, spfm_diag *out /* n entries */
 int64_t spfm_batch_points(const spfm_batch *b);
 
 /* Host-only helpers (no HIP call): the calibration C_Gamma(lambda/dx) used
- * when C_Gamma <= 0, and the explicit stability bound for a parameter set. */
+ * when C_Gamma <= 0, and the explicit stability bound for a parameter set
+ * with the h3 driving force (spfm_get_info reports the bound of a context). */
 double spfm_calibrate_cgamma(double lambda_over_dx, int coupling);
 double spfm_stable_dt(int stencil, int coupling, const double u[3], const double gamma[3],
                       double lambda, double Gamma, double M, double mu, double dx,

@@ -124,7 +124,12 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     r->walls = o.walls;
     for (int f = 0; f < 6; ++f) r->wall_sin[f] = ((o.walls >> (f / 2)) & 1) ? o.wall_sin[f] : 0.0;
     r->sx = sx; r->sy = sy; r->sz = sz;
-    r->dt_max = stable_dt(stencil, o.coupling, p.u, p.gamma, lambda, Gamma, M, mu, g->dx, p.C_Gamma);
+    if (o.interp < kH3 || o.interp > kHAbel) return fail(SPFM_E_INVAL, "unknown interp %d", o.interp);
+    if (o.interp != kH3 && o.coupling != kCF)
+        return fail(SPFM_E_INVAL, "h5 and h_Abel go with the CF coupling (Tab. 2)");
+    p.interp = o.interp;
+    r->dt_max = stable_dt(stencil, o.coupling, p.u, p.gamma, lambda, Gamma, M, mu, g->dx, p.C_Gamma,
+                          p.interp);
     if (!o.allow_unstable && p.dt > r->dt_max)
         return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, r->dt_max);
     return SPFM_OK;
@@ -300,12 +305,12 @@ struct spfm_ctx {
     hipError_t launch_unit(int from) {
         if (r.tsteps == 1) return launch_one(from);
         return launch_step_temporal((const float*)buf[from], (float*)buf[1 - from], kf, r.p.stencil,
-                                    r.p.coupling, r.tsteps, zlen, stream);
+                                    kernel_coupling(r.p.coupling, r.p.interp), r.tsteps, zlen, stream);
     }
     hipError_t launch_one(int from) {
         const void* in = buf[from];
         void* out = buf[1 - from];
-        const int S = r.p.stencil, C = r.p.coupling;
+        const int S = r.p.stencil, C = kernel_coupling(r.p.coupling, r.p.interp);
         if (r.walls) {   // ghost layers of the input from Eq. 7, then the step on the stored grid
             const hipError_t e = r.dtype == SPFM_F64
                                      ? launch_fill_walls<double>((double*)buf[from], wd, nghost, stream)
@@ -651,7 +656,8 @@ spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
     Params p = c->r.p;
     p.mu = mu;
-    const double dtm = stable_dt(p.stencil, p.coupling, p.u, p.gamma, p.lambda, p.Gamma, p.M, mu, p.dx, p.C_Gamma);
+    const double dtm = stable_dt(p.stencil, p.coupling, p.u, p.gamma, p.lambda, p.Gamma, p.M, mu, p.dx,
+                                 p.C_Gamma, p.interp);
     if (!c->r.allow_unstable && p.dt > dtm)
         return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, dtm);
     c->r.p = p;
@@ -692,6 +698,7 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     o->zchunk = c->zlen;
     o->tsteps = c->r.tsteps;
     o->walls = c->r.walls;
+    o->interp = c->r.p.interp;
     return SPFM_OK;
 }
 
@@ -728,7 +735,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;
     b->stencil = stencil;
-    b->coupling = o.coupling;
+    b->coupling = kernel_coupling(o.coupling, o.interp);
     b->stream = (hipStream_t)o.stream;
     b->r.resize(n);
     b->track.resize(n);

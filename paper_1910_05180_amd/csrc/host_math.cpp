@@ -73,7 +73,8 @@ double calibrate_cgamma(double lt, int coupling) {
 // P(n) = sum_k w_k g_k''(0) the potential curvature at phi = 0 (or 1):
 // TI: (lambda^2/|r_k|^2) 4 sinh^2(2 r_k.n / lambda); CF: 16/3 per direction.
 double stable_dt(int stencil, int coupling, const double u[3], const double gamma[3],
-                 double lambda, double Gamma, double M, double mu, double dx, double C_Gamma) {
+                 double lambda, double Gamma, double M, double mu, double dx, double C_Gamma,
+                 int interp) {
     const int nd = ndirs(stencil);
     double smax = 0.0;
     const int NT = 64;
@@ -123,7 +124,9 @@ double stable_dt(int stencil, int coupling, const double u[3], const double gamm
     }
     const double A = 2.0 * M / (3.0 * C_Gamma * lambda * lambda);
     const double B = 2.0 * M * mu / (3.0 * lambda * Gamma);
-    return 2.0 / (A * lambda * lambda * smax + A * pmax + 6.0 * fabs(B));
+    // slope of mu h'(phi) at the bulk states: h'' = 6 (h3), 0 (h5), 2 (h_Abel)
+    const double hpp = interp == kH5 ? 0.0 : (interp == kHAbel ? 2.0 : 6.0);
+    return 2.0 / (A * lambda * lambda * smax + A * pmax + hpp * fabs(B));
 }
 
 template <typename T>
@@ -141,7 +144,8 @@ StepCoef<T> make_coef(const Params& p) {
         if (j <= nsh) wsum += p.gamma[j - 1] * nu_of(j) * mcount[j - 1];
     }
     k.kcf = (T)(p.dt * A * 16.0 / 3.0 * wsum);
-    k.b = (T)(p.dt * 6.0 * B);
+    const double hfac = p.interp == kH5 ? 30.0 : (p.interp == kHAbel ? 2.0 : 6.0);
+    k.b = (T)(p.dt * hfac * B);
     k.kap2 = (T)(4.0 * p.dx / (p.lambda * M_LN2));
     k.eps = (T)p.eps;
     const double t = 8.0 * p.dx * p.tau / (p.lambda * M_LN2);

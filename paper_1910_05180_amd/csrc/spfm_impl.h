@@ -26,6 +26,17 @@
 namespace spfm {
 
 enum Coupling : int { kLocal = 0, kGlobal = 1, kCF = 2 };
+// Interpolation function of the driving force (Tab. 2): h3 = phi^2 (3 - 2 phi),
+// h5 = phi^3 (10 - 15 phi + 6 phi^2), h_Abel = phi^2 / (phi^2 + (1-phi)^2); with
+// x = phi(1-phi) their slopes are 6x, 30x^2 and 2x/(1-2x)^2.  The paper pairs
+// h5 and h_Abel with the CF potential only.
+enum Interp : int { kH3 = 0, kH5 = 1, kHAbel = 2 };
+// Kernel variants: the couplings above with h3, and CF with h5 or h_Abel.
+enum KernelCoupling : int { kCF5 = 3, kCFAbel = 4 };
+constexpr bool is_cf(int C) { return C >= kCF; }
+inline int kernel_coupling(int coupling, int interp) {
+    return coupling == kCF && interp == kH5 ? kCF5 : (coupling == kCF && interp == kHAbel ? kCFAbel : coupling);
+}
 
 template <typename T>
 struct StepCoef {
@@ -156,7 +167,7 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
     T upd = k.K[0] * s1;
     if (S >= 18) upd = fma(k.K[1], s2, upd);
     if (S >= 26) upd = fma(k.K[2], s3, upd);
-    if (C == kCF) {
+    if (is_cf(C)) {
         upd = fma(-k.kcf, x * u, upd);
     } else if (x != T(0)) {
         T q;
@@ -249,7 +260,15 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
         }
         upd = fma(-u, q, upd);
     }
-    upd = fma(-k.b, x, upd);
+    // Driving force mu h'(phi); b holds dt 6B (h3), dt 30B (h5) or dt 2B (h_Abel).
+    if (C == kCF5) {
+        upd = fma(-k.b, x * x, upd);
+    } else if (C == kCFAbel) {
+        const T d = T(1) - T(2) * x;
+        upd = fma(-k.b, x / (d * d), upd);
+    } else {
+        upd = fma(-k.b, x, upd);
+    }
     return p + upd;
 }
 

@@ -190,6 +190,8 @@ hipError_t dispatch_temporal(const float* in, float* out, const StepCoef<float>&
     SPFM_CASE(6, kLocal) SPFM_CASE(6, kGlobal) SPFM_CASE(6, kCF)
     SPFM_CASE(18, kLocal) SPFM_CASE(18, kGlobal) SPFM_CASE(18, kCF)
     SPFM_CASE(26, kLocal) SPFM_CASE(26, kGlobal) SPFM_CASE(26, kCF)
+    SPFM_CASE(6, kCF5) SPFM_CASE(18, kCF5) SPFM_CASE(26, kCF5)
+    SPFM_CASE(6, kCFAbel) SPFM_CASE(18, kCFAbel) SPFM_CASE(26, kCFAbel)
 #undef SPFM_CASE
     return hipErrorInvalidValue;
 }

@@ -22,6 +22,7 @@ KERNEL_AUTO, KERNEL_PLAIN, KERNEL_TILED = 0, 1, 2
 _DTYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
 _COUPLINGS = {"local": LOCAL, "global": GLOBAL, "cf": CF}
 _KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "tiled": KERNEL_TILED}
+_INTERPS = {"h3": 0, "h5": 1, "habel": 2}
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 
@@ -39,7 +40,8 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("d_phi", ctypes.c_void_p * 2),
                 ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
-                ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6)]
+                ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6),
+                ("interp", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -61,7 +63,7 @@ class Info(ctypes.Structure):
                 ("stencil", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
-                ("walls", ctypes.c_int32)]
+                ("walls", ctypes.c_int32), ("interp", ctypes.c_int32)]
 
 
 class SpfmError(RuntimeError):
@@ -148,7 +150,8 @@ def _stream_handle(stream):
 
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
-             allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None) -> Options:
+             allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None,
+             interp="h3") -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -165,6 +168,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.tsteps = int(tsteps)
     o.walls = _walls_mask(walls)
     o.wall_sin[:] = [float(v) for v in wall_sin] if wall_sin is not None else [0.0] * 6
+    o.interp = _INTERPS[interp] if isinstance(interp, str) else int(interp)
     return o
 
 
@@ -319,6 +323,12 @@ class SpfmBatch:
         if getattr(self, "_h", None):
             load().spfm_batch_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

@@ -1,0 +1,123 @@
+"""GPU parity of the CF models with the interpolation functions h5 and h_Abel
+(Tab. 2), and the model comparison of Fig. 6 on the device."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import as_f32_input, slab111, stable_dt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_05180_amd import spfm
+    spfm.load()
+    return spfm
+
+
+def run_pair(S, steps, *, dtype, kernel, stencil, interp, phi0, lam=1.5, mu=0.3):
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    shape = phi0.shape
+    p = oracle.params(shape, lam=lam, mu=mu, stencil=stencil, coupling="cf", eps=eps, interp=interp)
+    p.dt = stable_dt(p)
+    if dtype == "f32":
+        phi0 = as_f32_input(phi0)
+    print(f"case {interp} {dtype} {kernel} S={stencil} steps={steps} dt={p.dt:.4f}", flush=True)
+    ref = oracle.step(p, phi0, steps)
+    with S.Spfm(shape, lam=lam, mu=mu, stencil=stencil, dtype=dtype, coupling="cf", eps=eps,
+                C_Gamma=p.C_Gamma, kernel=kernel, dt=p.dt, interp=interp) as s:
+        s.set_field(phi0)
+        s.step(steps)
+        got = s.get_field().astype(np.float64)
+    return float(np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("interp", ["h5", "habel"])
+@pytest.mark.parametrize("kernel", ["plain", "tiled"])
+@pytest.mark.parametrize("stencil", [6, 18, 26])
+def test_cf_interp_fp64(S, interp, kernel, stencil):
+    assert run_pair(S, 40, dtype="f64", kernel=kernel, stencil=stencil, interp=interp,
+                    phi0=slab111()) <= 1e-12
+
+
+@pytest.mark.parametrize("interp", ["h5", "habel"])
+@pytest.mark.parametrize("kernel", ["plain", "tiled"])
+@pytest.mark.parametrize("stencil", [6, 18, 26])
+def test_cf_interp_fp32(S, interp, kernel, stencil):
+    assert run_pair(S, 200, dtype="f32", kernel=kernel, stencil=stencil, interp=interp,
+                    phi0=slab111()) <= 1e-5
+
+
+@pytest.mark.parametrize("interp", ["h5", "habel"])
+def test_cf_interp_fused_equals_plain(S, interp):
+    phi0 = slab111().astype(np.float32)
+    p = oracle.params(phi0.shape, lam=1.5, mu=0.3, stencil=26, coupling="cf", interp=interp)
+    dt = stable_dt(p)
+    out = []
+    for kw in (dict(kernel="plain"), dict(kernel="tiled", tsteps=2)):
+        with S.Spfm(phi0.shape, lam=1.5, mu=0.3, stencil=26, coupling="cf", dt=dt, interp=interp,
+                    **kw) as s:
+            s.set_field(phi0)
+            s.step(8)
+            out.append(s.get_field())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))
+
+
+def test_cf_interp_batch_equals_single_grids(S):
+    shapes = [(20, 9, 33), (8, 16, 40), (12, 12, 12)]
+    lams, mus = [1.5, 2.0, 2.5], [0.3, -0.2, 0.1]
+    ps = [oracle.params(sh, lam=l, mu=m, stencil=26, coupling="cf", interp="habel")
+          for sh, l, m in zip(shapes, lams, mus)]
+    dt = min(stable_dt(p) for p in ps)
+    fields = [oracle.init_planar(sh, (1, 2, 0), 0.3, lam=l).astype(np.float32)
+              for sh, l in zip(shapes, lams)]
+    with S.SpfmBatch(shapes, lam=lams, mu=mus, stencil=26, coupling="cf", interp="habel",
+                     dt=dt) as b:
+        for i, f in enumerate(fields):
+            b.set_field(i, f)
+        b.step(20)
+        batch = [b.get_field(i) for i in range(len(shapes))]
+    for sh, l, m, f, got in zip(shapes, lams, mus, fields, batch):
+        with S.Spfm(sh, lam=l, mu=m, stencil=26, coupling="cf", interp="habel", dt=dt,
+                    kernel="tiled", zchunk=32) as s:
+            s.set_field(f)
+            s.step(20)
+            assert np.array_equal(s.get_field().view(np.uint32), got.view(np.uint32))
+
+
+def slab_velocities(S, coupling, interp, lams, mu, *, n=64, dt=0.05, warm=4000, steps=8000):
+    """Batched [100] slabs (3 x 3 x n, two interfaces, 6 neighbours): the mean
+    outward interface velocity of each over the window."""
+    import torch
+    shapes = [(3, 3, n)] * len(lams)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        with S.SpfmBatch(shapes, lam=list(lams), mu=[mu] * len(lams), stencil=6,
+                         coupling=coupling, interp=interp, dt=dt, stream=st) as b:
+            b.init_planar([(1, 0, 0)] * len(lams), [0.37] * len(lams))
+            b.step(warm)
+            d0 = b.diagnostics()
+            b.step(steps)
+            d1 = b.diagnostics()
+    return [(e["interface_position"] - s["interface_position"]) / (e["time"] - s["time"])
+            for s, e in zip(d0, d1)]
+
+
+@pytest.mark.parametrize("interp", ["h3", "h5", "habel"])
+def test_fig6_cf_pins_at_low_resolution_and_drags_at_lambda_4(S, interp):
+    """Fig. 6 on the device: CF is pinned at lambda~ = 2.5 (mu~ = 0.01) and about
+    2e-2 slow at lambda~ = 4, in FP32 as in the FP64 oracle."""
+    v = slab_velocities(S, "cf", interp, (2.5, 4.0), 0.01)
+    print(f"CF+{interp}: v(2.5) = {v[0]:.3e}, err(4) = {v[1] / -0.01 - 1:+.3e}", flush=True)
+    assert abs(v[0]) < 1e-6
+    assert -4e-2 < v[1] / -0.01 - 1.0 < -1e-2
+
+
+def test_fig6_ti_moves_where_cf_pins(S):
+    v = slab_velocities(S, "local", "h3", (2.5, 4.0), 0.01)
+    print(f"TI_n: err(2.5) = {v[0] / -0.01 - 1:+.3e}, err(4) = {v[1] / -0.01 - 1:+.3e}", flush=True)
+    for x in v:
+        assert abs(x / -0.01 - 1.0) < 1e-4

@@ -43,6 +43,8 @@ def test_exports_every_declared_symbol(S):
     (dict(tsteps=2, kernel="plain"), -1),
     (dict(walls=8), -1), (dict(walls=-1), -1), (dict(walls=2, wall_sin=(0, 0, 1.5, 0, 0, 0)), -1),
     (dict(walls=4, wall_sin=(0, 0, 0, 0, 0, float("nan"))), -1), (dict(walls=1, tsteps=2), -1),
+    (dict(interp=3), -1), (dict(interp=-1), -1), (dict(interp="h5"), -1),
+    (dict(interp="habel", coupling="global"), -1),
 ])
 def test_create_rejects_bad_arguments_before_any_hip_call(S, kw, status):
     st, msg = S.try_create((16, 16, 16), **kw)
@@ -98,3 +100,15 @@ def test_walled_planes_count_their_ghosts(S):
     # a stored x-y plane of (2^14 + 2) x 2^15 FP32 values is 2^31 + 2^18 bytes
     st, msg = S.try_create((3, 16384, 32768 - 2), walls=1)
     assert st == -1 and "2^31" in msg
+
+
+@pytest.mark.parametrize("interp", ["h3", "h5", "habel"])
+def test_stability_bound_follows_the_interpolation(S, orc, interp):
+    """The context's bound (get_info on a tiny grid is host-only) equals the oracle's."""
+    p = orc.params((4, 4, 4), lam=2.0, mu=0.4, stencil=26, coupling="cf", interp=interp)
+    st, _ = S.try_create((16, 16, 16), lam=2.0, mu=0.4, coupling="cf", interp=interp,
+                         dt=1.001 * orc.stable_dt(p))
+    assert st == -4
+    st, _ = S.try_create((16, 16, 16), lam=2.0, mu=0.4, coupling="cf", interp=interp,
+                         dt=0.99 * orc.stable_dt(p))
+    assert st != -4
