@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls")
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -183,6 +183,44 @@ def walls_leg(spfm, torch, warm=400, steps=1600):
             "max_rel_velocity_error": worst, "rel_velocity_error": errs}
 
 
+def models_leg(spfm, torch, warm=2000, steps=4000):
+    """The 1D model comparison of the paper's Fig. 6 as batched [100] slabs
+    (3 x 3 x 256 periodic, two interfaces 128 dx apart, 6 neighbours, dt = 0.05,
+    FP32): for each model one launch per step steps the slabs of every
+    lambda~ in {4, 3, 2.5} and mu~ in {0.005, 0.01, 0.02, 0.05}.  Reports the
+    relative error of the mean interface velocity against -M mu / Gamma."""
+    models = [("CF+h3", "cf", "h3"), ("CF+h5", "cf", "h5"), ("CF+h_Abel", "cf", "habel"),
+              ("TI_100+h3", "global", "h3"), ("TI_n+h3", "local", "h3")]
+    cases = [(lam, mu) for lam in (4.0, 3.0, 2.5) for mu in (0.005, 0.01, 0.02, 0.05)]
+    shape, out, total_ms = (3, 3, 256), {}, 0.0
+    for name, coupling, interp in models:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            b = spfm.SpfmBatch([shape] * len(cases), lam=[c[0] for c in cases],
+                               mu=[c[1] for c in cases], stencil=6, coupling=coupling,
+                               interp=interp, dt=0.05, stream=stream)
+            b.init_planar([(1, 0, 0)] * len(cases), [0.37] * len(cases))
+            b.step(warm)
+            d0 = b.diagnostics()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.step(steps)
+            e1.record(stream)
+            d1 = b.diagnostics()
+            total_ms += e0.elapsed_time(e1)
+            b.close()
+        errs = {}
+        for (lam, mu), a, e in zip(cases, d0, d1):
+            v = (e["interface_position"] - a["interface_position"]) / (e["time"] - a["time"])
+            errs[f"lam{lam:g}_mu{mu:g}"] = v / -mu - 1.0
+        out[name] = errs
+    pts = shape[0] * shape[1] * shape[2] * len(cases)
+    return {"value": pts * steps * len(models) / (total_ms * 1e-3) / 1e9, "unit": "GLUPS",
+            "grids_per_launch": len(cases), "steps": steps,
+            "us_per_step": total_ms * 1e3 / (steps * len(models)), "rel_velocity_error": out}
+
+
 def cpu_baseline(w, steps):
     import numpy as np
 
@@ -276,6 +314,8 @@ def main():
         out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
     if args.only in ("", "walls"):
         out["orientation120_walls"] = walls_leg(spfm, torch)
+    if args.only in ("", "models"):
+        out["fig6_models"] = models_leg(spfm, torch)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
