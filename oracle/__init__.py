@@ -95,6 +95,11 @@ def lib():
             L.orc_step_walls.restype = ctypes.c_int
             L.orc_init_front.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, dp,
                                                               ctypes.c_double, dp]
+            L.orc_step_constant_volume.argtypes = [pp, dp, ctypes.c_long, dp]
+            L.orc_step_constant_volume.restype = ctypes.c_int
+            L.orc_init_box.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, dp, dp, dp]
+            L.orc_contour_points.argtypes = [pp, dp, ctypes.c_long, dp]
+            L.orc_contour_points.restype = ctypes.c_long
             L.orc_num_threads.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -266,6 +271,51 @@ def interp(which, phi: float) -> float:
 def interp_prime(which, phi: float) -> float:
     w = INTERPS[which] if isinstance(which, str) else int(which)
     return lib().orc_interp_prime(w, float(phi))
+
+
+def step_constant_volume(p: Params, phi: np.ndarray, nsteps: int):
+    """nsteps forward-Euler steps with the driving force chosen at every step so
+    that sum phi stays constant (Sec. 3.4).  Returns (phi, mu per step)."""
+    _check(p, phi)
+    out = phi.copy()
+    mu = np.empty(int(nsteps))
+    if lib().orc_step_constant_volume(ctypes.byref(p), _dp(out), int(nsteps), _dp(mu)) != 0:
+        raise MemoryError("oracle step allocation failed")
+    return out, mu
+
+
+def init_box(shape, lo, hi, *, dx=1.0, lam=4.0) -> np.ndarray:
+    """Box particle with smooth faces (product of Eq. 3 top hats over the axes)."""
+    nz, ny, nx = shape
+    out = np.empty(shape, dtype=np.float64)
+    a = np.ascontiguousarray(lo, dtype=np.float64)
+    b = np.ascontiguousarray(hi, dtype=np.float64)
+    lib().orc_init_box(nx, ny, nz, dx, lam, _dp(a), _dp(b), _dp(out))
+    return out
+
+
+def contour_points(p: Params, phi: np.ndarray) -> np.ndarray:
+    """phi = 1/2 contour points (x, y, z) on the grid edges (Eq. 8-10, l = 1/2)."""
+    _check(p, phi)
+    n = lib().orc_contour_points(ctypes.byref(p), _dp(phi), 0, None)
+    pts = np.empty((max(n, 1), 3))
+    lib().orc_contour_points(ctypes.byref(p), _dp(phi), n, _dp(pts))
+    return pts[:n]
+
+
+def sphericity(p: Params, phi: np.ndarray):
+    """Residual anisotropy of a particle (Sec. 3.4): barycentre c = sum phi x / sum phi,
+    R_i = |contour point - c|, eps_eff = (R_max - R_min) / (2 R_mean).
+    Returns (eps_eff, R_mean, R_min, R_max, c, number of points)."""
+    nz, ny, nx = phi.shape
+    w = math.fsum(phi.ravel())
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = np.array([math.fsum((phi * xx).ravel()), math.fsum((phi * yy).ravel()),
+                  math.fsum((phi * zz).ravel())]) / w * p.dx
+    pts = contour_points(p, phi)
+    R = np.sqrt(((pts - c) ** 2).sum(axis=1))
+    Rm = math.fsum(R) / R.size
+    return (R.max() - R.min()) / (2 * Rm), Rm, R.min(), R.max(), c, R.size
 
 
 def wall_value(phi_in: float, a: float) -> float:

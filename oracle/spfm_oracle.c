@@ -558,6 +558,84 @@ void orc_init_front(int nx, int ny, int nz, double dx, double lambda, const doub
             }
 }
 
+/* ---- Constant particle volume (Sec. 3.4) ----
+ * The rate of Eq. 2 is affine in the homogeneous driving force:
+ * rate_p(mu) = rate_p(0) - beta mu h'(phi_p), beta = 2M / (3 lambda Gamma).
+ * Reading: the paper imposes mu(t) "such that the integral volume neither
+ * shrinks nor grows"; here mu is chosen at every step so that the forward-Euler
+ * update leaves sum phi unchanged: mu = sum rate(0) / (beta sum h'). */
+int orc_step_constant_volume(const orc_params *p, double *phi, long nsteps, double *mu_out) {
+    long n = (long)p->nx * p->ny * p->nz;
+    double *rate = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!rate) return -1;
+    orc_params q = *p;
+    q.mu = 0.0;
+    const double beta = 2.0 * p->M / (3.0 * p->lambda * p->Gamma);
+    for (long s = 0; s < nsteps; ++s) {
+        orc_rate(&q, phi, rate);
+        acc_t r0 = {0.0, 0.0}, hp = {0.0, 0.0};
+        for (long i = 0; i < n; ++i) {
+            acc_add(&r0, rate[i]);
+            acc_add(&hp, interp_h_prime(p->interp, phi[i]));
+        }
+        const double den = beta * (hp.s + hp.c);
+        const double mu = den != 0.0 ? (r0.s + r0.c) / den : 0.0;
+        if (mu_out) mu_out[s] = mu;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i)
+            phi[i] = phi[i] + p->dt * (rate[i] - beta * mu * interp_h_prime(p->interp, phi[i]));
+    }
+    free(rate);
+    return 0;
+}
+
+/* Box particle: the product over the axes of smooth top hats of Eq. 3,
+ * phi = prod_d t(x_d), t(s) = f(s - lo_d) f(hi_d - s) with f(s) = (1 + tanh(2 s / lambda)) / 2. */
+void orc_init_box(int nx, int ny, int nz, double dx, double lambda, const double lo[3],
+                  const double hi[3], double *phi) {
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double pos[3] = {x * dx, y * dx, z * dx};
+                double v = 1.0;
+                for (int d = 0; d < 3; ++d)
+                    v *= 0.25 * (1.0 + tanh(2.0 * (pos[d] - lo[d]) / lambda)) *
+                         (1.0 + tanh(2.0 * (hi[d] - pos[d]) / lambda));
+                phi[((long)z * ny + y) * nx + x] = v;
+            }
+}
+
+/* phi = 1/2 contour points (Sec. 2.5, Eq. 8-10 at l = 1/2): on every grid edge
+ * (p, p + e_d) of a periodic field whose end values bracket 1/2, the point
+ * p + t e_d with t the zero of the linear interpolation of
+ * psi = (lambda/4) ln((1 - phi)/phi) (R18).  Fills up to maxpts points
+ * (x, y, z; unwrapped: p + t e_d may reach the box edge) and returns the count. */
+long orc_contour_points(const orc_params *p, const double *phi, long maxpts, double *pts) {
+    long cnt = 0;
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const double a = phi[lin(p, x, y, z)];
+                for (int d = 0; d < 3; ++d) {
+                    int q[3] = {x, y, z};
+                    q[d] += 1;
+                    const double b = phi[lin(p, wrap(q[0], p->nx), wrap(q[1], p->ny), wrap(q[2], p->nz))];
+                    if ((a - 0.5) * (b - 0.5) > 0.0 || a == b) continue;
+                    const double pa = 0.25 * p->lambda * log((1.0 - a) / a);
+                    const double pb = 0.25 * p->lambda * log((1.0 - b) / b);
+                    const double t = pa / (pa - pb);
+                    if (cnt < maxpts) {
+                        double *o = pts + 3 * cnt;
+                        o[0] = x * p->dx; o[1] = y * p->dx; o[2] = z * p->dx;
+                        o[d] += t * p->dx;
+                    }
+                    ++cnt;
+                }
+            }
+    return cnt;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

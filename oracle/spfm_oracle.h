@@ -91,6 +91,14 @@ int orc_step_walls(const orc_params *p, int walls, const double sin_alpha[6], do
 /* Single planar front of Eq. 3 (not periodic). */
 void orc_init_front(int nx, int ny, int nz, double dx, double lambda, const double n[3],
                     double offset, double *phi);
+/* nsteps forward-Euler steps at constant sum phi: mu chosen at every step;
+ * mu_out (nsteps values) may be NULL.  Returns 0, or -1 on allocation failure. */
+int orc_step_constant_volume(const orc_params *p, double *phi, long nsteps, double *mu_out);
+/* Box particle [lo, hi] (coordinates in units of length) with smooth faces. */
+void orc_init_box(int nx, int ny, int nz, double dx, double lambda, const double lo[3],
+                  const double hi[3], double *phi);
+/* phi = 1/2 contour points on the grid edges; returns their number. */
+long orc_contour_points(const orc_params *p, const double *phi, long maxpts, double *pts);
 int orc_num_threads(void);
 
 #ifdef __cplusplus
