@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models")
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models | cube")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -221,6 +221,36 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
             "us_per_step": total_ms * 1e3 / (steps * len(models)), "rel_velocity_error": out}
 
 
+def cube_leg(spfm, torch, steps=3000):
+    """The residual-anisotropy study of the paper's Fig. 9 on its 60^3 grid: a
+    cube particle (edge 30 dx) relaxed at constant volume (mu chosen on the
+    device at every step), FP32, 26 neighbours; TI_n at lambda~ = 4 and 2 and
+    CF at lambda~ = 2.  Reports eps_eff of the phi = 1/2 contour and the step rate."""
+    n, edge = 60, 30.0
+    lo = (n - edge) / 2 + 0.25
+    out, total_ms = {}, 0.0
+    for name, lam, coupling in (("TI_n_lam4", 4.0, "local"), ("TI_n_lam2", 2.0, "local"),
+                                ("CF_lam2", 2.0, "cf")):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm((n, n, n), lam=lam, mu=-0.1, stencil=26, coupling=coupling,
+                          conserve_volume=True, stream=stream)
+            s.init_box((lo, lo, lo), (lo + edge, lo + edge, lo + edge))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            c = s.contour_stats()
+            d = s.diagnostics()
+            total_ms += e0.elapsed_time(e1)
+            s.close()
+        out[name] = {"eps_eff": c["eps_eff"], "R_mean": c["R_mean"], "mu": d["mu"]}
+    pts = n ** 3
+    return {"value": pts * steps * 3 / (total_ms * 1e-3) / 1e9, "unit": "GLUPS", "grid": "60^3",
+            "steps": steps, "us_per_step": total_ms * 1e3 / (3 * steps), "runs": out}
+
+
 def cpu_baseline(w, steps):
     import numpy as np
 
@@ -316,6 +346,8 @@ def main():
         out["orientation120_walls"] = walls_leg(spfm, torch)
     if args.only in ("", "models"):
         out["fig6_models"] = models_leg(spfm, torch)
+    if args.only in ("", "cube"):
+        out["fig9_cube60"] = cube_leg(spfm, torch)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -112,6 +112,9 @@ typedef struct {
                            1 = h5 = phi^3 (10 - 15 phi + 6 phi^2),
                            2 = h_Abel = phi^2 / (phi^2 + (1 - phi)^2); 1 and 2 only with
                            coupling CF (the comparisons of Sec. 3.1), else SPFM_E_INVAL */
+    int32_t conserve_volume; /* nonzero: the homogeneous driving force is chosen at every step so
+                           that sum phi stays constant (Sec. 3.4; mu at create only sets the
+                           stability check); periodic grids, tsteps <= 1, not in batches */
 } spfm_options;
 
 typedef struct {
@@ -127,6 +130,8 @@ typedef struct {
     double phi_min, phi_max;
     double sum_phi, sum_x;     /* the raw sums: sum phi, sum phi(1-phi) */
     int32_t diverged;          /* number of points non-finite or |phi| > 2 */
+    double mu;                 /* driving force of the last step: the fixed mu, or with
+                                  conserve_volume the value chosen (NaN before the first step) */
 } spfm_diag;
 
 /* Parameters the library resolved at create time. */
@@ -140,7 +145,20 @@ typedef struct {
     int32_t tsteps;            /* steps per fused launch (1 = no temporal blocking) */
     int32_t walls;             /* walled axes (bit mask) */
     int32_t interp;            /* interpolation function (spfm_options.interp) */
+    int32_t conserve_volume;
 } spfm_info;
+
+/* Shape of a particle from its phi = 1/2 contour (Sec. 3.4, Eq. 8-10 at
+ * l = 1/2): contour points on the grid edges, distances from the barycentre
+ * sum phi x / sum phi, eps_eff = (R_max - R_min) / (2 R_mean).  Lengths in
+ * units of dx * (grid index); one particle not crossing the periodic box
+ * faces is assumed. */
+typedef struct {
+    double centre[3];
+    int64_t points;
+    double R_mean, R_min, R_max;
+    double eps_eff;
+} spfm_contour;
 
 typedef struct spfm_ctx spfm_ctx;
 typedef struct spfm_batch spfm_batch;
@@ -192,6 +210,13 @@ spfm_status spfm_init_spheres(spfm_ctx *ctx, int32_t n, const double *centers,
  * taken as the box cross-section across the axis of the largest |n_d|,
  * divided by |n_d|/|n|). */
 spfm_status spfm_init_front(spfm_ctx *ctx, const double n[3], double offset);
+/* Box particle with smooth faces: phi = prod_d f(x_d - lo_d) f(hi_d - x_d),
+ * f(s) = (1 + tanh(2 s / lambda)) / 2 (Eq. 3), lengths in units of length
+ * (x_d = grid index times dx).  lo < hi on every axis. */
+spfm_status spfm_init_box(spfm_ctx *ctx, const double lo[3], const double hi[3]);
+/* Contour statistics of the current field (FP64 reductions on the device;
+ * synchronises).  SPFM_E_STATE for walled grids. */
+spfm_status spfm_contour_stats(spfm_ctx *ctx, spfm_contour *out);
 
 /* Change the driving force (re-checks the stability bound). */
 spfm_status spfm_set_mu(spfm_ctx *ctx, double mu);

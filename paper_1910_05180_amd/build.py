@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["step_kernels.hip", "temporal.hip", "walls.hip", "reduce.hip", "init.hip", "host_math.cpp",
-           "api.cpp"]
+SOURCES = ["step_kernels.hip", "temporal.hip", "walls.hip", "volume.hip", "reduce.hip", "init.hip",
+           "host_math.cpp", "api.cpp"]
 LIB = os.path.join(HERE, "libspfm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 

@@ -44,6 +44,7 @@ struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
     int tsteps;   // steps per launch (temporal blocking), 1 = one step
+    int conserve_volume;   // mu chosen at every step so that sum phi is constant
     int walls;    // bit d: contact-angle walls on axis d
     double wall_sin[6];
     int sx, sy, sz;   // stored dims: the grid plus one ghost layer per end of a walled axis
@@ -72,6 +73,8 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
             if (!(std::fabs(o.wall_sin[f]) <= 1.0))
                 return fail(SPFM_E_INVAL, "wall_sin[%d] must be in [-1, 1]", f);
     if (o.walls && o.tsteps > 1) return fail(SPFM_E_INVAL, "walls need one step per launch (tsteps <= 1)");
+    if (o.conserve_volume && (o.walls || o.tsteps > 1))
+        return fail(SPFM_E_INVAL, "constant volume needs a periodic grid and one step per launch");
     // Stored dims.  The tiled kernels address one z-plane through a buffer
     // descriptor with 32-bit byte offsets.
     const int sx = g->nx + 2 * (o.walls & 1), sy = g->ny + 2 * ((o.walls >> 1) & 1),
@@ -122,6 +125,7 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     r->allow_unstable = o.allow_unstable;
     r->tsteps = o.tsteps > 1 ? o.tsteps : 1;
     r->walls = o.walls;
+    r->conserve_volume = o.conserve_volume ? 1 : 0;
     for (int f = 0; f < 6; ++f) r->wall_sin[f] = ((o.walls >> (f / 2)) & 1) ? o.wall_sin[f] : 0.0;
     r->sx = sx; r->sy = sy; r->sz = sz;
     if (o.interp < kH3 || o.interp > kHAbel) return fail(SPFM_E_INVAL, "unknown interp %d", o.interp);
@@ -258,6 +262,16 @@ struct spfm_ctx {
     WallCoef<float> wf;
     WallCoef<double> wd;
     int64_t nghost = 0;
+    // Constant volume: coefficients without the driving force, and device
+    // scratch for the reductions (kReduceBlocks x 8 partials, then g, mu, then
+    // the 7 contour results).
+    StepCoef<float> kf0;
+    StepCoef<double> kd0;
+    double* d_scratch = nullptr;
+    double* d_part() const { return d_scratch; }
+    double* d_state() const { return d_scratch + (size_t)kReduceBlocks * 8; }
+    double* d_contour() const { return d_state() + 2; }
+    static constexpr size_t kScratchDoubles = (size_t)kReduceBlocks * 8 + 2 + 7;
 
     // Grid points (the interior when there are walls) and the stored field.
     int64_t points() const { return (int64_t)r.p.nx * r.p.ny * r.p.nz; }
@@ -317,14 +331,26 @@ struct spfm_ctx {
                                      : launch_fill_walls<float>((float*)buf[from], wf, nghost, stream);
             if (e != hipSuccess) return e;
         }
+        const StepCoef<double>& cd = r.conserve_volume ? kd0 : kd;
+        const StepCoef<float>& cf = r.conserve_volume ? kf0 : kf;
+        hipError_t e;
         if (r.dtype == SPFM_F64) {
-            return r.kernel == SPFM_KERNEL_PLAIN
-                       ? launch_step_plain<double>((const double*)in, (double*)out, kd, S, C, stream)
-                       : launch_step_tiled<double>((const double*)in, (double*)out, kd, S, C, zlen, stream);
+            e = r.kernel == SPFM_KERNEL_PLAIN
+                    ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
+                    : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, zlen, stream);
+        } else {
+            e = r.kernel == SPFM_KERNEL_PLAIN
+                    ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
+                    : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, zlen, stream);
         }
-        return r.kernel == SPFM_KERNEL_PLAIN
-                   ? launch_step_plain<float>((const float*)in, (float*)out, kf, S, C, stream)
-                   : launch_step_tiled<float>((const float*)in, (float*)out, kf, S, C, zlen, stream);
+        if (e != hipSuccess || !r.conserve_volume) return e;
+        // the step ran without the driving force; add the one that keeps sum phi
+        const double dt_beta = r.p.dt * 2.0 * r.p.M / (3.0 * r.p.lambda * r.p.Gamma);
+        return r.dtype == SPFM_F64
+                   ? launch_cv_correct<double>((const double*)in, (double*)out, points(), r.p.interp,
+                                               dt_beta, d_part(), d_state(), stream)
+                   : launch_cv_correct<float>((const float*)in, (float*)out, points(), r.p.interp,
+                                              dt_beta, d_part(), d_state(), stream);
     }
     void refresh_coef() {
         kf = make_coef<float>(r.p);
@@ -332,6 +358,13 @@ struct spfm_ctx {
         kf.nx = kd.nx = r.sx;   // the kernels sweep the stored grid
         kf.ny = kd.ny = r.sy;
         kf.nz = kd.nz = r.sz;
+        Params p0 = r.p;
+        p0.mu = 0.0;
+        kf0 = make_coef<float>(p0);
+        kd0 = make_coef<double>(p0);
+        kf0.nx = kd0.nx = r.sx;
+        kf0.ny = kd0.ny = r.sy;
+        kf0.nz = kd0.nz = r.sz;
         wf.sx = wd.sx = r.sx;
         wf.sy = wd.sy = r.sy;
         wf.sz = wd.sz = r.sz;
@@ -530,6 +563,11 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     }
     st = c->red.init();
     if (st != SPFM_OK) { spfm_destroy(c); return st; }
+    if (hipMalloc(&c->d_scratch, sizeof(double) * spfm_ctx::kScratchDoubles) != hipSuccess) {
+        (void)hipGetLastError();
+        spfm_destroy(c);
+        return fail(SPFM_E_NOMEM, "device allocation of the reduction scratch failed");
+    }
     c->refresh_coef();
     *out = c;
     return SPFM_OK;
@@ -540,6 +578,7 @@ void spfm_destroy(spfm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
     c->graphs.clear();
     c->red.release();
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->owns) {
         if (c->buf[0]) (void)hipFree(c->buf[0]);
         if (c->buf[1]) (void)hipFree(c->buf[1]);
@@ -651,6 +690,47 @@ spfm_status spfm_init_front(spfm_ctx* c, const double n[3], double offset) {
     return SPFM_OK;
 }
 
+spfm_status spfm_init_box(spfm_ctx* c, const double lo[3], const double hi[3]) {
+    if (!c || !lo || !hi) return fail(SPFM_E_INVAL, "NULL argument");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(hi[d] > lo[d]))
+            return fail(SPFM_E_INVAL, "box must have finite lo < hi");
+    const Params& p = c->r.p;
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
+    hipError_t e = c->r.dtype == SPFM_F64
+                       ? launch_init_box<double>((double*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, lo, hi,
+                                                 c->stream)
+                       : launch_init_box<float>((float*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, lo, hi,
+                                                c->stream);
+    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "box init: %s", hipGetErrorString(e));
+    c->nsteps = 0;
+    c->track.reset(0, 0.0);
+    return SPFM_OK;
+}
+
+spfm_status spfm_contour_stats(spfm_ctx* c, spfm_contour* out) {
+    if (!c || !out) return fail(SPFM_E_INVAL, "NULL argument");
+    if (c->r.walls) return fail(SPFM_E_STATE, "contour statistics need a periodic grid");
+    const Params& p = c->r.p;
+    hipError_t e = c->r.dtype == SPFM_F64
+                       ? launch_contour_stats<double>((const double*)c->buf[c->cur], p.nx, p.ny, p.nz,
+                                                      c->d_part(), c->d_contour(), c->stream)
+                       : launch_contour_stats<float>((const float*)c->buf[c->cur], p.nx, p.ny, p.nz,
+                                                     c->d_part(), c->d_contour(), c->stream);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "contour statistics: %s", hipGetErrorString(e));
+    double h[7];
+    HIP_TRY(hipMemcpyAsync(h, c->d_contour(), sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 3; ++k) out->centre[k] = h[k] * p.dx;
+    out->points = (int64_t)h[3];
+    out->R_mean = h[3] > 0.0 ? h[4] / h[3] * p.dx : NAN;
+    out->R_min = h[3] > 0.0 ? h[5] * p.dx : NAN;
+    out->R_max = h[3] > 0.0 ? h[6] * p.dx : NAN;
+    out->eps_eff = h[3] > 0.0 ? (out->R_max - out->R_min) / (2.0 * out->R_mean) : NAN;
+    return SPFM_OK;
+}
+
 spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
@@ -683,6 +763,16 @@ spfm_status spfm_diagnostics(spfm_ctx* c, spfm_diag* out) {
     spfm_status st = c->red.run(field, c->r.dtype, c->points(), c->stream);
     if (st != SPFM_OK) return st;
     c->track.fill(out, *c->red.h_out, c->r.p.dx, c->r.p.lambda, c->nsteps, c->r.p.dt);
+    out->mu = c->r.p.mu;
+    if (c->r.conserve_volume) {
+        if (c->nsteps == 0) {
+            out->mu = NAN;   // no step taken yet
+        } else {
+            HIP_TRY(hipMemcpyAsync(&out->mu, c->d_state() + 1, sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+    }
     if (out->diverged) return fail(SPFM_E_DIVERGED, "%d points are non-finite or |phi| > 2", out->diverged);
     return SPFM_OK;
 }
@@ -699,6 +789,7 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     o->tsteps = c->r.tsteps;
     o->walls = c->r.walls;
     o->interp = c->r.p.interp;
+    o->conserve_volume = c->r.conserve_volume;
     return SPFM_OK;
 }
 
@@ -731,6 +822,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
     if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
     if (o.walls) return fail(SPFM_E_INVAL, "batches are periodic (walls = 0)");
+    if (o.conserve_volume) return fail(SPFM_E_INVAL, "batches keep mu fixed (conserve_volume = 0)");
     spfm_batch* b = new (std::nothrow) spfm_batch;
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;

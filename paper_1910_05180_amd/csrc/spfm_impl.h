@@ -363,6 +363,19 @@ template <typename T>
 hipError_t launch_init_front(T* phi, int nx, int ny, int nz, double dx, double lambda,
                              const double n[3], double offset, hipStream_t s);
 
+// Constant volume and contour statistics (volume.hip).  d_part holds
+// kReduceBlocks x 8 doubles; d_state 2 doubles (g, mu); d_out 7 doubles
+// (barycentre x, y, z, then count, sum R, min R, max R in grid units).
+template <typename T>
+hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
+                             double* d_part, double* d_state, hipStream_t s);
+template <typename T>
+hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_init_box(T* phi, int nx, int ny, int nz, double dx, double lambda,
+                           const double lo[3], const double hi[3], hipStream_t s);
+
 struct ReduceOut {   // device result of the diagnostics reduction
     double sum_phi, sum_x;
     double phi_min, phi_max;

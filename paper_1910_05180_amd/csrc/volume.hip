@@ -1,0 +1,314 @@
+// Constant particle volume (Sec. 3.4) and the phi = 1/2 contour statistics
+// that measure the residual anisotropy of a relaxed particle.
+//
+// Constant volume.  The rate of Eq. 2 is affine in the homogeneous driving
+// force, rate(mu) = rate(0) - beta mu h'(phi), beta = 2M / (3 lambda Gamma).  A
+// step is the ordinary step kernel with mu = 0, writing phi* = phi + dt rate(0),
+// followed by three launches that never leave the device:
+//   k_cv_partial  per-block FP64 compensated sums of phi* - phi and h'(phi);
+//   k_cv_final    g = sum(phi* - phi) / sum h'(phi) and mu = g / (dt beta),
+//                 stored in device memory;
+//   k_cv_apply    phi_new = phi* - g h'(phi), evaluated in FP64.
+// Then sum phi_new = sum phi up to the rounding of the stored values.
+//
+// Contours.  On every grid edge (p, p + e_d) whose end values bracket 1/2 the
+// contour point is p + t e_d with t the zero of the linear interpolation of
+// ln((1 - phi)/phi) (Eq. 8-10 at l = 1/2).  Two passes: the barycentre
+// sum phi x / sum phi, then count, sum, min and max of the distances of the
+// contour points from it.
+#include "spfm_impl.h"
+
+namespace spfm {
+
+namespace {
+
+struct Acc {   // TwoSum accumulator
+    double s, c;
+    __device__ __forceinline__ void add(double v) {
+        const double t = s + v;
+        const double bp = t - s;
+        c += (s - (t - bp)) + (v - bp);
+        s = t;
+    }
+    __device__ __forceinline__ void merge(double os, double oc) {
+        add(os);
+        c += oc;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+__device__ __forceinline__ double h_prime(int interp, double phi) {
+    const double x = phi * (1.0 - phi);
+    if (interp == kH5) return 30.0 * x * x;
+    if (interp == kHAbel) {
+        const double d = 1.0 - 2.0 * x;
+        return 2.0 * x / (d * d);
+    }
+    return 6.0 * x;
+}
+
+// Block sums of NQ (s, c) pairs plus NM min and max values, in a fixed order:
+// wave butterflies, then thread 0 over the waves.  Returns on thread 0.
+template <int NQ>
+__device__ __forceinline__ void block_sums(Acc (&a)[NQ], double& mn, double& mx) {
+    for (int m = 32; m > 0; m >>= 1) {
+        for (int q = 0; q < NQ; ++q) {
+            const double os = __shfl_xor(a[q].s, m), oc = __shfl_xor(a[q].c, m);
+            a[q].merge(os, oc);
+        }
+        mn = fmin(mn, __shfl_xor(mn, m));
+        mx = fmax(mx, __shfl_xor(mx, m));
+    }
+    __shared__ double sh[kReduceThreads / 64][2 * NQ + 2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        for (int q = 0; q < NQ; ++q) { sh[wave][2 * q] = a[q].s; sh[wave][2 * q + 1] = a[q].c; }
+        sh[wave][2 * NQ] = mn;
+        sh[wave][2 * NQ + 1] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kReduceThreads / 64; ++w) {
+            for (int q = 0; q < NQ; ++q) a[q].merge(sh[w][2 * q], sh[w][2 * q + 1]);
+            mn = fmin(mn, sh[w][2 * NQ]);
+            mx = fmax(mx, sh[w][2 * NQ + 1]);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void k_cv_partial(const T* __restrict__ phi_old,
+                                                               const T* __restrict__ phi_new,
+                                                               int64_t n, int interp,
+                                                               double* __restrict__ part) {
+    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    double mn = 0.0, mx = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride) {
+        const double o = (double)phi_old[i];
+        a[0].add((double)phi_new[i] - o);
+        a[1].add(h_prime(interp, o));
+    }
+    block_sums<2>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        double* q = part + (size_t)blockIdx.x * 4;
+        q[0] = a[0].s; q[1] = a[0].c; q[2] = a[1].s; q[3] = a[1].c;
+    }
+}
+
+// state[0] = g (the correction per unit h'), state[1] = mu.
+__global__ __launch_bounds__(kReduceThreads) void k_cv_final(const double* __restrict__ part,
+                                                             int nparts, double dt_beta,
+                                                             double* __restrict__ state) {
+    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    double mn = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) {
+        const double* q = part + (size_t)b * 4;
+        a[0].merge(q[0], q[1]);
+        a[1].merge(q[2], q[3]);
+    }
+    block_sums<2>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        const double den = a[1].value();
+        const double g = den != 0.0 ? a[0].value() / den : 0.0;
+        state[0] = g;
+        state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cv_apply(T* __restrict__ phi_new, const T* __restrict__ phi_old,
+                                                  int64_t n, int interp,
+                                                  const double* __restrict__ state) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double g = state[0];
+    phi_new[i] = (T)((double)phi_new[i] - g * h_prime(interp, (double)phi_old[i]));
+}
+
+// Pass 1 of the contour statistics: sum phi, sum phi x, sum phi y, sum phi z.
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void k_moments_partial(const T* __restrict__ phi, int nx,
+                                                                    int ny, int nz,
+                                                                    double* __restrict__ part) {
+    Acc a[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    double mn = 0.0, mx = 0.0;
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride) {
+        const double v = (double)phi[i];
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        a[0].add(v);
+        a[1].add(v * x);
+        a[2].add(v * y);
+        a[3].add(v * z);
+    }
+    block_sums<4>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        double* q = part + (size_t)blockIdx.x * 8;
+        for (int k = 0; k < 4; ++k) { q[2 * k] = a[k].s; q[2 * k + 1] = a[k].c; }
+    }
+}
+
+// centre[0..2] = barycentre in grid units.
+__global__ __launch_bounds__(kReduceThreads) void k_moments_final(const double* __restrict__ part,
+                                                                  int nparts,
+                                                                  double* __restrict__ centre) {
+    Acc a[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    double mn = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) {
+        const double* q = part + (size_t)b * 8;
+        for (int k = 0; k < 4; ++k) a[k].merge(q[2 * k], q[2 * k + 1]);
+    }
+    block_sums<4>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        const double w = a[0].value();
+        for (int k = 0; k < 3; ++k) centre[k] = a[k + 1].value() / w;
+    }
+}
+
+// Pass 2: count, sum, min and max of the contour-point distances from the centre.
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void k_contour_partial(const T* __restrict__ phi, int nx,
+                                                                    int ny, int nz,
+                                                                    const double* __restrict__ centre,
+                                                                    double* __restrict__ part) {
+    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};   // count, sum R
+    double mn = INFINITY, mx = -INFINITY;
+    const double c[3] = {centre[0], centre[1], centre[2]};
+    const int dims[3] = {nx, ny, nz};
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride) {
+        const int p[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((int64_t)nx * ny))};
+        const double va = (double)phi[i];
+        for (int d = 0; d < 3; ++d) {
+            int q[3] = {p[0], p[1], p[2]};
+            q[d] = q[d] + 1 == dims[d] ? 0 : q[d] + 1;
+            const double vb = (double)phi[((int64_t)q[2] * ny + q[1]) * nx + q[0]];
+            if ((va - 0.5) * (vb - 0.5) > 0.0 || va == vb) continue;
+            const double la = log((1.0 - va) / va), lb = log((1.0 - vb) / vb);
+            const double t = la / (la - lb);
+            double r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double xk = (double)p[k] + (k == d ? t : 0.0) - c[k];
+                r2 += xk * xk;
+            }
+            const double R = sqrt(r2);
+            a[0].add(1.0);
+            a[1].add(R);
+            mn = fmin(mn, R);
+            mx = fmax(mx, R);
+        }
+    }
+    block_sums<2>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        double* q = part + (size_t)blockIdx.x * 6;
+        q[0] = a[0].s; q[1] = a[0].c; q[2] = a[1].s; q[3] = a[1].c; q[4] = mn; q[5] = mx;
+    }
+}
+
+// out[0..3] = count, sum R, min R, max R (grid units).
+__global__ __launch_bounds__(kReduceThreads) void k_contour_final(const double* __restrict__ part,
+                                                                  int nparts,
+                                                                  double* __restrict__ out) {
+    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    double mn = INFINITY, mx = -INFINITY;
+    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) {
+        const double* q = part + (size_t)b * 6;
+        a[0].merge(q[0], q[1]);
+        a[1].merge(q[2], q[3]);
+        mn = fmin(mn, q[4]);
+        mx = fmax(mx, q[5]);
+    }
+    block_sums<2>(a, mn, mx);
+    if (threadIdx.x == 0) {
+        out[0] = a[0].value();
+        out[1] = a[1].value();
+        out[2] = mn;
+        out[3] = mx;
+    }
+}
+
+__device__ __forceinline__ double rising(double s, double four_over_lambda) {
+    return 1.0 / (1.0 + exp(-four_over_lambda * s));
+}
+
+// Box particle: product over the axes of f(x - lo) f(hi - x), f the rising
+// profile of Eq. 3 (f(s) = (1 + tanh(2 s / lambda)) / 2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_box(T* __restrict__ phi, int nx, int ny, int nz,
+                                                  double dx, double fol, double lx, double ly,
+                                                  double lz, double hx, double hy, double hz) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)nx * ny * nz) return;
+    const double pos[3] = {dx * (double)(i % nx), dx * (double)((i / nx) % ny),
+                           dx * (double)(i / ((int64_t)nx * ny))};
+    const double lo[3] = {lx, ly, lz}, hi[3] = {hx, hy, hz};
+    double v = 1.0;
+    for (int d = 0; d < 3; ++d) v *= rising(pos[d] - lo[d], fol) * rising(hi[d] - pos[d], fol);
+    phi[i] = (T)v;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
+                             double* d_part, double* d_state, hipStream_t s) {
+    hipLaunchKernelGGL((k_cv_partial<T>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, phi_old,
+                       phi_new, n, interp, d_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cv_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, kReduceBlocks, dt_beta,
+                       d_state);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cv_apply<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi_new,
+                       phi_old, n, interp, d_state);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
+                                hipStream_t s) {
+    // d_out[0..2]: barycentre, d_out[3..6]: count, sum R, min R, max R
+    hipLaunchKernelGGL((k_moments_partial<T>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, phi,
+                       nx, ny, nz, d_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, kReduceBlocks,
+                       d_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_contour_partial<T>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, phi,
+                       nx, ny, nz, d_out, d_part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_contour_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, kReduceBlocks,
+                       d_out + 3);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_box(T* phi, int nx, int ny, int nz, double dx, double lambda,
+                           const double lo[3], const double hi[3], hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL((k_init_box<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi, nx,
+                       ny, nz, dx, 4.0 / lambda, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cv_correct<float>(const float*, float*, int64_t, int, double, double*,
+                                             double*, hipStream_t);
+template hipError_t launch_cv_correct<double>(const double*, double*, int64_t, int, double, double*,
+                                              double*, hipStream_t);
+template hipError_t launch_contour_stats<float>(const float*, int, int, int, double*, double*,
+                                                hipStream_t);
+template hipError_t launch_contour_stats<double>(const double*, int, int, int, double*, double*,
+                                                 hipStream_t);
+template hipError_t launch_init_box<float>(float*, int, int, int, double, double, const double*,
+                                           const double*, hipStream_t);
+template hipError_t launch_init_box<double>(double*, int, int, int, double, double, const double*,
+                                            const double*, hipStream_t);
+
+}  // namespace spfm

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
                 ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6),
-                ("interp", ctypes.c_int32)]
+                ("interp", ctypes.c_int32), ("conserve_volume", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -50,7 +50,7 @@ class Diag(ctypes.Structure):
                 ("interface_position", ctypes.c_double), ("velocity", ctypes.c_double),
                 ("phi_min", ctypes.c_double), ("phi_max", ctypes.c_double),
                 ("sum_phi", ctypes.c_double), ("sum_x", ctypes.c_double),
-                ("diverged", ctypes.c_int32)]
+                ("diverged", ctypes.c_int32), ("mu", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -63,7 +63,14 @@ class Info(ctypes.Structure):
                 ("stencil", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
-                ("walls", ctypes.c_int32), ("interp", ctypes.c_int32)]
+                ("walls", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("conserve_volume", ctypes.c_int32)]
+
+
+class Contour(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double * 3), ("points", ctypes.c_int64),
+                ("R_mean", ctypes.c_double), ("R_min", ctypes.c_double), ("R_max", ctypes.c_double),
+                ("eps_eff", ctypes.c_double)]
 
 
 class SpfmError(RuntimeError):
@@ -97,6 +104,8 @@ def load():
         "spfm_init_planar": ([vp, ip, d], ctypes.c_int),
         "spfm_init_spheres": ([vp, i32, dp, dp], ctypes.c_int),
         "spfm_init_front": ([vp, dp, d], ctypes.c_int),
+        "spfm_init_box": ([vp, dp, dp], ctypes.c_int),
+        "spfm_contour_stats": ([vp, ctypes.POINTER(Contour)], ctypes.c_int),
         "spfm_set_mu": ([vp, d], ctypes.c_int),
         "spfm_step": ([vp, i64], ctypes.c_int),
         "spfm_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
@@ -151,7 +160,7 @@ def _stream_handle(stream):
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
              allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None,
-             interp="h3") -> Options:
+             interp="h3", conserve_volume=False) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -169,6 +178,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.walls = _walls_mask(walls)
     o.wall_sin[:] = [float(v) for v in wall_sin] if wall_sin is not None else [0.0] * 6
     o.interp = _INTERPS[interp] if isinstance(interp, str) else int(interp)
+    o.conserve_volume = 1 if conserve_volume else 0
     return o
 
 
@@ -269,6 +279,19 @@ class Spfm:
         assert c.shape[0] == r.size
         dp = ctypes.POINTER(ctypes.c_double)
         _check(load().spfm_init_spheres(self._h, r.size, c.ctypes.data_as(dp), r.ctypes.data_as(dp)))
+
+    def init_box(self, lo, hi):
+        a = np.ascontiguousarray(lo, dtype=np.float64).reshape(3)
+        b = np.ascontiguousarray(hi, dtype=np.float64).reshape(3)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().spfm_init_box(self._h, a.ctypes.data_as(dp), b.ctypes.data_as(dp)))
+
+    def contour_stats(self) -> dict:
+        c = Contour()
+        _check(load().spfm_contour_stats(self._h, ctypes.byref(c)))
+        out = {n: getattr(c, n) for n, _ in Contour._fields_}
+        out["centre"] = tuple(c.centre)
+        return out
 
     def init_front(self, n, offset: float = 0.0):
         v = np.ascontiguousarray(n, dtype=np.float64).reshape(3)

@@ -45,6 +45,7 @@ def test_exports_every_declared_symbol(S):
     (dict(walls=4, wall_sin=(0, 0, 0, 0, 0, float("nan"))), -1), (dict(walls=1, tsteps=2), -1),
     (dict(interp=3), -1), (dict(interp=-1), -1), (dict(interp="h5"), -1),
     (dict(interp="habel", coupling="global"), -1),
+    (dict(conserve_volume=True, walls=1), -1), (dict(conserve_volume=True, tsteps=2), -1),
 ])
 def test_create_rejects_bad_arguments_before_any_hip_call(S, kw, status):
     st, msg = S.try_create((16, 16, 16), **kw)
