@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models | cube")
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models | "
+                         "cube | friction")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -251,6 +252,35 @@ def cube_leg(spfm, torch, steps=3000):
             "steps": steps, "us_per_step": total_ms * 1e3 / (3 * steps), "runs": out}
 
 
+def friction_leg(spfm):
+    """The grid friction force study of the paper's Fig. 3: oscillation
+    amplitude of the total force on an ideal front moved through the grid (12
+    positions over one grid spacing) in the 300 x 1 x 1 system, for CF,
+    TI_<120> and TI_n at lambda~ = 1 and 3, orientations about [001] and [011]
+    from 0 to 75 degrees every 15 (FP64, 26 neighbours, one step per position).
+    The line crosses the front once; as n_x -> 0 the line sum (which counts
+    1/n_x of the front per unit area) diverges, so 90 degrees is left out."""
+    import math
+    import time
+
+    from paper_1910_05180_amd import friction
+    u120 = (1 / math.sqrt(5), 2 / math.sqrt(5), 0.0)
+    models = (("CF", "cf", (1.0, 0.0, 0.0)), ("TI_120", "global", u120), ("TI_n", "local", (1.0, 0.0, 0.0)))
+    out, t0 = {}, time.perf_counter()
+    for lam in (1.0, 3.0):
+        for name, coupling, u in models:
+            row = {}
+            for axis in ("001", "011"):
+                for deg in range(0, 76, 15):
+                    t = math.radians(deg)
+                    n = (math.cos(t), math.sin(t), 0.0) if axis == "001" else \
+                        (math.cos(t), math.sin(t) / math.sqrt(2), math.sin(t) / math.sqrt(2))
+                    row[f"{axis}:{deg}"] = friction.amplitude(spfm, coupling=coupling, lam=lam, n=n, u=u)
+            out[f"{name}_lam{lam:g}"] = row
+    return {"amplitude": out, "wall_s": time.perf_counter() - t0,
+            "system": "300x1x1 between exact contact-angle walls, FP64"}
+
+
 def cpu_baseline(w, steps):
     import numpy as np
 
@@ -348,6 +378,8 @@ def main():
         out["fig6_models"] = models_leg(spfm, torch)
     if args.only in ("", "cube"):
         out["fig9_cube60"] = cube_leg(spfm, torch)
+    if args.only in ("", "friction"):
+        out["fig3_friction"] = friction_leg(spfm)
     if not args.no_cpu and f32 is not None:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

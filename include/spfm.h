@@ -70,7 +70,7 @@ typedef enum { SPFM_LOCAL = 0, SPFM_GLOBAL = 1, SPFM_CF = 2 } spfm_coupling;
 typedef enum { SPFM_KERNEL_AUTO = 0, SPFM_KERNEL_PLAIN = 1, SPFM_KERNEL_TILED = 2 } spfm_kernel;
 
 typedef struct {
-    int32_t nx, ny, nz; /* grid points per axis, each >= 3; periodic */
+    int32_t nx, ny, nz; /* grid points per axis: >= 3 on periodic axes, >= 1 on walled axes */
     double dx;          /* grid spacing, > 0 */
 } spfm_grid;
 
@@ -167,7 +167,7 @@ typedef struct spfm_batch spfm_batch;
  * lambda: interface width (Eq. 3), Gamma: interface energy, M: kinetic
  * coefficient, mu: driving force (Eq. 1-2); stencil: 6, 18 or 26.
  * Returns SPFM_E_INVAL for non-positive lambda, Gamma, M or dx, an unknown
- * stencil, coupling or dtype, a grid edge below 3, a grid too large (one
+ * stencil, coupling or dtype, a grid edge below 3 (below 1 on a walled axis), a grid too large (one
  * stored z-plane of 2^31 bytes or more, ny > 262140 or nz > 65535), a walls mask
  * outside 0..7 or |wall_sin| > 1 on a walled axis, walls with tsteps > 1,
  * a zero GLOBAL direction,

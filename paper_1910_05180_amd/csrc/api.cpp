@@ -57,8 +57,12 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
     if (!g) return fail(SPFM_E_INVAL, "grid is NULL");
     spfm_options o;
     if (opt) o = *opt; else std::memset(&o, 0, sizeof o);
-    if (g->nx < 3 || g->ny < 3 || g->nz < 3)
-        return fail(SPFM_E_INVAL, "grid edges must be >= 3 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+    // A periodic axis needs 3 points; a walled one 1 (its ghost layers complete the stencil).
+    const int wmask = opt ? opt->walls : 0;
+    const int emin[3] = {(wmask & 1) ? 1 : 3, (wmask & 2) ? 1 : 3, (wmask & 4) ? 1 : 3};
+    if (g->nx < emin[0] || g->ny < emin[1] || g->nz < emin[2])
+        return fail(SPFM_E_INVAL, "grid edges must be >= 3, or >= 1 on walled axes (got %d x %d x %d)",
+                    g->nx, g->ny, g->nz);
     if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SPFM_E_INVAL, "dx must be > 0");
     if (!(lambda > 0.0) || !(Gamma > 0.0) || !(M > 0.0) || !std::isfinite(lambda) ||
         !std::isfinite(Gamma) || !std::isfinite(M))
