@@ -143,6 +143,13 @@ StepCoef<T> make_coef(const Params& p) {
         k.K[j - 1] = (T)(p.dt * A * p.lambda * p.lambda * W);
         if (j <= nsh) wsum += p.gamma[j - 1] * nu_of(j) * mcount[j - 1];
     }
+    {
+        double Kd[3];
+        for (int j = 1; j <= 3; ++j)
+            Kd[j - 1] = j <= nsh ? p.dt * A * p.lambda * p.lambda * p.gamma[j - 1] * nu_of(j) / (j * p.dx * p.dx) : 0.0;
+        k.A1 = (T)(Kd[0] + 4.0 * Kd[1] + 4.0 * Kd[2]);
+        k.A2 = (T)(Kd[1] + 2.0 * Kd[2]);
+    }
     k.kcf = (T)(p.dt * A * 16.0 / 3.0 * wsum);
     const double hfac = p.interp == kH5 ? 30.0 : (p.interp == kHAbel ? 2.0 : 6.0);
     k.b = (T)(p.dt * hfac * B);

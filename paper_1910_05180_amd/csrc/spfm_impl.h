@@ -43,6 +43,7 @@ struct StepCoef {
     int nx, ny, nz;
     int pad;
     T K[3];    // dt A lambda^2 W_j per shell
+    T A1, A2;  // tail sums: K_1 + 4 K_2 + 4 K_3 and K_2 + 2 K_3 (A3 = K_3)
     T kcf;     // CF: dt A (16/3) sum_k gamma_j nu_j
     T b;       // dt 6 B
     T kap2;    // LOCAL: 4 dx / (lambda ln 2), exponent scale for exp2
@@ -195,11 +196,13 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             const T cz = (ez - T(1)) * (ez - T(1)) * rz;
             // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
             // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
-            const T c1 = cx + cy + cz;
-            const T c2 = fma(cx, cy, fma(cy, cz, cx * cz));
-            q = k.K[0] * c1;
-            if (S >= 18) q = fma(k.K[1], fma(T(4), c1, c2), q);
-            if (S >= 26) q = fma(k.K[2], fma(T(4), c1, fma(T(2), c2, cx * cy * cz)), q);
+            // K_1 s_1 + K_2 s_2 + K_3 s_3 = A1 c1 + A2 c2 + K_3 cx cy cz with
+            // c1 = sum c, c2 = sum of pair products (A1, A2 folded on the host).
+            const T cxy = cx + cy, pxy = cx * cy;
+            const T c1 = cxy + cz;
+            q = k.A1 * c1;
+            if (S >= 18) q = fma(k.A2, fma(cz, cxy, pxy), q);
+            if (S >= 26) q = fma(k.K[2], pxy * cz, q);
             q *= x;
             // The full coupling only where some lane of the wave needs it; the vote
             // keeps the branch wave-uniform, so tail-only waves skip it entirely.

@@ -48,8 +48,8 @@ __global__ __launch_bounds__(256) void k_step_plain(const T* __restrict__ in, T*
 template <typename T>
 struct PlaneRegs {
     T c;        // phi at the column
-    T fc;       // sum over the 4 in-plane face neighbours of (phi - c)
-    T dc;       // sum over the 4 in-plane diagonal neighbours of (phi - c)
+    T fc;       // sum of phi over the 4 in-plane face neighbours
+    T dc;       // sum of phi over the 4 in-plane diagonal neighbours
     T gx, gy;   // LOCAL: in-plane central differences of psi' at the column
     T pc;       // LOCAL: psi' at the column
 };
@@ -59,11 +59,11 @@ struct PlaneRegs {
 // from global memory once (coalesced rows) two iterations before it is staged
 // into a four-slot LDS ring, together with psi' of every cell for TI_n.  Every
 // thread reads its 3x3 in-plane neighbourhood of each plane once and keeps
-// per-plane partial sums in registers; with them the 26-neighbour shell sums of
-// point z are
-//   s1 = fc(z) + e,  s2 = dc(z) + fc(z-1) + fc(z+1) + 4e,  s3 = dc(z-1) + dc(z+1) + 4e,
-//   e = (c(z-1) - c(z)) + (c(z+1) - c(z)),
-// all built from differences of nearby values.  Two output planes are produced
+// per-plane sums in registers (its value c, the sum F of its 4 face neighbours
+// and the sum D of its 4 diagonal neighbours); with them the shell sums of
+// second differences of point z are
+//   s1 = F(z) + c(z-1) + c(z+1) - 6c(z),  s2 = D(z) + F(z-1) + F(z+1) - 12c(z),
+//   s3 = D(z-1) + D(z+1) - 8c(z).  Two output planes are produced
 // per iteration (one barrier per two planes, two independent points per thread).
 // Planes are numbered relative to the sweep, r = 0 for z0 - 1; plane r lives in
 // LDS slot r & 3.  Iterations start at r = 1 (mod 4) and alternate parity, so the
@@ -133,9 +133,8 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         const T* P = sphi + slot * HP + b;
         const T c = P[LX + 1];
         R.c = c;
-        R.fc = ((P[LX + 2] - c) + (P[LX] - c)) + ((P[2 * LX + 1] - c) + (P[1] - c));
-        if (S >= 18)
-            R.dc = ((P[2 * LX + 2] - c) + (P[0] - c)) + ((P[2 * LX] - c) + (P[2] - c));
+        R.fc = (P[LX + 2] + P[LX]) + (P[2 * LX + 1] + P[1]);
+        if (S >= 18) R.dc = (P[2 * LX + 2] + P[0]) + (P[2 * LX] + P[2]);
         if (C == kLocal) {
             const T* Q = spsi + slot * HP + b;
             R.gx = Q[LX + 2] - Q[LX];
@@ -147,12 +146,17 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     const int dst_off = ((y0 + ty) * nx + (x0 + tx)) * (int)sizeof(T);
     auto point = [&](__amdgpu_buffer_rsrc_t dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
                      const PlaneRegs<T>& Rp) {
+        // Shell sums of second differences from the raw plane sums, each with its
+        // own multiple of the centre value taken off (exactly 0 where phi is 0 or
+        // 1 throughout; elsewhere the rounding of the sums stays well below half
+        // an ulp of the new value):
+        //   s1 = F(z) + c(z-1) + c(z+1) - 6p, s2 = D(z) + F(z-1) + F(z+1) - 12p,
+        //   s3 = D(z-1) + D(z+1) - 8p.
         const T p = R0.c;
-        const T e = (Rm.c - p) + (Rp.c - p);
-        const T s1 = R0.fc + e;
+        const T s1 = fma(T(-6), p, R0.fc + (Rm.c + Rp.c));
         T s2 = T(0), s3 = T(0);
-        if (S >= 18) s2 = fma(T(4), e, R0.dc + (Rm.fc + Rp.fc));
-        if (S >= 26) s3 = fma(T(4), e, Rm.dc + Rp.dc);
+        if (S >= 18) s2 = fma(T(-12), p, R0.dc + (Rm.fc + Rp.fc));
+        if (S >= 26) s3 = fma(T(-8), p, Rm.dc + Rp.dc);
         auto grad = [&](T& gx, T& gy, T& gz) {
             gx = R0.gx;
             gy = R0.gy;
