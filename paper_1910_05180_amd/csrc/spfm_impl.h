@@ -61,8 +61,14 @@ struct StepCoef {
 // inverse of Eq. 3, linear in position on an ideal profile).
 // FP32 uses the native CDNA transcendental instructions (v_log_f32, v_exp_f32,
 // v_rcp_f32, v_rsq_f32; about 1 ulp); FP64 uses the full-precision library.
+// max(v, eps) for eps > 0 as a signed-integer max of the bit patterns: positive
+// floats order like their patterns, negative ones (and -0) lose to eps, a NaN
+// stays NaN; one instruction, and the loaded value needs no quieting.
+__device__ __forceinline__ float floor_pos(float v, float eps) {
+    return __int_as_float(max(__float_as_int(v), __float_as_int(eps)));
+}
 __device__ __forceinline__ float psi2(float phi, float eps) {
-    return __builtin_amdgcn_logf(fmaxf(1.0f - phi, eps)) - __builtin_amdgcn_logf(fmaxf(phi, eps));
+    return __builtin_amdgcn_logf(floor_pos(1.0f - phi, eps)) - __builtin_amdgcn_logf(floor_pos(phi, eps));
 }
 __device__ __forceinline__ double psi2(double phi, double eps) {
     return log2(fmax(1.0 - phi, eps)) - log2(fmax(phi, eps));
@@ -187,13 +193,28 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
                 g2 = flat ? T(1) : g2;
             }
             const T sc = k.kap2 * fast_rsqrt(g2);
-            const T ex = fast_exp2(sc * gx), ey = fast_exp2(sc * gy), ez = fast_exp2(sc * gz);
-            const T r = fast_rcp(ex * ey * ez);
-            const T rx = r * ey * ez, ry = r * ex * ez, rz = r * ex * ey;
-            // c_i = 2cosh(kappa n_i) - 2 = (E-1)^2/E
-            const T cx = (ex - T(1)) * (ex - T(1)) * rx;
-            const T cy = (ey - T(1)) * (ey - T(1)) * ry;
-            const T cz = (ez - T(1)) * (ez - T(1)) * rz;
+            // E_i = 2^(kappa n_i) and 1/E_i, and c_i = 2cosh(kappa n_i) - 2 = (E-1)^2/E
+            T ex, ey, ez, rx, ry, rz, cx, cy, cz;
+            if constexpr (sizeof(T) == 4) {
+                // FP32: c_i = (F - G)^2 with F = 2^(a/2), G = 2^(-a/2); six hardware
+                // exponentials are cheaper than a reciprocal chain.
+                const T hx = T(0.5) * sc * gx, hy = T(0.5) * sc * gy, hz = T(0.5) * sc * gz;
+                const T fx = fast_exp2(hx), gx_ = fast_exp2(-hx);
+                const T fy = fast_exp2(hy), gy_ = fast_exp2(-hy);
+                const T fz = fast_exp2(hz), gz_ = fast_exp2(-hz);
+                cx = (fx - gx_) * (fx - gx_);
+                cy = (fy - gy_) * (fy - gy_);
+                cz = (fz - gz_) * (fz - gz_);
+                ex = fx * fx; ey = fy * fy; ez = fz * fz;
+                rx = gx_ * gx_; ry = gy_ * gy_; rz = gz_ * gz_;
+            } else {
+                ex = fast_exp2(sc * gx); ey = fast_exp2(sc * gy); ez = fast_exp2(sc * gz);
+                const T r = fast_rcp(ex * ey * ez);
+                rx = r * ey * ez; ry = r * ex * ez; rz = r * ex * ey;
+                cx = (ex - T(1)) * (ex - T(1)) * rx;
+                cy = (ey - T(1)) * (ey - T(1)) * ry;
+                cz = (ez - T(1)) * (ez - T(1)) * rz;
+            }
             // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
             // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
             // K_1 s_1 + K_2 s_2 + K_3 s_3 = A1 c1 + A2 c2 + K_3 cx cy cz with
