@@ -36,7 +36,7 @@ ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..6
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the factors the same counters give for the copy
 # reference; None whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = None
+TRAFFIC_BYTES_LOCAL26 = (43494.0 * 2.0 + 70835.4) * 1024
 
 
 def parse():
