@@ -28,10 +28,12 @@ ALG_BYTES_F64 = 16
 # transcendental per lane per cycle).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic FP32 operations per point update of the TI_n 26-neighbour step on
-# the grain workload: 39 where phi(1-phi) = 0 (14% of points), 86 in the tail
-# branch (76%), 195 with the full coupling (10%), counted from the per-point
-# formulas (shell sums, normal, exponentials, coupling terms, update, psi').
-ALG_OPS_LOCAL26 = 0.14 * 39 + 0.76 * 86 + 0.10 * 195
+# the grain workload, counted from the per-point formulas the kernel evaluates:
+# 28 where phi(1-phi) = 0 (14% of points: psi' 6, plane sums 6, shell sums 8,
+# update 7, test 1), 65 in the tail branch (76%: those plus the normal 8, the
+# exponentials and c_i 16, the tail sums 9, tests 2) and 179 with the full
+# coupling (10%: 114 more for the 13 directional terms).
+ALG_OPS_LOCAL26 = 0.14 * 28 + 0.76 * 65 + 0.10 * 179
 ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..64)
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the factors the same counters give for the copy
