@@ -29,23 +29,26 @@ ALG_BYTES_F64 = 16
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic FP32 operations per point update of the TI_n 26-neighbour step on
 # the grain workload, counted from the per-point formulas the kernel evaluates:
-# 28 where phi(1-phi) = 0 (14% of points: psi' 6, plane sums 6, shell sums 8,
-# update 7, test 1), 65 in the tail branch (76%: those plus the normal 8, the
-# exponentials and c_i 16, the tail sums 9, tests 2) and 179 with the full
-# coupling (10%: 114 more for the 13 directional terms).
-ALG_OPS_LOCAL26 = 0.14 * 28 + 0.76 * 65 + 0.10 * 179
-ZCHUNK = 16                    # planes per block (the fastest in sweeps of 8..64)
+# 28 where phi(1-phi) = 0 (psi' 6, plane sums 6, shell sums 8, update 7, test 1),
+# 64 in the tail branch (plus the normal 9, the exponentials and c_i 15, the
+# tail sums 9, u and its term 2, test 1) and 163 with the full coupling (99
+# more: 2 sinh 6, the shell-2 and shell-3 m_k 37, three running fractions 52,
+# their sum 3, select 1).  The point mix over the timed steps (2050 to 3050 of
+# the run) is 13.1% / 79.8% / 7.1%.
+ALG_OPS_LOCAL26 = 0.131 * 28 + 0.798 * 64 + 0.071 * 163
+ZCHUNK = 32                    # leading planes per block (the fastest in sweeps of 16..64)
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the factors the same counters give for the copy
 # reference; None whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = (43494.0 * 2.0 + 70835.4) * 1024
+TRAFFIC_BYTES_LOCAL26 = None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2000,
+                    help="untimed steps first (the clocks settle over the first few hundred)")
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)

@@ -95,7 +95,11 @@ typedef struct {
     int32_t kernel;     /* spfm_kernel */
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
-                           library (timed at the first step for AUTO, a size rule for TILED) */
+                           library (timed at the first step for AUTO, a size rule for TILED).
+                           Single steps cut each tile column into blocks of zchunk planes,
+                           except its last min(nz, 2 zchunk) planes, which go in blocks of
+                           halving length down to 4 (dispatched last, so that the GPU drains
+                           evenly); fused steps (tsteps > 1) use zchunk planes throughout */
     int32_t tsteps;     /* temporal blocking: steps fused into one pass over the field, 0 or 1 =
                            none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
                            equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
@@ -140,8 +144,8 @@ typedef struct {
     double gamma[3];
     double dt_max;             /* explicit stability bound */
     int32_t stencil, coupling, dtype, kernel;
-    int32_t zchunk;            /* planes per block of the tiled kernel (chosen by timing
-                                  at the first spfm_step when kernel is AUTO) */
+    int32_t zchunk;            /* leading planes per block of the tiled kernel (chosen by
+                                  timing at the first spfm_step when kernel is AUTO) */
     int32_t tsteps;            /* steps per fused launch (1 = no temporal blocking) */
     int32_t walls;             /* walled axes (bit mask) */
     int32_t interp;            /* interpolation function (spfm_options.interp) */

@@ -18,6 +18,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed FP32 instructions (v_pk_*_f32) anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only where the source writes fma(): every inlined
+    # copy of the point update then rounds alike, so results do not depend on
+    # the tiling or on which loop of a sweep computes a plane
+    "-ffp-contract=off",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

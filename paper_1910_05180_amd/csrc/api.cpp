@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/spfm.h"
@@ -313,9 +314,13 @@ struct spfm_ctx {
         return from_interior(buf[1 - cur], buf[cur]);
     }
 
-    int zlen = kTileZ;        // planes per block of the tiled kernel
+    int zlen = kTileZ;        // planes per block of the tiled kernel (the leading chunks)
     bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
     bool tuned = false;
+    // Work items of the tiled kernel (tile_schedule of the stored grid for zlen).
+    TileItem* d_items = nullptr;
+    int nitems = 0;
+    size_t items_cap = 0;
 
     // Steps per launch of launch_unit.
     int unit() const { return r.tsteps; }
@@ -341,11 +346,13 @@ struct spfm_ctx {
         if (r.dtype == SPFM_F64) {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
-                    : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, zlen, stream);
+                    : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, d_items,
+                                                nitems, stream);
         } else {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
-                    : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, zlen, stream);
+                    : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, d_items,
+                                               nitems, stream);
         }
         if (e != hipSuccess || !r.conserve_volume) return e;
         // the step ran without the driving force; add the one that keeps sum phi
@@ -421,14 +428,147 @@ struct spfm_batch {
 
 namespace {
 
+// z-chunks of one tile column of a single-step sweep: the first nz - tail
+// planes in the fewest chunks of at most zb planes, of equal length to within
+// one (phase 0), then the last `tail` planes in chunks that halve from zb / 2
+// down to 4 planes, two of each size (phases 1, 2, ... in order).
+struct ZChunk {
+    int z0, len, phase;
+};
+std::vector<ZChunk> guided_chunks(int nz, int zb, int tail) {
+    std::vector<ZChunk> out;
+    tail = std::max(0, std::min(nz, tail));
+    const int lead = nz - tail, nlead = (lead + zb - 1) / zb;
+    for (int i = 0, z = 0; i < nlead; ++i) {
+        const int len = lead / nlead + (i < lead % nlead ? 1 : 0);
+        out.push_back(ZChunk{z, len, 0});
+        z += len;
+    }
+    int z = lead, phase = 1;
+    for (int size = std::max(zb / 2, 4); z < nz; size = std::max(size / 2, 4))
+        for (int rep = 0; rep < 2 && z < nz; ++rep) {
+            const int len = std::min(size, nz - z);
+            out.push_back(ZChunk{z, len, phase++});
+            z += len;
+        }
+    return out;
+}
+
+// Tail planes of a column of nz planes: the short chunks at the end of a step
+// should hold about one round of the work the GPU keeps resident (256 CUs x 4
+// SIMDs x 7 waves x 64 lanes, each lane owning one column point, times 32
+// planes), and at most a quarter of the step.
+int tail_planes(int nz, int64_t total_points) {
+    const double resident = 256.0 * 4 * 7 * 64 * 32;
+    const double f = std::min(0.25, resident / (double)std::max<int64_t>(total_points, 1));
+    return std::min(nz, (int)std::lround(f * nz));
+}
+
 // Planes per block: the longest z-chunk (at most kTileZ) that still gives at
-// least 2^20 threads (two full rounds of 512-thread blocks on 256 CUs) for
-// tiles tx x kTileY.
-int default_zlen(int nx, int ny, int nz, int tx) {
-    const int64_t cols = (int64_t)((nx + tx - 1) / tx) * ((ny + kTileY - 1) / kTileY);
+// least min_threads threads for tiles tx x ty, counting the guided chunks of
+// the single-grid step (guided) or uniform chunks (the temporal kernel).
+int default_zlen(int nx, int ny, int nz, int tx, int ty, bool guided, int64_t min_threads) {
+    const int64_t cols = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+    const int tail = tail_planes(nz, (int64_t)nx * ny * nz);
+    auto chunks = [&](int zb) -> int64_t {
+        return guided ? (int64_t)guided_chunks(nz, zb, tail).size() : (nz + zb - 1) / zb;
+    };
     int z = kTileZ;
-    while (z > 8 && cols * ((nz + z - 1) / z) * tx * kTileY < ((int64_t)1 << 20)) z /= 2;
+    while (z > 8 && cols * chunks(z) * tx * ty < min_threads) z /= 2;
     return z;
+}
+
+// Work items of the tiled step over one or more grids (TileItem.inst = grid
+// index), in dispatch order (block b runs on XCD b mod 8).  Every tile row (a
+// grid and a row of ty tiles, through all x and z) belongs to one XCD, so its
+// halo rows and z-chunk boundaries meet in one L2.  Rows are dealt to the XCDs
+// round robin (spread: an interface concentrated in one part of a grid, like a
+// centred grain, is shared by all XCDs) or in contiguous groups of equal point
+// counts (so that neighbouring rows also share an L2, which pays when the
+// fields do not fit the last-level cache).  Each XCD's list holds its rows' tile
+// columns cut along z by guided_chunks (tails from tail_planes of the total
+// point count): all phase-0 chunks first (grid by grid,
+// z chunk by z chunk), then the tail chunks phase by phase, so the blocks
+// dispatched last are short and the SIMDs run out of work together instead of
+// idling behind a few long blocks at the end of the step.  Shorter XCD lists
+// are padded with empty items (zlen 0).
+struct GridDims {
+    int nx, ny, nz;
+};
+std::vector<TileItem> tile_schedule(const std::vector<GridDims>& grids, int tx, int ty, int zb,
+                                    bool spread) {
+    struct Row {
+        int inst, y0, xcd;
+    };
+    std::vector<Row> rows;
+    int64_t total = 0;
+    for (int g = 0; g < (int)grids.size(); ++g)
+        for (int y0 = 0; y0 < grids[g].ny; y0 += ty) {
+            rows.push_back(Row{g, y0, 0});
+            total += (int64_t)grids[g].nx * grids[g].nz * std::min(ty, grids[g].ny - y0);
+        }
+    int64_t acc = 0;
+    for (size_t r = 0; r < rows.size(); ++r) {
+        const GridDims& d = grids[rows[r].inst];
+        const int64_t w = (int64_t)d.nx * d.nz * std::min(ty, d.ny - rows[r].y0);
+        // contiguous: the group whose share of the points holds the row's midpoint
+        rows[r].xcd = spread ? (int)(r % kNumXcd)
+                             : (int)std::min<int64_t>(kNumXcd - 1, (2 * acc + w) * kNumXcd / (2 * total));
+        acc += w;
+    }
+    const size_t ng = grids.size();
+    std::vector<std::vector<int>> y0s(kNumXcd * ng);   // row origins of grid g on XCD k
+    for (const Row& row : rows) y0s[row.xcd * ng + row.inst].push_back(row.y0);
+    std::vector<std::vector<ZChunk>> zc(ng);
+    int nphase = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        zc[g] = guided_chunks(grids[g].nz, zb, tail_planes(grids[g].nz, total));
+        for (const ZChunk& c : zc[g]) nphase = std::max(nphase, c.phase + 1);
+    }
+    std::vector<std::vector<TileItem>> per(kNumXcd);
+    for (int k = 0; k < kNumXcd; ++k)
+        for (int ph = 0; ph < nphase; ++ph)
+            for (size_t g = 0; g < ng; ++g) {
+                if (y0s[k * ng + g].empty()) continue;
+                for (const ZChunk& c : zc[g]) {
+                    if (c.phase != ph) continue;
+                    for (const int y0 : y0s[k * ng + g])
+                        for (int x0 = 0; x0 < grids[g].nx; x0 += tx)
+                            per[k].push_back(TileItem{(int)g, x0, y0, c.z0, c.len});
+                }
+            }
+    size_t m = 0;
+    for (const auto& v : per) m = std::max(m, v.size());
+    std::vector<TileItem> out(m * kNumXcd, TileItem{0, 0, 0, 0, 0});
+    for (int k = 0; k < kNumXcd; ++k)
+        for (size_t i = 0; i < per[k].size(); ++i) out[i * kNumXcd + k] = per[k][i];
+    return out;
+}
+
+spfm_status set_schedule(spfm_ctx* c, int zb) {
+    HIP_TRY(hipStreamSynchronize(c->stream));   // no launch may still read the old table
+    const int tx = tile_x(c->r.dtype == SPFM_F32, c->r.p.coupling);
+    const std::vector<TileItem> items =
+        tile_schedule({GridDims{c->r.sx, c->r.sy, c->r.sz}}, tx, kTileY, zb, true);
+    if (items.size() > 0x7fffffff) return fail(SPFM_E_INVAL, "too many tiles");
+    if (items.size() > c->items_cap) {
+        if (c->d_items) (void)hipFree(c->d_items);
+        c->d_items = nullptr;
+        c->items_cap = 0;
+        if (hipMalloc(&c->d_items, items.size() * sizeof(TileItem)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_items = nullptr;
+            return fail(SPFM_E_NOMEM, "device allocation of the tile schedule failed");
+        }
+        c->items_cap = items.size();
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_items, items.data(), items.size() * sizeof(TileItem),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->nitems = (int)items.size();
+    c->zlen = zb;
+    c->graphs.clear();
+    return SPFM_OK;
 }
 
 // SPFM_KERNEL_AUTO: time the tiled kernel for several z-chunk lengths on the
@@ -450,7 +590,8 @@ spfm_status autotune(spfm_ctx* c) {
         for (int ci = 0; ci < 4; ++ci) {
             const int z = cand[ci];
             if (ci > 0 && z > 2 * c->r.p.nz) break;
-            c->zlen = z;
+            st = set_schedule(c, z);   // also sets zlen, which the temporal kernel takes
+            if (st != SPFM_OK) break;
             hipError_t e = hipSuccess;
             for (int i = 0; i < 7 && e == hipSuccess; ++i) {
                 if (i == 2) e = hipEventRecord(e0, c->stream);
@@ -467,10 +608,10 @@ spfm_status autotune(spfm_ctx* c) {
     int bi = 0;
     for (int ci = 1; ci < 4; ++ci)
         if (best[ci] < best[bi]) bi = ci;
-    c->zlen = cand[bi];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return st;
+    if (st != SPFM_OK) return st;
+    return set_schedule(c, cand[bi]);
 }
 
 template <typename Obj>
@@ -546,8 +687,13 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     c->r = r;
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
-    const int tx = r.tsteps > 1 ? 64 : tile_x(r.dtype == SPFM_F32, r.p.coupling);   // temporal: 64 x 8
-    c->zlen = (opt && opt->zchunk > 0) ? opt->zchunk : default_zlen(r.sx, r.sy, r.sz, tx);
+    const bool f32 = r.dtype == SPFM_F32;
+    const bool temporal = r.tsteps > 1;
+    const int tx = temporal ? 64 : tile_x(f32, r.p.coupling);      // temporal: 64 x 8
+    c->zlen = (opt && opt->zchunk > 0)
+                  ? opt->zchunk
+                  : default_zlen(r.sx, r.sy, r.sz, tx, kTileY, !temporal,
+                                 temporal ? (int64_t)1 << 20 : (int64_t)1 << 19);
     const size_t bytes = c->stored_bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
@@ -573,6 +719,10 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
         return fail(SPFM_E_NOMEM, "device allocation of the reduction scratch failed");
     }
     c->refresh_coef();
+    if (r.kernel == SPFM_KERNEL_TILED) {   // single tiled steps (also the remainder of fused ones)
+        st = set_schedule(c, c->zlen);
+        if (st != SPFM_OK) { spfm_destroy(c); return st; }
+    }
     *out = c;
     return SPFM_OK;
 }
@@ -583,6 +733,7 @@ void spfm_destroy(spfm_ctx* c) {
     c->graphs.clear();
     c->red.release();
     if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_items) (void)hipFree(c->d_items);
     if (c->owns) {
         if (c->buf[0]) (void)hipFree(c->buf[0]);
         if (c->buf[1]) (void)hipFree(c->buf[1]);
@@ -837,7 +988,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     b->track.resize(n);
     b->offset.resize(n);
     std::vector<StepCoef<float>> coef(n);
-    std::vector<TileItem> items;
+    std::vector<GridDims> dims(n);
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         spfm_status st = resolve(&grids[i], lambda[i], Gamma[i], M[i], mu[i], stencil, &o, &b->r[i]);
@@ -854,19 +1005,11 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         const int64_t np = (int64_t)p.nx * p.ny * p.nz;
         b->points += np;
         off += (np + 63) / 64 * 64;   // keep every grid 256-byte aligned
-        const int tx = tile_x(true, o.coupling);
-        for (int z0 = 0; z0 < p.nz; z0 += kTileZ)
-            for (int y0 = 0; y0 < p.ny; y0 += kTileY)
-                for (int x0 = 0; x0 < p.nx; x0 += tx) items.push_back(TileItem{i, x0, y0, z0, kTileZ});
+        dims[i] = GridDims{p.nx, p.ny, p.nz};
     }
+    const std::vector<TileItem> items =
+        tile_schedule(dims, tile_x(true, o.coupling), kTileY, kTileZ, false);
     if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
-    {   // dispatch order: each XCD gets a contiguous run of tiles (see xcd_remap); the
-        // slabs of a batch spread their interfaces evenly, so no dealing is needed
-        std::vector<TileItem> order(items.size());
-        const int nt = (int)items.size();
-        for (int s = 0; s < nt; ++s) order[s] = items[xcd_remap(s, nt)];
-        items.swap(order);
-    }
     b->total = off;
     b->nitems = (int)items.size();
     const size_t bytes = (size_t)off * sizeof(float);

@@ -154,6 +154,7 @@ StepCoef<T> make_coef(const Params& p) {
     const double hfac = p.interp == kH5 ? 30.0 : (p.interp == kHAbel ? 2.0 : 6.0);
     k.b = (T)(p.dt * hfac * B);
     k.kap2 = (T)(4.0 * p.dx / (p.lambda * M_LN2));
+    k.kap2h = (T)(2.0 * p.dx / (p.lambda * M_LN2));
     k.eps = (T)p.eps;
     const double t = 8.0 * p.dx * p.tau / (p.lambda * M_LN2);
     k.tau2 = (T)(t * t);

@@ -47,6 +47,7 @@ struct StepCoef {
     T kcf;     // CF: dt A (16/3) sum_k gamma_j nu_j
     T b;       // dt 6 B
     T kap2;    // LOCAL: 4 dx / (lambda ln 2), exponent scale for exp2
+    T kap2h;   // LOCAL: kap2 / 2 (FP32 evaluates 2^(+-kap2 n_i / 2))
     T eps;     // floor of the log arguments in psi
     T tau2;    // LOCAL: |grad log2((1-phi)/phi)|^2 (central differences, per 2 dx)
                // below tau2 -> normal (1,0,0)
@@ -106,11 +107,12 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 // branch instead of being turned into an unconditional computation and a select.
 __device__ __forceinline__ void keep_branch() { __asm__ volatile("" ::: "memory"); }
 
-// Running sum of y_k / (1 + y_k) kept as one fraction num/den.
+// Running sum of y_k / (1 + y_k) kept as one fraction num/den, started from
+// the first term y_0 = m x.
 template <typename T>
 struct Frac {
     T num, den;
-    __device__ __forceinline__ Frac() : num(T(0)), den(T(1)) {}
+    __device__ __forceinline__ Frac(T m, T x) : num(m * x), den(fma(m, x, T(1))) {}
     __device__ __forceinline__ void add(T y) {
         num = fma(y, num + den, num);
         den = fma(den, y, den);
@@ -122,19 +124,19 @@ struct Frac {
 template <typename T, int S>
 __device__ __forceinline__ T shell_sums(T m1x, T m1y, T m1z, const T (&m2)[6], const T (&m3)[4], T x,
                                         const StepCoef<T>& k) {
-    Frac<T> f1;
-    f1.add(m1x * x); f1.add(m1y * x); f1.add(m1z * x);
+    Frac<T> f1(m1x, x);
+    f1.add(m1y * x); f1.add(m1z * x);
     T q = k.K[0] * f1.value();
     if (S >= 18) {
-        Frac<T> f2;
+        Frac<T> f2(m2[0], x);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) f2.add(m2[i] * x);
+        for (int i = 1; i < 6; ++i) f2.add(m2[i] * x);
         q = fma(k.K[1], f2.value(), q);
     }
     if (S >= 26) {
-        Frac<T> f3;
+        Frac<T> f3(m3[0], x);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f3.add(m3[i] * x);
+        for (int i = 1; i < 4; ++i) f3.add(m3[i] * x);
         q = fma(k.K[2], f3.value(), q);
     }
     return q;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void shell_laplacian(At at, T p, T& s1, T& s2, T& s3)
 template <typename T, int S, int C, typename Grad>
 __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const StepCoef<T>& k) {
     const T x = p * (T(1) - p);
-    const T u = T(1) - T(2) * p;
+    const T u = fma(T(-2), p, T(1));
     T upd = k.K[0] * s1;
     if (S >= 18) upd = fma(k.K[1], s2, upd);
     if (S >= 26) upd = fma(k.K[2], s3, upd);
@@ -181,7 +183,7 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
         if (C == kLocal) {
             T gx, gy, gz;
             grad(gx, gy, gz);
-            T g2 = gx * gx + gy * gy + gz * gz;
+            T g2 = fma(gx, gx, fma(gy, gy, gz * gz));
             // Fallback normal (1,0,0) where |grad psi'| is below tau; rare, so
             // waves without such a lane skip the selects.
             const bool flat = !(g2 >= k.tau2);
@@ -192,28 +194,37 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
                 gz = flat ? T(0) : gz;
                 g2 = flat ? T(1) : g2;
             }
-            const T sc = k.kap2 * fast_rsqrt(g2);
-            // E_i = 2^(kappa n_i) and 1/E_i, and c_i = 2cosh(kappa n_i) - 2 = (E-1)^2/E
-            T ex, ey, ez, rx, ry, rz, cx, cy, cz;
+            const T rg = fast_rsqrt(g2);
+            // c_i = 2cosh(kappa n_i) - 2 and s_i = 2sinh(kappa n_i) (the latter for
+            // the full coupling only)
+            T sx, sy, sz, cx, cy, cz;
             if constexpr (sizeof(T) == 4) {
                 // FP32: c_i = (F - G)^2 with F = 2^(a/2), G = 2^(-a/2); six hardware
                 // exponentials are cheaper than a reciprocal chain.
-                const T hx = T(0.5) * sc * gx, hy = T(0.5) * sc * gy, hz = T(0.5) * sc * gz;
+                const T sc = k.kap2h * rg;
+                const T hx = sc * gx, hy = sc * gy, hz = sc * gz;
                 const T fx = fast_exp2(hx), gx_ = fast_exp2(-hx);
                 const T fy = fast_exp2(hy), gy_ = fast_exp2(-hy);
                 const T fz = fast_exp2(hz), gz_ = fast_exp2(-hz);
-                cx = (fx - gx_) * (fx - gx_);
-                cy = (fy - gy_) * (fy - gy_);
-                cz = (fz - gz_) * (fz - gz_);
-                ex = fx * fx; ey = fy * fy; ez = fz * fz;
-                rx = gx_ * gx_; ry = gy_ * gy_; rz = gz_ * gz_;
+                const T dx = fx - gx_, dy = fy - gy_, dz = fz - gz_;
+                cx = dx * dx;
+                cy = dy * dy;
+                cz = dz * dz;
+                sx = fma(fx, fx, -(gx_ * gx_));   // F^2 - G^2
+                sy = fma(fy, fy, -(gy_ * gy_));
+                sz = fma(fz, fz, -(gz_ * gz_));
             } else {
-                ex = fast_exp2(sc * gx); ey = fast_exp2(sc * gy); ez = fast_exp2(sc * gz);
+                // E_i = 2^(kappa n_i) and 1/E_i from one reciprocal; c_i = (E-1)^2/E
+                const T sc = k.kap2 * rg;
+                const T ex = fast_exp2(sc * gx), ey = fast_exp2(sc * gy), ez = fast_exp2(sc * gz);
                 const T r = fast_rcp(ex * ey * ez);
-                rx = r * ey * ez; ry = r * ex * ez; rz = r * ex * ey;
+                const T rx = r * ey * ez, ry = r * ex * ez, rz = r * ex * ey;
                 cx = (ex - T(1)) * (ex - T(1)) * rx;
                 cy = (ey - T(1)) * (ey - T(1)) * ry;
                 cz = (ez - T(1)) * (ez - T(1)) * rz;
+                sx = ex - rx;
+                sy = ey - ry;
+                sz = ez - rz;
             }
             // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
             // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
@@ -230,46 +241,46 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             const bool full = !(fabs(x) < k.xtail);
             if (__ballot(full) != 0) {
                 keep_branch();
-                const T sx = ex - rx, sy = ey - ry, sz = ez - rz;   // 2 sinh
                 T m2[6];   // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
                 T m3[4];   // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
                 // 2cosh(a+-b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2
                 {
-                    const T pc = cx * cy, ps = sx * sy, base = cx + cy;
-                    m2[0] = fma(T(0.5), pc + ps, base);
-                    m2[1] = fma(T(0.5), pc - ps, base);
+                    const T ps = sx * sy, base = cx + cy;
+                    m2[0] = fma(T(0.5), fma(cx, cy, ps), base);
+                    m2[1] = fma(T(0.5), fma(cx, cy, -ps), base);
                 }
                 {
-                    const T pc = cy * cz, ps = sy * sz, base = cy + cz;
-                    m2[2] = fma(T(0.5), pc + ps, base);
-                    m2[3] = fma(T(0.5), pc - ps, base);
+                    const T ps = sy * sz, base = cy + cz;
+                    m2[2] = fma(T(0.5), fma(cy, cz, ps), base);
+                    m2[3] = fma(T(0.5), fma(cy, cz, -ps), base);
                 }
                 {
-                    const T pc = cx * cz, ps = sx * sz, base = cx + cz;
-                    m2[4] = fma(T(0.5), pc + ps, base);
-                    m2[5] = fma(T(0.5), pc - ps, base);
+                    const T ps = sx * sz, base = cx + cz;
+                    m2[4] = fma(T(0.5), fma(cx, cz, ps), base);
+                    m2[5] = fma(T(0.5), fma(cx, cz, -ps), base);
                 }
                 if (S >= 26) {
                     // 2sinh(a+-b) = (s_a (c_b+2) +- (c_a+2) s_b)/2, then
                     // 2cosh(w+-z) - 2 = m_w + c_z + (m_w c_z +- s_w s_z)/2
-                    const T hxy_p = T(0.5) * (sx * (cy + T(2)) + (cx + T(2)) * sy);
-                    const T hxy_m = T(0.5) * (sx * (cy + T(2)) - (cx + T(2)) * sy);
+                    const T csy = (cx + T(2)) * sy;
+                    const T hxy_p = T(0.5) * fma(sx, cy + T(2), csy);
+                    const T hxy_m = T(0.5) * fma(sx, cy + T(2), -csy);
                     {
-                        const T pc = m2[0] * cz, ps = hxy_p * sz, base = m2[0] + cz;
-                        m3[0] = fma(T(0.5), pc + ps, base);
-                        m3[1] = fma(T(0.5), pc - ps, base);
+                        const T ps = hxy_p * sz, base = m2[0] + cz;
+                        m3[0] = fma(T(0.5), fma(m2[0], cz, ps), base);
+                        m3[1] = fma(T(0.5), fma(m2[0], cz, -ps), base);
                     }
                     {
-                        const T pc = m2[1] * cz, ps = hxy_m * sz, base = m2[1] + cz;
-                        m3[2] = fma(T(0.5), pc + ps, base);
-                        m3[3] = fma(T(0.5), pc - ps, base);
+                        const T ps = hxy_m * sz, base = m2[1] + cz;
+                        m3[2] = fma(T(0.5), fma(m2[1], cz, ps), base);
+                        m3[3] = fma(T(0.5), fma(m2[1], cz, -ps), base);
                     }
                 }
                 const T qf = shell_sums<T, S>(cx, cy, cz, m2, m3, x, k);
                 q = full ? qf : q;
             }
         } else {
-            q = x * (k.K[0] * k.msum[0] + k.K[1] * k.msum[1] + k.K[2] * k.msum[2]);
+            q = x * fma(k.K[0], k.msum[0], fma(k.K[1], k.msum[1], k.K[2] * k.msum[2]));
             const bool full = !(fabs(x) < k.xtail);
             if (__ballot(full) != 0) {
                 keep_branch();
@@ -327,9 +338,10 @@ struct TileItem {   // one block of the batched step: grid index, tile origin, p
 template <typename T>
 hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              hipStream_t s);
+// One block per entry of the device table d_items (nitems entries, in dispatch order).
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             int zlen, hipStream_t s);
+                             const TileItem* d_items, int nitems, hipStream_t s);
 // TB = tsteps (2..4) steps per launch, FP32 (temporal.hip).
 hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<float>& k, int stencil,
                                 int coupling, int tsteps, int zlen, hipStream_t s);
@@ -359,20 +371,6 @@ __host__ __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int q = n / kNumXcd, r = n % kNumXcd;
     const int k = b % kNumXcd, i = b / kNumXcd;
     return k < r ? k * (q + 1) + i : r * (q + 1) + (k - r) * q + i;
-}
-
-// Dispatch slot b -> logical tile with the tiles dealt to the XCDs in runs of
-// `run` consecutive tiles, round robin: XCD k processes runs k, k + 8, ... in
-// order.  Each run keeps its halo sharing inside one L2, and work that is
-// concentrated in space (an interface) is spread over all XCDs.  The last
-// incomplete round falls back to xcd_remap; run <= 0 selects xcd_remap for all.
-__host__ __device__ __forceinline__ int xcd_deal(int b, int n, int run) {
-    if (run <= 0) return xcd_remap(b, n);
-    const int round = kNumXcd * run;
-    const int full = (n / round) * round;
-    if (b >= full) return full + xcd_remap(b - full, n - full);
-    const int k = b % kNumXcd, i = b / kNumXcd;
-    return ((i / run) * kNumXcd + k) * run + i % run;
 }
 
 // Number of ghost points of a padded field (the threads of one fill).

@@ -54,7 +54,7 @@ struct PlaneRegs {
     T pc;       // LOCAL: psi' at the column
 };
 
-// One block sweeps the tile [x0, x0+TX) x [y0, y0+kTileY) x [z0, z0+zlen)
+// One block sweeps the tile [x0, x0+TX) x [y0, y0+TY) x [z0, z0+zlen)
 // (clipped to the grid).  Each plane of the tile plus a one-cell halo is read
 // from global memory once (coalesced rows) two iterations before it is staged
 // into a four-slot LDS ring, together with psi' of every cell for TI_n.  Every
@@ -74,13 +74,13 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
                                            T* __restrict__ sphi, T* __restrict__ spsi) {
     // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
     // wave computes a kWaveX x (64 / kWaveX) patch of the tile.
-    constexpr int TX = tile_x(sizeof(T) == 4, C);
-    constexpr int HX = TX + 2, HY = kTileY + 2, NC = HX * HY;
+    constexpr int TX = tile_x(sizeof(T) == 4, C), TY = kTileY;
+    constexpr int HX = TX + 2, HY = TY + 2, NC = HX * HY;
     constexpr int LX = lds_row(TX), HP = LX * HY;
-    constexpr int NT = TX * kTileY;
+    constexpr int NT = TX * TY;
     constexpr int WX = kWaveX, WY = 64 / kWaveX;
     static_assert(NT <= NC && NC <= 2 * NT, "the halo plane takes two load rounds");
-    static_assert(TX % WX == 0 && kTileY % WY == 0 && LX >= HX, "wave patches tile the block");
+    static_assert(TX % WX == 0 && TY % WY == 0 && LX >= HX, "wave patches tile the block");
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int tx = (wave % (TX / WX)) * WX + lane % WX;
@@ -236,8 +236,9 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
 template <typename T, int C>
 struct Smem {
     static constexpr int TX = tile_x(sizeof(T) == 4, C);
-    static constexpr int NT = TX * kTileY;                    // threads per block
-    static constexpr int HP = lds_row(TX) * (kTileY + 2);     // one staged plane
+    static constexpr int TY = kTileY;
+    static constexpr int NT = TX * TY;                        // threads per block
+    static constexpr int HP = lds_row(TX) * (TY + 2);         // one staged plane
 };
 
 #ifndef SPFM_WAVES_F32
@@ -250,16 +251,17 @@ struct WavesPerSimd {
     static constexpr int value = sizeof(T) == 4 ? SPFM_WAVES_F32 : 4;
 };
 
+// One block per work item of a tile schedule (see the host-side schedule
+// builder): the item gives the tile column origin and its z-chunk; items with
+// zlen = 0 pad the table and exit at once.
 template <typename T, int S, int C>
-__global__ __launch_bounds__((Smem<T, C>::NT), WavesPerSimd<T>::value) void k_step_tiled(const T* __restrict__ in,
-                                                               T* __restrict__ out, StepCoef<T> k,
-                                                               int ntx, int nty, int ntiles,
-                                                               int zlen, int run) {
+__global__ __launch_bounds__((Smem<T, C>::NT), WavesPerSimd<T>::value) void k_step_tiled(
+    const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items) {
     __shared__ T sphi[4 * Smem<T, C>::HP];
     __shared__ T spsi[C == kLocal ? 4 * Smem<T, C>::HP : 1];
-    const int t = xcd_deal(blockIdx.x, ntiles, run);
-    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    tile_sweep<T, S, C>(in, out, k, tx * Smem<T, C>::TX, ty * kTileY, tz * zlen, zlen, sphi, spsi);
+    const TileItem it = items[blockIdx.x];
+    if (it.zlen <= 0) return;
+    tile_sweep<T, S, C>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi);
 }
 
 template <int S, int C>
@@ -270,6 +272,7 @@ __global__ __launch_bounds__((Smem<float, C>::NT), WavesPerSimd<float>::value) v
     __shared__ float sphi[4 * Smem<float, C>::HP];
     __shared__ float spsi[C == kLocal ? 4 * Smem<float, C>::HP : 1];
     const TileItem it = items[blockIdx.x];
+    if (it.zlen <= 0) return;   // padding of the schedule
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
     tile_sweep<float, S, C>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, it.zlen, sphi,
@@ -303,16 +306,11 @@ struct PlainLaunch {
 
 template <typename T, int S, int C>
 struct TiledLaunch {
-    static hipError_t run(const T* in, T* out, const StepCoef<T>& k, int zlen, hipStream_t s) {
-        if (zlen < 1) return hipErrorInvalidValue;
-        constexpr int TX = Smem<T, C>::TX;
-        const int ntx = (k.nx + TX - 1) / TX, nty = (k.ny + kTileY - 1) / kTileY;
-        const int ntz = (k.nz + zlen - 1) / zlen;
-        const int64_t n = (int64_t)ntx * nty * ntz;
-        if (n > 0x7fffffff) return hipErrorInvalidValue;
-        // One row of tiles per run: every XCD gets every eighth row.
-        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)n), dim3(Smem<T, C>::NT), 0, s,
-                           in, out, k, ntx, nty, (int)n, zlen, ntx);
+    static hipError_t run(const T* in, T* out, const StepCoef<T>& k, const TileItem* items,
+                          int nitems, hipStream_t s) {
+        if (nitems <= 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)nitems), dim3(Smem<T, C>::NT), 0, s,
+                           in, out, k, items);
         return hipGetLastError();
     }
 };
@@ -338,8 +336,8 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             int zlen, hipStream_t s) {
-    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, zlen, s);
+                             const TileItem* d_items, int nitems, hipStream_t s) {
+    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, d_items, nitems, s);
 }
 
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
@@ -354,8 +352,8 @@ template hipError_t launch_step_plain<float>(const float*, float*, const StepCoe
 template hipError_t launch_step_plain<double>(const double*, double*, const StepCoef<double>&, int,
                                               int, hipStream_t);
 template hipError_t launch_step_tiled<float>(const float*, float*, const StepCoef<float>&, int, int,
-                                             int, hipStream_t);
+                                             const TileItem*, int, hipStream_t);
 template hipError_t launch_step_tiled<double>(const double*, double*, const StepCoef<double>&, int,
-                                              int, int, hipStream_t);
+                                              int, const TileItem*, int, hipStream_t);
 
 }  // namespace spfm

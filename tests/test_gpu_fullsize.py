@@ -1,5 +1,6 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
-(FP32 tiled kernel, 16 planes per block), on sampled outputs.
+(FP32 tiled kernel, guided z-chunks led by 32 planes per block), on sampled
+outputs.
 
 The GPU builds its own initial field; the oracle builds its own at the
 dependency cone of each sampled point (a point's value after K steps depends
@@ -13,7 +14,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-ZCHUNK = 16
+ZCHUNK = 32
 
 
 @pytest.fixture(scope="module")

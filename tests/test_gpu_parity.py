@@ -217,3 +217,24 @@ def test_graph_replay_equals_direct_launches(S):
                     s.step(chunk)
                 res.append(s.get_field())
     assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("coupling", ["local", "global", "cf"])
+def test_results_do_not_depend_on_the_zchunk(S, coupling):
+    """The z-chunk decides which blocks compute a plane and in which loop of
+    their sweep: the step result is the same bit for bit (a 160^3 grain; with
+    multiply-add fusion left to the compiler, planes computed in different loops
+    of a sweep rounded differently)."""
+    from paper_1910_05180_amd import inputs
+    w = inputs.sphere256()
+    shape = (160, 160, 160)
+    out = []
+    for zc in (8, 13, 32, 64):
+        print(f"case {coupling} zchunk={zc}", flush=True)
+        with S.Spfm(shape, lam=w.lam, mu=0.01, stencil=26, dtype="f32", coupling=coupling,
+                    u=(1.0, 2.0, 0.0), kernel="tiled", zchunk=zc, dt=w.dt) as s:
+            s.init_spheres([(80.3, 79.6, 80.1)], [50.0])
+            s.step(40)
+            out.append(s.get_field())
+    for f in out[1:]:
+        assert np.array_equal(out[0], f)
