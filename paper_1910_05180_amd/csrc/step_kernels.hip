@@ -165,11 +165,26 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         const T v = point_core<T, S, C>(p, s1, s2, s3, grad, k);
         if (active) buf_store(v, dst, dst_off);
     };
-    // Descriptors of input plane r (relative numbering) and output plane z.
-    auto plane_in = [&](int r) {
-        return plane_rsrc(in + (size_t)wrap_once(z0 - 1 + r, nz) * plane, plane_bytes);
+    // Descriptors of the input planes, fetched strictly in order r = 0, 1, ...
+    // (plane z0 - 1 + r with periodic wrap), and of the output planes, written
+    // in order z0, z0 + 1, ...: running byte pointers advanced one plane per use.
+    int fetch_z = wrap_once(z0 - 1, nz);
+    const char* fetch_ptr = reinterpret_cast<const char*>(in) + (size_t)fetch_z * plane_bytes;
+    auto next_in = [&]() {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(fetch_ptr, plane_bytes);
+        fetch_ptr += plane_bytes;
+        if (++fetch_z == nz) {
+            fetch_z = 0;
+            fetch_ptr = reinterpret_cast<const char*>(in);
+        }
+        return rs;
     };
-    auto plane_out = [&](int z) { return plane_rsrc(out + (size_t)z * plane, plane_bytes); };
+    char* out_ptr = reinterpret_cast<char*>(out) + (size_t)z0 * plane_bytes;
+    auto next_out = [&]() {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(out_ptr, plane_bytes);
+        out_ptr += plane_bytes;
+        return rs;
+    };
 
     // Iteration producing planes r, r+1 (slots: parity 0 reads 2, 3 and
     // writes 0, 1; parity 1 reads 0, 1 and writes 2, 3) with registers P0..P3
@@ -188,10 +203,10 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         if (!G || r + 2 <= last) load_slot(rd + 1, P3);
         if (!G || r + 3 <= last) stage_slot(wr, Q0);
         if (!G || r + 4 <= last) stage_slot(wr + 1, Q1);
-        if (!G || r + 7 <= last) fetch_at(plane_in(r + 7), Q0);
-        if (!G || r + 8 <= last) fetch_at(plane_in(r + 8), Q1);
-        if (!G || r <= nout) point(plane_out(z0 - 1 + r), P0, P1, P2);
-        if (!G || r + 1 <= nout) point(plane_out(z0 + r), P1, P2, P3);
+        if (!G || r + 7 <= last) fetch_at(next_in(), Q0);
+        if (!G || r + 8 <= last) fetch_at(next_in(), Q1);
+        if (!G || r <= nout) point(next_out(), P0, P1, P2);
+        if (!G || r + 1 <= nout) point(next_out(), P1, P2, P3);
     };
     using P0t = std::integral_constant<int, 0>;
     using P1t = std::integral_constant<int, 1>;
@@ -206,11 +221,11 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         Pair v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (r <= last) fetch_at(plane_in(r), v[r]);
-        if (4 <= last) fetch_at(plane_in(4), qa0);
-        if (5 <= last) fetch_at(plane_in(5), qa1);
-        if (6 <= last) fetch_at(plane_in(6), qb0);
-        if (7 <= last) fetch_at(plane_in(7), qb1);
+            if (r <= last) fetch_at(next_in(), v[r]);
+        if (4 <= last) fetch_at(next_in(), qa0);
+        if (5 <= last) fetch_at(next_in(), qa1);
+        if (6 <= last) fetch_at(next_in(), qb0);
+        if (7 <= last) fetch_at(next_in(), qb1);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (r <= last) stage_slot(r, v[r]);
