@@ -96,10 +96,11 @@ typedef struct {
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
                            library (timed at the first step for AUTO, a size rule for TILED).
-                           Single steps cut each tile column into blocks of zchunk planes,
-                           except its last min(nz, 2 zchunk) planes, which go in blocks of
-                           halving length down to 4 (dispatched last, so that the GPU drains
-                           evenly); fused steps (tsteps > 1) use zchunk planes throughout */
+                           Single steps cut each tile column into blocks of at most zchunk
+                           planes, except a tail (about 1.4 rounds of the work the GPU keeps
+                           resident, at most 35% of the column) in blocks of halving length
+                           down to 4, dispatched last so that the GPU drains evenly; fused
+                           steps (tsteps > 1) use zchunk planes throughout */
     int32_t tsteps;     /* temporal blocking: steps fused into one pass over the field, 0 or 1 =
                            none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
                            equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
