@@ -95,11 +95,18 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, flo
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off, double*) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// Aux = cache-policy bits of the store: 0 (default) or kStoreThrough = sc0 | sc1
+// (system scope, written through the L2).  Writing the new field through
+// leaves fewer dirty L2 lines to flush when the step kernel ends: the TI_n step
+// measured 1.5% faster with it (FP32), the bandwidth-heavier CF step 1.3% slower.
+constexpr int kStoreThrough = 17;
+template <int Aux = 0>
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, Aux);
 }
+template <int Aux = 0>
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, Aux);
 }
 
 // An empty statement with side effects: the compiler may not speculate the

@@ -163,7 +163,7 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             gz = Rp.pc - Rm.pc;
         };
         const T v = point_core<T, S, C>(p, s1, s2, s3, grad, k);
-        if (active) buf_store(v, dst, dst_off);
+        if (active) buf_store<(C == kLocal && sizeof(T) == 4) ? kStoreThrough : 0>(v, dst, dst_off);
     };
     // Descriptors of the input planes, fetched strictly in order r = 0, 1, ...
     // (plane z0 - 1 + r with periodic wrap), and of the output planes, written
