@@ -106,7 +106,7 @@ typedef struct {
                            equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
                            n / tsteps fused launches and n % tsteps single steps */
     int32_t walls;      /* bit d (d = 0, 1, 2 for x, y, z): contact-angle walls at both ends of
-                           axis d instead of periodic wrap (not with tsteps > 1, not in batches) */
+                           axis d instead of periodic wrap (not with tsteps > 1) */
     double wall_sin[6]; /* faces -x, +x, -y, +y, -z, +z: sin(alpha) of Eq. 7, in [-1, 1]: a ghost
                            is its inward neighbour moved by dx sin(alpha) along the profile
                            coordinate (towards phi = 0 for > 0).  A planar front of normal n
@@ -120,6 +120,9 @@ typedef struct {
     int32_t conserve_volume; /* nonzero: the homogeneous driving force is chosen at every step so
                            that sum phi stays constant (Sec. 3.4; mu at create only sets the
                            stability check); periodic grids, tsteps <= 1, not in batches */
+    const double *batch_wall_sin; /* batches with walls: 6 values per grid, wall_sin of grid i at
+                           6 i (read at spfm_batch_create only); NULL = wall_sin for every grid.
+                           Ignored by single contexts */
 } spfm_options;
 
 typedef struct {
@@ -231,18 +234,28 @@ spfm_status spfm_step(spfm_ctx *ctx, int64_t n);
 spfm_status spfm_diagnostics(spfm_ctx *ctx, spfm_diag *out);
 spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
 
-/* Many independent periodic grids of different sizes stepped together: one
- * kernel launch per step covers every tile of every grid, and spfm_batch_step
+/* Many independent grids of different sizes stepped together: one kernel
+ * launch per step covers every tile of every grid, and spfm_batch_step
  * captures the launches of n steps in one HIP graph.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
- * eps, tau, allow_unstable) apply to every grid; each grid gets its own
- * lambda, Gamma, M, mu; d_phi must be NULL and tsteps <= 1. */
+ * eps, tau, allow_unstable, walls) apply to every grid; each grid gets its own
+ * lambda, Gamma, M, mu and, with walls, its own wall angles from
+ * batch_wall_sin (the orientation sweeps of Sec. 3.2 in one launch; the
+ * ghosts of every grid are filled by one more launch per step, at most 65535
+ * grids); d_phi must be NULL, tsteps <= 1 and conserve_volume 0.  Fields,
+ * initial conditions and diagnostics refer to the interior of each grid. */
 spfm_status spfm_batch_create(int32_t n, const spfm_grid *grids, const double *lambda,
                               const double *Gamma, const double *M, const double *mu,
                               int stencil, const spfm_options *opt, spfm_batch **out);
 void spfm_batch_destroy(spfm_batch *b);
 spfm_status spfm_batch_init_planar(spfm_batch *b, const int32_t *hkl /* 3n */,
                                    const double *offset /* n */);
+/* A planar front of normal n (3 per grid, into phi = 0) through the centre of
+ * grid i shifted by offset[i] along it (Eq. 3), as spfm_init_front; a normal
+ * component along an axis needs walls on that axis.  Positions are then
+ * tracked along each grid's normal. */
+spfm_status spfm_batch_init_front(spfm_batch *b, const double *n /* 3n */,
+                                  const double *offset /* n */);
 spfm_status spfm_batch_set_field(spfm_batch *b, int32_t i, const void *src, int src_on_device);
 spfm_status spfm_batch_get_field(spfm_batch *b, int32_t i, void *dst, int dst_on_device);
 spfm_status spfm_batch_step(spfm_batch *b, int64_t n);

@@ -237,6 +237,54 @@ double slab_area(int nx, int ny, int nz, double dx, const int32_t hkl[3]) {
     return 2.0 * (double)nx * ny * nz * dx * dx * dx / P;
 }
 
+// Wall coefficients of a resolved grid: stored dims, walled axes and the
+// composed Eq. 7 coefficient of every ghost class (the shifts of the walls
+// crossed from the ghost to its interior point add up).
+template <typename T>
+WallCoef<T> wall_coef(const Resolved& r) {
+    WallCoef<T> w;
+    w.sx = r.sx;
+    w.sy = r.sy;
+    w.sz = r.sz;
+    w.walls = r.walls;
+    for (int cz = -1; cz <= 1; ++cz)
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) {
+                const int c[3] = {cx, cy, cz};
+                double sh = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    if (c[d] != 0) sh += r.wall_sin[2 * d + (c[d] > 0 ? 1 : 0)];
+                w.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)] = (T)std::tanh(2.0 * r.p.dx * sh / r.p.lambda);
+            }
+    return w;
+}
+
+// Copies between a dense grid-shaped array and the interior of a stored field
+// (walls on the axes of the mask: one ghost layer at each end).
+template <typename T>
+hipError_t copy_to_interior(T* stored, const T* dense, const Resolved& r, hipStream_t s) {
+    const Params& p = r.p;
+    return launch_box_copy<T>(stored, r.sx, r.sy, r.walls & 1, (r.walls >> 1) & 1, (r.walls >> 2) & 1,
+                              dense, p.nx, p.ny, 0, 0, 0, p.nx, p.ny, p.nz, s);
+}
+template <typename T>
+hipError_t copy_from_interior(T* dense, const T* stored, const Resolved& r, hipStream_t s) {
+    const Params& p = r.p;
+    return launch_box_copy<T>(dense, p.nx, p.ny, 0, 0, 0, stored, r.sx, r.sy, r.walls & 1,
+                              (r.walls >> 1) & 1, (r.walls >> 2) & 1, p.nx, p.ny, p.nz, s);
+}
+
+// Area of a planar front of normal n in a box: the cross-section normal to the
+// axis the front crosses (largest |n_d|) divided by that component of n / |n|.
+double front_area(const Params& p, const double n[3]) {
+    const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    int d = 0;
+    for (int k = 1; k < 3; ++k)
+        if (std::fabs(n[k]) > std::fabs(n[d])) d = k;
+    const int ext[3] = {p.nx, p.ny, p.nz};
+    return (double)ext[(d + 1) % 3] * ext[(d + 2) % 3] * p.dx * p.dx / (std::fabs(n[d]) / nn);
+}
+
 // Replays of kGraphSteps launches captured from a step function, one graph per
 // starting buffer; invalidated whenever the coefficients change.
 struct GraphCache {
@@ -282,28 +330,16 @@ struct spfm_ctx {
     int64_t points() const { return (int64_t)r.p.nx * r.p.ny * r.p.nz; }
     size_t bytes() const { return (size_t)points() * elem_size(r.dtype); }
     size_t stored_bytes() const { return (size_t)r.sx * r.sy * r.sz * elem_size(r.dtype); }
-    int gx() const { return r.walls & 1; }
-    int gy() const { return (r.walls >> 1) & 1; }
-    int gz() const { return (r.walls >> 2) & 1; }
     // Copy between a dense grid-shaped array and the interior of a stored field.
     hipError_t to_interior(void* stored, const void* dense) {
-        const Params& p = r.p;
         return r.dtype == SPFM_F64
-                   ? launch_box_copy<double>((double*)stored, r.sx, r.sy, gx(), gy(), gz(),
-                                             (const double*)dense, p.nx, p.ny, 0, 0, 0, p.nx, p.ny,
-                                             p.nz, stream)
-                   : launch_box_copy<float>((float*)stored, r.sx, r.sy, gx(), gy(), gz(),
-                                            (const float*)dense, p.nx, p.ny, 0, 0, 0, p.nx, p.ny,
-                                            p.nz, stream);
+                   ? copy_to_interior<double>((double*)stored, (const double*)dense, r, stream)
+                   : copy_to_interior<float>((float*)stored, (const float*)dense, r, stream);
     }
     hipError_t from_interior(void* dense, const void* stored) {
-        const Params& p = r.p;
         return r.dtype == SPFM_F64
-                   ? launch_box_copy<double>((double*)dense, p.nx, p.ny, 0, 0, 0,
-                                             (const double*)stored, r.sx, r.sy, gx(), gy(), gz(),
-                                             p.nx, p.ny, p.nz, stream)
-                   : launch_box_copy<float>((float*)dense, p.nx, p.ny, 0, 0, 0, (const float*)stored,
-                                            r.sx, r.sy, gx(), gy(), gz(), p.nx, p.ny, p.nz, stream);
+                   ? copy_from_interior<double>((double*)dense, (const double*)stored, r, stream)
+                   : copy_from_interior<float>((float*)dense, (const float*)stored, r, stream);
     }
     // A grid-dense array of the current field: the live buffer itself, or (with
     // walls) its interior packed into the other buffer, which the next step
@@ -376,24 +412,8 @@ struct spfm_ctx {
         kf0.nx = kd0.nx = r.sx;
         kf0.ny = kd0.ny = r.sy;
         kf0.nz = kd0.nz = r.sz;
-        wf.sx = wd.sx = r.sx;
-        wf.sy = wd.sy = r.sy;
-        wf.sz = wd.sz = r.sz;
-        wf.walls = wd.walls = r.walls;
-        // Composed Eq. 7 coefficient of every ghost class: the shifts of the
-        // walls crossed from the ghost to its interior point add up.
-        for (int cz = -1; cz <= 1; ++cz)
-            for (int cy = -1; cy <= 1; ++cy)
-                for (int cx = -1; cx <= 1; ++cx) {
-                    const int c[3] = {cx, cy, cz};
-                    double sh = 0.0;
-                    for (int d = 0; d < 3; ++d)
-                        if (c[d] != 0) sh += r.wall_sin[2 * d + (c[d] > 0 ? 1 : 0)];
-                    const double a = std::tanh(2.0 * r.p.dx * sh / r.p.lambda);
-                    const int i = (cx + 1) + 3 * (cy + 1) + 9 * (cz + 1);
-                    wf.a[i] = (float)a;
-                    wd.a[i] = a;
-                }
+        wf = wall_coef<float>(r);
+        wd = wall_coef<double>(r);
         nghost = wall_ghosts(r.sx, r.sy, r.sz, r.walls);
         graphs.clear();
     }
@@ -414,6 +434,11 @@ struct spfm_batch {
     TileItem* d_items = nullptr;
     int nitems = 0;
     int stencil = 26, coupling = 0;
+    // Walls (the same axes on every grid): per-grid coefficients on the device,
+    // and the largest ghost count, the extent of the batched fill.
+    int walls = 0;
+    WallCoef<float>* d_wall = nullptr;
+    int64_t max_ghost = 0;
     Reducer red;
     std::vector<Tracker> track;
     GraphCache graphs;
@@ -421,8 +446,27 @@ struct spfm_batch {
     int unit() const { return 1; }
     hipError_t launch_unit(int from) { return launch_one(from); }
     hipError_t launch_one(int from) {
+        if (walls) {   // ghost layers of every input grid from Eq. 7, then the step
+            const hipError_t e = launch_fill_walls_batched(buf[from], d_wall, d_offset, n, max_ghost,
+                                                           stream);
+            if (e != hipSuccess) return e;
+        }
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
                                    stencil, coupling, stream);
+    }
+    // Grid i as a dense array: its region of the current buffer, or (with walls)
+    // its interior packed into its region of the other buffer, which the next
+    // step overwrites anyway.
+    hipError_t dense_grid(int i, const float** out) {
+        if (!walls) { *out = buf[cur] + offset[i]; return hipSuccess; }
+        *out = buf[1 - cur] + offset[i];
+        return copy_from_interior<float>(buf[1 - cur] + offset[i], buf[cur] + offset[i], r[i], stream);
+    }
+    // Where a dense initial field of grid i is written before to_grid.
+    float* dense_target(int i) { return (walls ? buf[1 - cur] : buf[cur]) + offset[i]; }
+    hipError_t to_grid(int i) {
+        if (!walls) return hipSuccess;
+        return copy_to_interior<float>(buf[cur] + offset[i], buf[1 - cur] + offset[i], r[i], stream);
     }
 };
 
@@ -833,16 +877,9 @@ spfm_status spfm_init_front(spfm_ctx* c, const double n[3], double offset) {
                                                   offset, c->stream);
     if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
     if (e != hipSuccess) return fail(SPFM_E_HIP, "front init: %s", hipGetErrorString(e));
-    // Position along n: the phase volume change over the front's area, the box
-    // cross-section normal to the axis the front crosses (largest |n_d|)
-    // divided by that component.
-    int d = 0;
-    for (int k = 1; k < 3; ++k)
-        if (std::fabs(n[k]) > std::fabs(n[d])) d = k;
-    const int ext[3] = {p.nx, p.ny, p.nz};
-    const double area = (double)ext[(d + 1) % 3] * ext[(d + 2) % 3] * p.dx * p.dx / (std::fabs(n[d]) / nn);
+    // Position along n: the phase volume change over the front's area.
     c->nsteps = 0;
-    c->track.reset(1, area);
+    c->track.reset(1, front_area(p, n));
     return SPFM_OK;
 }
 
@@ -961,6 +998,7 @@ void spfm_batch_destroy(spfm_batch* b) {
     if (b->d_coef) (void)hipFree(b->d_coef);
     if (b->d_offset) (void)hipFree(b->d_offset);
     if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_wall) (void)hipFree(b->d_wall);
     delete b;
 }
 
@@ -977,22 +1015,27 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.C_Gamma > 0.0) return fail(SPFM_E_INVAL, "batches calibrate C_Gamma per grid");
     if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
     if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
-    if (o.walls) return fail(SPFM_E_INVAL, "batches are periodic (walls = 0)");
     if (o.conserve_volume) return fail(SPFM_E_INVAL, "batches keep mu fixed (conserve_volume = 0)");
+    if (o.walls && n > 65535) return fail(SPFM_E_INVAL, "batches with walls hold at most 65535 grids");
     spfm_batch* b = new (std::nothrow) spfm_batch;
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;
     b->stencil = stencil;
     b->coupling = kernel_coupling(o.coupling, o.interp);
     b->stream = (hipStream_t)o.stream;
+    b->walls = o.walls;
     b->r.resize(n);
     b->track.resize(n);
     b->offset.resize(n);
     std::vector<StepCoef<float>> coef(n);
+    std::vector<WallCoef<float>> wall(o.walls ? n : 0);
     std::vector<GridDims> dims(n);
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
-        spfm_status st = resolve(&grids[i], lambda[i], Gamma[i], M[i], mu[i], stencil, &o, &b->r[i]);
+        spfm_options oi = o;   // per-grid wall angles, when given
+        if (o.walls && o.batch_wall_sin)
+            for (int f = 0; f < 6; ++f) oi.wall_sin[f] = o.batch_wall_sin[6 * i + f];
+        spfm_status st = resolve(&grids[i], lambda[i], Gamma[i], M[i], mu[i], stencil, &oi, &b->r[i]);
         if (st != SPFM_OK) {
             spfm_batch_destroy(b);
             char tmp[512];
@@ -1000,13 +1043,21 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
             std::snprintf(g_err, sizeof g_err, "%s", tmp);
             return st;
         }
-        const Params& p = b->r[i].p;
+        const Resolved& ri = b->r[i];
+        const Params& p = ri.p;
         coef[i] = make_coef<float>(p);
+        coef[i].nx = ri.sx;   // the kernels sweep the stored grid
+        coef[i].ny = ri.sy;
+        coef[i].nz = ri.sz;
         b->offset[i] = off;
-        const int64_t np = (int64_t)p.nx * p.ny * p.nz;
-        b->points += np;
-        off += (np + 63) / 64 * 64;   // keep every grid 256-byte aligned
-        dims[i] = GridDims{p.nx, p.ny, p.nz};
+        b->points += (int64_t)p.nx * p.ny * p.nz;
+        const int64_t ns = (int64_t)ri.sx * ri.sy * ri.sz;
+        off += (ns + 63) / 64 * 64;   // keep every grid 256-byte aligned
+        dims[i] = GridDims{ri.sx, ri.sy, ri.sz};
+        if (o.walls) {
+            wall[i] = wall_coef<float>(ri);
+            b->max_ghost = std::max(b->max_ghost, wall_ghosts(ri.sx, ri.sy, ri.sz, ri.walls));
+        }
     }
     const std::vector<TileItem> items =
         tile_schedule(dims, tile_x(true, o.coupling), kTileY, kTileZ, false);
@@ -1017,7 +1068,8 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (hipMalloc(&b->buf[0], bytes) != hipSuccess || hipMalloc(&b->buf[1], bytes) != hipSuccess ||
         hipMalloc(&b->d_coef, sizeof(StepCoef<float>) * n) != hipSuccess ||
         hipMalloc(&b->d_offset, sizeof(int64_t) * n) != hipSuccess ||
-        hipMalloc(&b->d_items, sizeof(TileItem) * items.size()) != hipSuccess) {
+        hipMalloc(&b->d_items, sizeof(TileItem) * items.size()) != hipSuccess ||
+        (o.walls && hipMalloc(&b->d_wall, sizeof(WallCoef<float>) * n) != hipSuccess)) {
         (void)hipGetLastError();
         spfm_batch_destroy(b);
         return fail(SPFM_E_NOMEM, "device allocation failed");
@@ -1027,6 +1079,8 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (hipMemcpy(b->d_coef, coef.data(), sizeof(StepCoef<float>) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_offset, b->offset.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_items, items.data(), sizeof(TileItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (o.walls && hipMemcpy(b->d_wall, wall.data(), sizeof(WallCoef<float>) * n,
+                              hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemset(b->buf[0], 0, bytes) != hipSuccess || hipMemset(b->buf[1], 0, bytes) != hipSuccess) {
         spfm_batch_destroy(b);
         return fail(SPFM_E_HIP, "batch upload failed");
@@ -1045,10 +1099,36 @@ spfm_status spfm_batch_init_planar(spfm_batch* b, const int32_t* hkl, const doub
     for (int i = 0; i < b->n; ++i) {
         const Params& p = b->r[i].p;
         const int h[3] = {hkl[3 * i], hkl[3 * i + 1], hkl[3 * i + 2]};
-        hipError_t e = launch_init_planar<float>(b->buf[b->cur] + b->offset[i], p.nx, p.ny, p.nz,
-                                                 p.dx, p.lambda, h, offset[i], b->stream);
+        hipError_t e = launch_init_planar<float>(b->dense_target(i), p.nx, p.ny, p.nz, p.dx, p.lambda,
+                                                 h, offset[i], b->stream);
+        if (e == hipSuccess) e = b->to_grid(i);
         if (e != hipSuccess) return fail(SPFM_E_HIP, "init launch: %s", hipGetErrorString(e));
         b->track[i].reset(1, slab_area(p.nx, p.ny, p.nz, p.dx, hkl + 3 * i));
+    }
+    b->nsteps = 0;
+    return SPFM_OK;
+}
+
+spfm_status spfm_batch_init_front(spfm_batch* b, const double* n, const double* offset) {
+    if (!b || !n || !offset) return fail(SPFM_E_INVAL, "NULL argument");
+    for (int i = 0; i < b->n; ++i) {
+        const double* ni = n + 3 * i;
+        const double nn = std::sqrt(ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2]);
+        if (!(nn > 0.0) || !std::isfinite(nn))
+            return fail(SPFM_E_INVAL, "grid %d: n must be finite and nonzero", i);
+        if (!std::isfinite(offset[i])) return fail(SPFM_E_INVAL, "grid %d: offset not finite", i);
+        for (int d = 0; d < 3; ++d)
+            if (ni[d] != 0.0 && !((b->walls >> d) & 1))
+                return fail(SPFM_E_INVAL, "grid %d: a front varying along axis %d needs walls on that axis",
+                            i, d);
+    }
+    for (int i = 0; i < b->n; ++i) {
+        const Params& p = b->r[i].p;
+        hipError_t e = launch_init_front<float>(b->dense_target(i), p.nx, p.ny, p.nz, p.dx, p.lambda,
+                                                n + 3 * i, offset[i], b->stream);
+        if (e == hipSuccess) e = b->to_grid(i);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "front init: %s", hipGetErrorString(e));
+        b->track[i].reset(1, front_area(p, n + 3 * i));
     }
     b->nsteps = 0;
     return SPFM_OK;
@@ -1058,8 +1138,9 @@ spfm_status spfm_batch_set_field(spfm_batch* b, int32_t i, const void* src, int 
     if (!b || i < 0 || i >= b->n) return fail(SPFM_E_INVAL, "bad batch index");
     const Params& p = b->r[i].p;
     const size_t bytes = (size_t)p.nx * p.ny * p.nz * sizeof(float);
-    spfm_status st = copy_in(b->buf[b->cur] + b->offset[i], src, bytes, src_on_device, b->stream);
+    spfm_status st = copy_in(b->dense_target(i), src, bytes, src_on_device, b->stream);
     if (st != SPFM_OK) return st;
+    HIP_TRY(b->to_grid(i));
     b->track[i].reset(0, 0.0);
     return SPFM_OK;
 }
@@ -1068,7 +1149,9 @@ spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on
     if (!b || i < 0 || i >= b->n) return fail(SPFM_E_INVAL, "bad batch index");
     const Params& p = b->r[i].p;
     const size_t bytes = (size_t)p.nx * p.ny * p.nz * sizeof(float);
-    return copy_out(dst, b->buf[b->cur] + b->offset[i], bytes, dst_on_device, b->stream);
+    const float* src = nullptr;
+    HIP_TRY(b->dense_grid(i, &src));
+    return copy_out(dst, src, bytes, dst_on_device, b->stream);
 }
 
 spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
@@ -1081,8 +1164,9 @@ spfm_status spfm_batch_diagnostics(spfm_batch* b, spfm_diag* out) {
     int bad = 0;
     for (int i = 0; i < b->n; ++i) {
         const Params& p = b->r[i].p;
-        spfm_status st = b->red.run(b->buf[b->cur] + b->offset[i], SPFM_F32,
-                                    (int64_t)p.nx * p.ny * p.nz, b->stream);
+        const float* field = nullptr;
+        HIP_TRY(b->dense_grid(i, &field));
+        spfm_status st = b->red.run(field, SPFM_F32, (int64_t)p.nx * p.ny * p.nz, b->stream);
         if (st != SPFM_OK) return st;
         b->track[i].fill(&out[i], *b->red.h_out, p.dx, p.lambda, b->nsteps, p.dt);
         bad += out[i].diverged;

@@ -384,6 +384,10 @@ __host__ __device__ __forceinline__ int xcd_remap(int b, int n) {
 int64_t wall_ghosts(int sx, int sy, int sz, int walls);
 template <typename T>
 hipError_t launch_fill_walls(T* phi, const WallCoef<T>& w, int64_t nghost, hipStream_t s);
+// The ghosts of n grids in one launch: grid g at buf + d_offset[g] with
+// coefficients d_w[g]; max_ghost = the largest ghost count (n <= 65535).
+hipError_t launch_fill_walls_batched(float* buf, const WallCoef<float>* d_w, const int64_t* d_offset,
+                                     int n, int64_t max_ghost, hipStream_t s);
 template <typename T>
 hipError_t launch_box_copy(T* dst, int dnx, int dny, int dx0, int dy0, int dz0, const T* src,
                            int snx, int sny, int sx0, int sy0, int sz0, int bx, int by, int bz,

@@ -17,9 +17,9 @@ namespace spfm {
 
 namespace {
 
+// Ghost point i of the stored field phi (i beyond the ghost count: nothing).
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill_walls(T* __restrict__ phi, WallCoef<T> w) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void fill_ghost(T* __restrict__ phi, const WallCoef<T>& w, int64_t i) {
     const int SX = w.sx, SY = w.sy, SZ = w.sz;
     const int gx = w.walls & 1, gy = (w.walls >> 1) & 1, gz = (w.walls >> 2) & 1;
     // Ghost cells in three disjoint sets: the x-ghost planes (all y, z), the
@@ -55,6 +55,22 @@ __global__ __launch_bounds__(256) void k_fill_walls(T* __restrict__ phi, WallCoe
     const T a = w.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)];
     const T v = phi[src];
     phi[dst] = (T(1) - a) * v / (T(1) - a * (T(2) * v - T(1)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_walls(T* __restrict__ phi, WallCoef<T> w) {
+    fill_ghost(phi, w, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// The ghosts of every grid of a batch: blockIdx.y selects the grid (its field
+// at buf + offset[g], its coefficients w[g]); blocks past its ghost count exit.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_walls_batched(T* __restrict__ buf,
+                                                            const WallCoef<T>* __restrict__ w,
+                                                            const int64_t* __restrict__ offset) {
+    const int g = blockIdx.y;
+    const WallCoef<T> wc = w[g];
+    fill_ghost(buf + offset[g], wc, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // dst box origin (dx0, dy0, dz0) in a dst field of dims (dnx, dny), src likewise;
@@ -105,6 +121,15 @@ template <typename T>
 hipError_t launch_fill_walls(T* phi, const WallCoef<T>& w, int64_t nghost, hipStream_t s) {
     if (nghost <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_fill_walls<T>), dim3(blocks_for(nghost)), dim3(256), 0, s, phi, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_walls_batched(float* buf, const WallCoef<float>* d_w, const int64_t* d_offset,
+                                     int n, int64_t max_ghost, hipStream_t s) {
+    if (n <= 0 || max_ghost <= 0) return hipSuccess;
+    if (n > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fill_walls_batched<float>), dim3(blocks_for(max_ghost), (unsigned)n), dim3(256),
+                       0, s, buf, d_w, d_offset);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
                 ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6),
-                ("interp", ctypes.c_int32), ("conserve_volume", ctypes.c_int32)]
+                ("interp", ctypes.c_int32), ("conserve_volume", ctypes.c_int32),
+                ("batch_wall_sin", ctypes.c_void_p)]
 
 
 class Diag(ctypes.Structure):
@@ -112,6 +113,7 @@ def load():
         "spfm_get_info": ([vp, ctypes.POINTER(Info)], ctypes.c_int),
         "spfm_batch_create": ([i32, ctypes.POINTER(Grid), dp, dp, dp, dp, ctypes.c_int,
                                ctypes.POINTER(Options), ctypes.POINTER(vp)], ctypes.c_int),
+        "spfm_batch_init_front": ([vp, dp, dp], ctypes.c_int),
         "spfm_batch_destroy": ([vp], None),
         "spfm_batch_init_planar": ([vp, ip, dp], ctypes.c_int),
         "spfm_batch_set_field": ([vp, i32, vp, ctypes.c_int], ctypes.c_int),
@@ -319,12 +321,19 @@ class Spfm:
 
 
 class SpfmBatch:
-    """Many independent periodic grids stepped by one launch per step."""
+    """Many independent grids stepped by one launch per step.  With walls,
+    wall_sin may hold one row of six face values per grid."""
 
-    def __init__(self, shapes, *, lam, mu, dx=1.0, Gamma=1.0, M=1.0, stencil=26, **opts):
+    def __init__(self, shapes, *, lam, mu, dx=1.0, Gamma=1.0, M=1.0, stencil=26, wall_sin=None,
+                 **opts):
         L = load()
         n = len(shapes)
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        per_grid = wall_sin is not None and np.ndim(wall_sin) == 2
+        if per_grid:
+            self._wall_sin = np.ascontiguousarray(np.asarray(wall_sin, dtype=np.float64).reshape(n, 6))
+        elif wall_sin is not None:
+            opts["wall_sin"] = wall_sin
 
         def arr(v):
             v = np.broadcast_to(np.asarray(v, dtype=np.float64), (n,))
@@ -334,6 +343,8 @@ class SpfmBatch:
         dxs = arr(dx)
         grids = (Grid * n)(*[Grid(s[2], s[1], s[0], float(dxs[i])) for i, s in enumerate(self.shapes)])
         self._opts = _options(**opts)
+        if per_grid:
+            self._opts.batch_wall_sin = self._wall_sin.ctypes.data
         dp = ctypes.POINTER(ctypes.c_double)
         h = ctypes.c_void_p()
         _check(L.spfm_batch_create(n, grids, self._lam.ctypes.data_as(dp), self._Gamma.ctypes.data_as(dp),
@@ -368,6 +379,13 @@ class SpfmBatch:
         o = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1))
         _check(load().spfm_batch_init_planar(self._h, h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                              o.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def init_front(self, normals, offsets):
+        """Planar fronts of the given normals (one row of three per grid)."""
+        nv = np.ascontiguousarray(np.asarray(normals, dtype=np.float64).reshape(-1, 3))
+        o = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().spfm_batch_init_front(self._h, nv.ctypes.data_as(dp), o.ctypes.data_as(dp)))
 
     def set_field(self, i: int, field):
         a = np.ascontiguousarray(field, dtype=np.float32)

@@ -185,3 +185,67 @@ def test_orientation_study_fp32_equals_fp64(S):
     v32 = front_velocity(S, n, dtype="f32", steps=800)
     v64 = front_velocity(S, n, dtype="f64", steps=800)
     assert abs(v32 / v64 - 1.0) < 1e-4
+
+
+ORIENTATIONS = [rot001(math.radians(d)) for d in (0, 15, 30, 45)] + \
+               [rot011(math.radians(d)) for d in (15, 30, 45)]
+
+
+def test_walled_batch_equals_single_contexts(S):
+    """The orientation study as one batch (seven 120 x 10 x 10 walled grids,
+    each with its own wall angles and driving force) equals seven separate
+    walled contexts bit for bit, field and front position."""
+    shape, lam, mu0, dt, steps = (10, 10, 120), 4.0, 0.05, 0.05, 300
+    ns = [np.asarray(n) / np.linalg.norm(n) for n in ORIENTATIONS]
+    sins = [oracle.front_sin_alpha(n) for n in ns]
+    mus = [mu0 * n[0] for n in ns]
+    print(f"case walled batch of {len(ns)} orientations, {steps} steps", flush=True)
+    with S.SpfmBatch([shape] * len(ns), lam=lam, mu=mus, stencil=26, coupling="local", dt=dt,
+                     walls=7, wall_sin=sins) as b:
+        b.init_front(ns, [20.0] * len(ns))
+        b.step(steps)
+        db = b.diagnostics()
+        fields = [b.get_field(i) for i in range(len(ns))]
+    for i, n in enumerate(ns):
+        with S.Spfm(shape, lam=lam, mu=mus[i], stencil=26, dtype="f32", coupling="local", dt=dt,
+                    walls=7, wall_sin=sins[i], kernel="tiled") as s:
+            s.init_front(n, 20.0)
+            s.step(steps)
+            d = s.diagnostics()
+            assert np.array_equal(s.get_field(), fields[i]), i
+        assert d["interface_position"] == db[i]["interface_position"], i
+        assert d["sum_phi"] == db[i]["sum_phi"], i
+
+
+@pytest.mark.parametrize("walls", [1, 6, 7])
+def test_walled_batch_of_uneven_grids_matches_the_oracle(S, walls):
+    """Grids of different, ragged sizes with the same walled axes, each with its
+    own wall angles, against the oracle's wall-after-wall fill (FP32 bar)."""
+    shapes = [(9, 11, 37), (5, 6, 20), (12, 3, 70)] if walls != 1 else [(9, 11, 37), (5, 6, 20)]
+    lam, mu = 2.5, 0.02
+    rng = np.random.default_rng(7)
+    sas, fields, ps = [], [], []
+    for shape in shapes:
+        n = rng.normal(size=3)
+        n[[d for d in range(3) if not (walls >> d) & 1]] = 0.0
+        n[0] = abs(n[0]) + 0.5 if walls & 1 else n[0]
+        n = n / np.linalg.norm(n)
+        sa = oracle.front_sin_alpha(n)
+        sas.append(sa)
+        fields.append(as_f32_input(oracle.front(shape, n, 0.7, lam=lam)))
+        p = oracle.params(shape, lam=lam, mu=mu, stencil=26, coupling="local", eps=1e-30)
+        ps.append(p)
+    dt = min(stable_dt(p) for p in ps)
+    steps = 60
+    print(f"case walled batch walls={walls} shapes={shapes}", flush=True)
+    with S.SpfmBatch(shapes, lam=lam, mu=mu, stencil=26, coupling="local", dt=dt, walls=walls,
+                     wall_sin=sas) as b:
+        for i, f in enumerate(fields):
+            b.set_field(i, f)
+            assert np.array_equal(b.get_field(i), f.astype(np.float32))
+        b.step(steps)
+        got = [b.get_field(i).astype(np.float64) for i in range(len(shapes))]
+    for i, p in enumerate(ps):
+        p.dt = dt
+        ref = oracle.step_walls(p, fields[i], walls, sas[i], steps)
+        assert float(np.abs(got[i] - ref).max()) <= 1e-5, i

@@ -113,3 +113,33 @@ def test_stability_bound_follows_the_interpolation(S, orc, interp):
     st, _ = S.try_create((16, 16, 16), lam=2.0, mu=0.4, coupling="cf", interp=interp,
                          dt=0.99 * orc.stable_dt(p))
     assert st != -4
+
+
+def try_batch(S, shapes, **kw):
+    """spfm_batch_create on the CPU: returns (status, message); validation runs
+    before any device allocation."""
+    try:
+        b = S.SpfmBatch(shapes, lam=4.0, mu=0.01, **kw)
+    except S.SpfmError as e:
+        return e.status, str(e)
+    b.close()
+    return 0, ""
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(walls=1, wall_sin=[(0, 0, 0, 0, 0, 0), (1.5, 0, 0, 0, 0, 0)]), "grid 1: wall_sin[0]"),
+    (dict(walls=1, wall_sin=[(0, float("nan"), 0, 0, 0, 0), (0, 0, 0, 0, 0, 0)]), "grid 0: wall_sin[1]"),
+    (dict(walls=1, tsteps=2), "tsteps"),
+    (dict(walls=1, conserve_volume=True), "conserve_volume"),
+])
+def test_walled_batch_validates_each_grid(S, kw, needle):
+    st, msg = try_batch(S, [(8, 8, 20), (8, 8, 24)], **kw)
+    assert st == -1 and needle in msg, msg
+
+
+def test_walled_batch_accepts_short_walled_axes(S):
+    """A walled axis needs only one point (its ghost layers complete the
+    stencil), per grid of a batch as for a single grid: validation passes, and
+    creation then stops only at the device."""
+    st, msg = try_batch(S, [(1, 1, 50), (2, 3, 40)], walls="yz", wall_sin=[(0,) * 6, (0,) * 6])
+    assert st != -1, msg
