@@ -92,19 +92,26 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     // In-plane byte offsets (fixed along the sweep) and LDS positions of this
     // thread's two halo cells; cells are numbered row by row so that loads are
     // coalesced.  The first always exists, the second only for tid + NT < NC.
+    // Periodic wrap of a halo coordinate v in [-1, n + H - 2] (H = halo extent):
+    // one conditional add or subtract when n >= H (the grid-wide, uniform
+    // common case), a modulo for grids narrower than a tile.
+    auto wrap = [](int v, int n, int H) {
+        if (n >= H) {
+            v = v < 0 ? v + n : v;
+            return v >= n ? v - n : v;
+        }
+        v %= n;
+        return v < 0 ? v + n : v;
+    };
     int loff0, loff1, soff0, soff1;
     {
-        int gx = x0 - 1 + tid % HX, gy = y0 - 1 + tid / HX;
+        const int gx = wrap(x0 - 1 + tid % HX, nx, HX), gy = wrap(y0 - 1 + tid / HX, ny, HY);
         soff0 = (tid / HX) * LX + tid % HX;
-        gx %= nx; if (gx < 0) gx += nx;
-        gy %= ny; if (gy < 0) gy += ny;
         loff0 = (gy * nx + gx) * (int)sizeof(T);
         const int c1 = tid + NT;
         soff1 = (c1 / HX) * LX + c1 % HX;
-        gx = x0 - 1 + c1 % HX; gy = y0 - 1 + c1 / HX;
-        gx %= nx; if (gx < 0) gx += nx;
-        gy %= ny; if (gy < 0) gy += ny;
-        loff1 = c1 < NC ? (gy * nx + gx) * (int)sizeof(T) : 0;
+        const int hx = wrap(x0 - 1 + c1 % HX, nx, HX), hy = wrap(y0 - 1 + c1 / HX, ny, HY);
+        loff1 = c1 < NC ? (hy * nx + hx) * (int)sizeof(T) : 0;
     }
     const bool has1 = tid + NT < NC;
     const int nout = min(zlen, nz - z0);   // output planes z0 .. z0+nout-1
