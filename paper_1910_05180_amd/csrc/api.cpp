@@ -532,11 +532,11 @@ int default_zlen(int nx, int ny, int nz, int tx, int ty, bool guided, int64_t mi
 // counts (so that neighbouring rows also share an L2, which pays when the
 // fields do not fit the last-level cache).  Each XCD's list holds its rows' tile
 // columns cut along z by guided_chunks (tails from tail_planes of the total
-// point count): all phase-0 chunks first (grid by grid,
-// z chunk by z chunk), then the tail chunks phase by phase, so the blocks
-// dispatched last are short and the SIMDs run out of work together instead of
-// idling behind a few long blocks at the end of the step.  Shorter XCD lists
-// are padded with empty items (zlen 0).
+// point count): all phase-0 chunks first (grid by grid, z chunk by z chunk),
+// then the tail chunks phase by phase, so the blocks dispatched last are short
+// and the SIMDs run out of work together instead of idling behind a few long
+// blocks at the end of the step.  Shorter XCD lists are padded with empty items
+// (zlen 0).
 struct GridDims {
     int nx, ny, nz;
 };
