@@ -31,16 +31,16 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # the grain workload, counted from the per-point formulas the kernel evaluates:
 # 28 where phi(1-phi) = 0 (psi' 6, plane sums 6, shell sums 8, update 7, test 1),
 # 64 in the tail branch (plus the normal 9, the exponentials and c_i 15, the
-# tail sums 9, u and its term 2, test 1) and 163 with the full coupling (99
-# more: 2 sinh 6, the shell-2 and shell-3 m_k 37, three running fractions 52,
-# their sum 3, select 1).  The point mix over the timed steps (2050 to 3050 of
-# the run) is 13.1% / 79.8% / 7.1%.
-ALG_OPS_LOCAL26 = 0.131 * 28 + 0.798 * 64 + 0.071 * 163
+# tail sums 9, u and its term 2, test 1) and 157 with the full coupling (93
+# more: 2 sinh 6, x-scaled terms 4, the shell-2 and shell-3 y_k 40, three running
+# fractions 39, their sum 3, select 1).  The point mix over the timed steps
+# (2050 to 3050 of the run) is 13.1% / 79.8% / 7.1%.
+ALG_OPS_LOCAL26 = 0.131 * 28 + 0.798 * 64 + 0.071 * 157
 ZCHUNK = 32                    # leading planes per block (the fastest in sweeps of 16..64)
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the factors the same counters give for the copy
 # reference; None whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = (44103.8 * 2.0 + 65536.0) * 1024
+TRAFFIC_BYTES_LOCAL26 = None
 
 
 def parse():

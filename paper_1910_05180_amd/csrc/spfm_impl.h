@@ -115,11 +115,11 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 __device__ __forceinline__ void keep_branch() { __asm__ volatile("" ::: "memory"); }
 
 // Running sum of y_k / (1 + y_k) kept as one fraction num/den, started from
-// the first term y_0 = m x.
+// the first term y_0.
 template <typename T>
 struct Frac {
     T num, den;
-    __device__ __forceinline__ Frac(T m, T x) : num(m * x), den(fma(m, x, T(1))) {}
+    __device__ __forceinline__ explicit Frac(T y) : num(y), den(y + T(1)) {}
     __device__ __forceinline__ void add(T y) {
         num = fma(y, num + den, num);
         den = fma(den, y, den);
@@ -127,23 +127,25 @@ struct Frac {
     __device__ __forceinline__ T value() const { return num * fast_rcp(den); }
 };
 
-// sum_j K_j sum_{k in shell j} y_k / (1 + y_k) with y_k = m_k x, one fraction per shell.
+// sum_j K_j sum_{k in shell j} y_k / (1 + y_k), one fraction per shell (y2 is
+// read for S >= 18, y3 for S = 26).
 template <typename T, int S>
-__device__ __forceinline__ T shell_sums(T m1x, T m1y, T m1z, const T (&m2)[6], const T (&m3)[4], T x,
+__device__ __forceinline__ T shell_sums(const T (&y1)[3], const T (&y2)[6], const T (&y3)[4],
                                         const StepCoef<T>& k) {
-    Frac<T> f1(m1x, x);
-    f1.add(m1y * x); f1.add(m1z * x);
+    Frac<T> f1(y1[0]);
+    f1.add(y1[1]);
+    f1.add(y1[2]);
     T q = k.K[0] * f1.value();
     if (S >= 18) {
-        Frac<T> f2(m2[0], x);
+        Frac<T> f2(y2[0]);
 #pragma unroll
-        for (int i = 1; i < 6; ++i) f2.add(m2[i] * x);
+        for (int i = 1; i < 6; ++i) f2.add(y2[i]);
         q = fma(k.K[1], f2.value(), q);
     }
     if (S >= 26) {
-        Frac<T> f3(m3[0], x);
+        Frac<T> f3(y3[0]);
 #pragma unroll
-        for (int i = 1; i < 4; ++i) f3.add(m3[i] * x);
+        for (int i = 1; i < 4; ++i) f3.add(y3[i]);
         q = fma(k.K[2], f3.value(), q);
     }
     return q;
@@ -248,42 +250,55 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             const bool full = !(fabs(x) < k.xtail);
             if (__ballot(full) != 0) {
                 keep_branch();
-                T m2[6];   // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
-                T m3[4];   // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
-                // 2cosh(a+-b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2
-                {
-                    const T ps = sx * sy, base = cx + cy;
-                    m2[0] = fma(T(0.5), fma(cx, cy, ps), base);
-                    m2[1] = fma(T(0.5), fma(cx, cy, -ps), base);
-                }
-                {
-                    const T ps = sy * sz, base = cy + cz;
-                    m2[2] = fma(T(0.5), fma(cy, cz, ps), base);
-                    m2[3] = fma(T(0.5), fma(cy, cz, -ps), base);
-                }
-                {
-                    const T ps = sx * sz, base = cx + cz;
-                    m2[4] = fma(T(0.5), fma(cx, cz, ps), base);
-                    m2[5] = fma(T(0.5), fma(cx, cz, -ps), base);
+                // y_k = x m_k straight from x-scaled pieces: with
+                // 2cosh(a +- b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2,
+                // y = x c_a + x c_b + (x/2)(c_a c_b +- s_a s_b).
+                const T xh = T(0.5) * x;
+                const T y1[3] = {x * cx, x * cy, x * cz};
+                T y2[6];   // shell 2: x+y, x-y, y+z, y-z, x+z, x-z
+                T y3[4];   // shell 3: x+y+z, x+y-z, x-y+z, x-y-z
+                T pxy = T(0), mxy = T(0);   // c_x c_y +- s_x s_y
+                if (S >= 18) {
+                    {
+                        const T ps = sx * sy, b = y1[0] + y1[1];
+                        pxy = fma(cx, cy, ps);
+                        mxy = fma(cx, cy, -ps);
+                        y2[0] = fma(xh, pxy, b);
+                        y2[1] = fma(xh, mxy, b);
+                    }
+                    {
+                        const T ps = sy * sz, b = y1[1] + y1[2];
+                        y2[2] = fma(xh, fma(cy, cz, ps), b);
+                        y2[3] = fma(xh, fma(cy, cz, -ps), b);
+                    }
+                    {
+                        const T ps = sx * sz, b = y1[0] + y1[2];
+                        y2[4] = fma(xh, fma(cx, cz, ps), b);
+                        y2[5] = fma(xh, fma(cx, cz, -ps), b);
+                    }
                 }
                 if (S >= 26) {
-                    // 2sinh(a+-b) = (s_a (c_b+2) +- (c_a+2) s_b)/2, then
-                    // 2cosh(w+-z) - 2 = m_w + c_z + (m_w c_z +- s_w s_z)/2
+                    // w = x +- y: m_w = c_x + c_y + (c_x c_y +- s_x s_y)/2 and
+                    // 2sinh(w) = (s_x (c_y+2) +- (c_x+2) s_y)/2; then
+                    // x (2cosh(w +- z) - 2) = x m_w + x c_z + (x/2)(m_w c_z +- s_w s_z),
+                    // with x m_w = y2[0] or y2[1].
+                    const T cxy = cx + cy;
+                    const T mp = fma(T(0.5), pxy, cxy), mm = fma(T(0.5), mxy, cxy);
                     const T csy = (cx + T(2)) * sy;
-                    const T hxy_p = T(0.5) * fma(sx, cy + T(2), csy);
-                    const T hxy_m = T(0.5) * fma(sx, cy + T(2), -csy);
+                    const T hp = T(0.5) * fma(sx, cy + T(2), csy);
+                    const T hm = T(0.5) * fma(sx, cy + T(2), -csy);
                     {
-                        const T ps = hxy_p * sz, base = m2[0] + cz;
-                        m3[0] = fma(T(0.5), fma(m2[0], cz, ps), base);
-                        m3[1] = fma(T(0.5), fma(m2[0], cz, -ps), base);
+                        const T ps = hp * sz, b = y2[0] + y1[2];
+                        y3[0] = fma(xh, fma(mp, cz, ps), b);
+                        y3[1] = fma(xh, fma(mp, cz, -ps), b);
                     }
                     {
-                        const T ps = hxy_m * sz, base = m2[1] + cz;
-                        m3[2] = fma(T(0.5), fma(m2[1], cz, ps), base);
-                        m3[3] = fma(T(0.5), fma(m2[1], cz, -ps), base);
+                        const T ps = hm * sz, b = y2[1] + y1[2];
+                        y3[2] = fma(xh, fma(mm, cz, ps), b);
+                        y3[3] = fma(xh, fma(mm, cz, -ps), b);
                     }
                 }
-                const T qf = shell_sums<T, S>(cx, cy, cz, m2, m3, x, k);
+                const T qf = shell_sums<T, S>(y1, y2, y3, k);
                 q = full ? qf : q;
             }
         } else {
@@ -291,12 +306,13 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
             const bool full = !(fabs(x) < k.xtail);
             if (__ballot(full) != 0) {
                 keep_branch();
-                T m2[6], m3[4];
+                const T y1[3] = {k.mg[0] * x, k.mg[1] * x, k.mg[2] * x};
+                T y2[6], y3[4];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) m2[i] = k.mg[3 + i];
+                for (int i = 0; i < 6; ++i) y2[i] = k.mg[3 + i] * x;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) m3[i] = k.mg[9 + i];
-                const T qf = shell_sums<T, S>(k.mg[0], k.mg[1], k.mg[2], m2, m3, x, k);
+                for (int i = 0; i < 4; ++i) y3[i] = k.mg[9 + i] * x;
+                const T qf = shell_sums<T, S>(y1, y2, y3, k);
                 q = full ? qf : q;
             }
         }

@@ -264,10 +264,11 @@ struct Smem {
 };
 
 #ifndef SPFM_WAVES_F32
-#define SPFM_WAVES_F32 6
+#define SPFM_WAVES_F32 7
 #endif
-// Waves per SIMD the tiled kernels are compiled for: FP32 fits its working set
-// in 64 VGPRs (8 waves); FP64 needs about twice as many registers.
+// Waves per SIMD the tiled kernels are compiled for: FP32 TI_n fits in 72 VGPRs
+// (7 waves; left free, the compiler takes 79 and 6 waves, which ran 1.5%
+// slower); FP64 needs about twice as many registers.
 template <typename T>
 struct WavesPerSimd {
     static constexpr int value = sizeof(T) == 4 ? SPFM_WAVES_F32 : 4;
