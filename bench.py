@@ -153,8 +153,8 @@ def walls_leg(spfm, torch, warm=400, steps=1600):
     planar fronts rotated about [001] (0, 15, 30, 45 degrees) and [011] (15, 30,
     45 degrees) between contact-angle walls (Eq. 7) that hold their
     orientation, TI_n, 26 neighbours, lambda = 4 dx, mu = mu0 cos(theta),
-    mu0 = 0.05, dt = 0.05, FP32, all seven in one walled batch (one fill and
-    one step launch per step).  Reports the aggregate step rate and the largest
+    mu0 = 0.05, dt = 0.05, FP32, all seven in one walled batch (one step
+    launch per step; the kernel computes the wall ghosts as it reads them).  Reports the aggregate step rate and the largest
     relative error of the fronts' x-velocity against -M mu0 / Gamma."""
     import math
     import numpy as np

@@ -238,11 +238,12 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * launch per step covers every tile of every grid, and spfm_batch_step
  * captures the launches of n steps in one HIP graph.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
- * eps, tau, allow_unstable, walls) apply to every grid; each grid gets its own
+ * eps, tau, allow_unstable, walls, zchunk) apply to every grid (zchunk 0: 32
+ * planes, halved down to 4 while the batch gives fewer than 2^19 threads); each grid gets its own
  * lambda, Gamma, M, mu and, with walls, its own wall angles from
  * batch_wall_sin (the orientation sweeps of Sec. 3.2 in one launch; the
- * ghosts of every grid are filled by one more launch per step, at most 65535
- * grids); d_phi must be NULL, tsteps <= 1 and conserve_volume 0.  Fields,
+ * kernel computes the ghost values of Eq. 7 as it reads them); d_phi must be
+ * NULL, tsteps <= 1 and conserve_volume 0.  Fields,
  * initial conditions and diagnostics refer to the interior of each grid. */
 spfm_status spfm_batch_create(int32_t n, const spfm_grid *grids, const double *lambda,
                               const double *Gamma, const double *M, const double *mu,

@@ -315,6 +315,9 @@ struct spfm_ctx {
     WallCoef<float> wf;
     WallCoef<double> wd;
     int64_t nghost = 0;
+    // Device copy of the wall coefficients of the stored dtype (walls only), read
+    // by the tiled kernels, which compute the ghosts they need themselves.
+    void* d_wall = nullptr;
     // Constant volume: coefficients without the driving force, and device
     // scratch for the reductions (kReduceBlocks x 8 partials, then g, mu, then
     // the 7 contour results).
@@ -370,7 +373,7 @@ struct spfm_ctx {
         const void* in = buf[from];
         void* out = buf[1 - from];
         const int S = r.p.stencil, C = kernel_coupling(r.p.coupling, r.p.interp);
-        if (r.walls) {   // ghost layers of the input from Eq. 7, then the step on the stored grid
+        if (r.walls && r.kernel == SPFM_KERNEL_PLAIN) {   // ghost layers of the input from Eq. 7
             const hipError_t e = r.dtype == SPFM_F64
                                      ? launch_fill_walls<double>((double*)buf[from], wd, nghost, stream)
                                      : launch_fill_walls<float>((float*)buf[from], wf, nghost, stream);
@@ -383,12 +386,12 @@ struct spfm_ctx {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
                     : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, d_items,
-                                                nitems, stream);
+                                                nitems, (const WallCoef<double>*)d_wall, stream);
         } else {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
                     : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, d_items,
-                                               nitems, stream);
+                                               nitems, (const WallCoef<float>*)d_wall, stream);
         }
         if (e != hipSuccess || !r.conserve_volume) return e;
         // the step ran without the driving force; add the one that keeps sum phi
@@ -435,10 +438,9 @@ struct spfm_batch {
     int nitems = 0;
     int stencil = 26, coupling = 0;
     // Walls (the same axes on every grid): per-grid coefficients on the device,
-    // and the largest ghost count, the extent of the batched fill.
+    // read by the batched kernel, which computes the ghosts it needs itself.
     int walls = 0;
     WallCoef<float>* d_wall = nullptr;
-    int64_t max_ghost = 0;
     Reducer red;
     std::vector<Tracker> track;
     GraphCache graphs;
@@ -446,13 +448,8 @@ struct spfm_batch {
     int unit() const { return 1; }
     hipError_t launch_unit(int from) { return launch_one(from); }
     hipError_t launch_one(int from) {
-        if (walls) {   // ghost layers of every input grid from Eq. 7, then the step
-            const hipError_t e = launch_fill_walls_batched(buf[from], d_wall, d_offset, n, max_ghost,
-                                                           stream);
-            if (e != hipSuccess) return e;
-        }
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
-                                   stencil, coupling, stream);
+                                   walls ? d_wall : nullptr, stencil, coupling, stream);
     }
     // Grid i as a dense array: its region of the current buffer, or (with walls)
     // its interior packed into its region of the other buffer, which the next
@@ -509,17 +506,32 @@ int tail_planes(int nz, int64_t total_points) {
     return std::min(nz, (int)std::lround(f * nz));
 }
 
-// Planes per block: the longest z-chunk (at most kTileZ) that still gives at
-// least min_threads threads for tiles tx x ty, counting the guided chunks of
-// the single-grid step (guided) or uniform chunks (the temporal kernel).
-int default_zlen(int nx, int ny, int nz, int tx, int ty, bool guided, int64_t min_threads) {
-    const int64_t cols = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
-    const int tail = tail_planes(nz, (int64_t)nx * ny * nz);
-    auto chunks = [&](int zb) -> int64_t {
-        return guided ? (int64_t)guided_chunks(nz, zb, tail).size() : (nz + zb - 1) / zb;
+// Tile grids of a schedule (stored dimensions).
+struct GridDims {
+    int nx, ny, nz;
+};
+
+// Planes per block: the longest z-chunk (kTileZ, halved down to zmin) that
+// still gives at least min_threads threads for tiles tx x ty over all grids,
+// counting the guided chunks of the single-step schedule (guided) or uniform
+// chunks (the temporal kernel).  Grids too small to fill the GPU get shorter
+// chunks: more blocks, each with a shorter dependent chain of plane loads.
+int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided,
+                 int64_t min_threads, int zmin) {
+    int64_t total = 0;
+    for (const GridDims& d : grids) total += (int64_t)d.nx * d.ny * d.nz;
+    auto threads = [&](int zb) {
+        int64_t t = 0;
+        for (const GridDims& d : grids) {
+            const int64_t cols = (int64_t)((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty);
+            const int64_t ch = guided ? (int64_t)guided_chunks(d.nz, zb, tail_planes(d.nz, total)).size()
+                                      : (d.nz + zb - 1) / zb;
+            t += cols * ch * tx * ty;
+        }
+        return t;
     };
     int z = kTileZ;
-    while (z > 8 && cols * chunks(z) * tx * ty < min_threads) z /= 2;
+    while (z > zmin && threads(z) < min_threads) z /= 2;
     return z;
 }
 
@@ -537,9 +549,6 @@ int default_zlen(int nx, int ny, int nz, int tx, int ty, bool guided, int64_t mi
 // and the SIMDs run out of work together instead of idling behind a few long
 // blocks at the end of the step.  Shorter XCD lists are padded with empty items
 // (zlen 0).
-struct GridDims {
-    int nx, ny, nz;
-};
 std::vector<TileItem> tile_schedule(const std::vector<GridDims>& grids, int tx, int ty, int zb,
                                     bool spread) {
     struct Row {
@@ -737,8 +746,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     const int tx = temporal ? 64 : tile_x(f32, r.p.coupling);      // temporal: 64 x 8
     c->zlen = (opt && opt->zchunk > 0)
                   ? opt->zchunk
-                  : default_zlen(r.sx, r.sy, r.sz, tx, kTileY, !temporal,
-                                 temporal ? (int64_t)1 << 20 : (int64_t)1 << 19);
+                  : default_zlen({GridDims{r.sx, r.sy, r.sz}}, tx, kTileY, !temporal,
+                                 temporal ? (int64_t)1 << 20 : (int64_t)1 << 19, 8);
     const size_t bytes = c->stored_bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
@@ -764,6 +773,21 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
         return fail(SPFM_E_NOMEM, "device allocation of the reduction scratch failed");
     }
     c->refresh_coef();
+    if (r.walls && r.kernel == SPFM_KERNEL_TILED) {
+        const bool f64 = r.dtype == SPFM_F64;
+        const size_t wb = f64 ? sizeof(WallCoef<double>) : sizeof(WallCoef<float>);
+        if (hipMalloc(&c->d_wall, wb) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_wall = nullptr;
+            spfm_destroy(c);
+            return fail(SPFM_E_NOMEM, "device allocation of the wall coefficients failed");
+        }
+        const void* src = f64 ? (const void*)&c->wd : (const void*)&c->wf;
+        if (hipMemcpy(c->d_wall, src, wb, hipMemcpyHostToDevice) != hipSuccess) {
+            spfm_destroy(c);
+            return fail(SPFM_E_HIP, "upload of the wall coefficients failed");
+        }
+    }
     if (r.kernel == SPFM_KERNEL_TILED) {   // single tiled steps (also the remainder of fused ones)
         st = set_schedule(c, c->zlen);
         if (st != SPFM_OK) { spfm_destroy(c); return st; }
@@ -779,6 +803,7 @@ void spfm_destroy(spfm_ctx* c) {
     c->red.release();
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_wall) (void)hipFree(c->d_wall);
     if (c->owns) {
         if (c->buf[0]) (void)hipFree(c->buf[0]);
         if (c->buf[1]) (void)hipFree(c->buf[1]);
@@ -1016,7 +1041,6 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
     if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
     if (o.conserve_volume) return fail(SPFM_E_INVAL, "batches keep mu fixed (conserve_volume = 0)");
-    if (o.walls && n > 65535) return fail(SPFM_E_INVAL, "batches with walls hold at most 65535 grids");
     spfm_batch* b = new (std::nothrow) spfm_batch;
     if (!b) return fail(SPFM_E_NOMEM, "host allocation failed");
     b->n = n;
@@ -1054,13 +1078,11 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         const int64_t ns = (int64_t)ri.sx * ri.sy * ri.sz;
         off += (ns + 63) / 64 * 64;   // keep every grid 256-byte aligned
         dims[i] = GridDims{ri.sx, ri.sy, ri.sz};
-        if (o.walls) {
-            wall[i] = wall_coef<float>(ri);
-            b->max_ghost = std::max(b->max_ghost, wall_ghosts(ri.sx, ri.sy, ri.sz, ri.walls));
-        }
+        if (o.walls) wall[i] = wall_coef<float>(ri);
     }
-    const std::vector<TileItem> items =
-        tile_schedule(dims, tile_x(true, o.coupling), kTileY, kTileZ, false);
+    const int btx = tile_x(true, o.coupling);
+    const int zb = o.zchunk > 0 ? o.zchunk : default_zlen(dims, btx, kTileY, true, (int64_t)1 << 19, 4);
+    const std::vector<TileItem> items = tile_schedule(dims, btx, kTileY, zb, false);
     if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
     b->total = off;
     b->nitems = (int)items.size();

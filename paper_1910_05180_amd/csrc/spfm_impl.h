@@ -351,6 +351,14 @@ struct WallCoef {
     T a[27];
 };
 
+// Eq. 7 as a map of the inward neighbour's value v: the ideal profile moved by
+// the length d with tanh(2 d / lambda) = a (a = 0 returns v exactly).  The one
+// expression both the ghost fill and the walled sweeps evaluate.
+template <typename T>
+__device__ __forceinline__ T wall_map(T v, T a) {
+    return (T(1) - a) * v / (T(1) - a * (T(2) * v - T(1)));
+}
+
 // ---- launchers (step_kernels.hip, reduce.hip, init.hip, walls.hip) ----
 struct TileItem {   // one block of the batched step: grid index, tile origin, planes
     int inst;
@@ -362,16 +370,22 @@ template <typename T>
 hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              hipStream_t s);
 // One block per entry of the device table d_items (nitems entries, in dispatch order).
+// d_wall (device memory) non-null: the stored grid has contact-angle walls, and
+// ghost cells are computed from their interior neighbours as they are staged
+// (Eq. 7), so no fill launch is needed.
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             const TileItem* d_items, int nitems, hipStream_t s);
+                             const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
+                             hipStream_t s);
 // TB = tsteps (2..4) steps per launch, FP32 (temporal.hip).
 hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<float>& k, int stencil,
                                 int coupling, int tsteps, int zlen, hipStream_t s);
-// Batched step: instance i reads buf_in + offset[i], writes buf_out + offset[i].
+// Batched step: instance i reads buf_in + offset[i], writes buf_out + offset[i];
+// with d_wall (one entry per instance) the grids have walls, as for the tiled step.
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
-                               int stencil, int coupling, hipStream_t s);
+                               const WallCoef<float>* d_wall, int stencil, int coupling,
+                               hipStream_t s);
 // Tiles of the single-step tiled kernels: a block marches one tile column
 // kTileX x kTileY along z, each of its waves computing a 16 x 4 patch.  FP32
 // TI_n uses 16 x 8 columns (two waves): its full-coupling branch makes the
@@ -400,10 +414,6 @@ __host__ __device__ __forceinline__ int xcd_remap(int b, int n) {
 int64_t wall_ghosts(int sx, int sy, int sz, int walls);
 template <typename T>
 hipError_t launch_fill_walls(T* phi, const WallCoef<T>& w, int64_t nghost, hipStream_t s);
-// The ghosts of n grids in one launch: grid g at buf + d_offset[g] with
-// coefficients d_w[g]; max_ghost = the largest ghost count (n <= 65535).
-hipError_t launch_fill_walls_batched(float* buf, const WallCoef<float>* d_w, const int64_t* d_offset,
-                                     int n, int64_t max_ghost, hipStream_t s);
 template <typename T>
 hipError_t launch_box_copy(T* dst, int dnx, int dny, int dx0, int dy0, int dz0, const T* src,
                            int snx, int sny, int sx0, int sy0, int sz0, int bx, int by, int bz,

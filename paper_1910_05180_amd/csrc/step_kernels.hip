@@ -68,10 +68,17 @@ struct PlaneRegs {
 // Planes are numbered relative to the sweep, r = 0 for z0 - 1; plane r lives in
 // LDS slot r & 3.  Iterations start at r = 1 (mod 4) and alternate parity, so the
 // slots each iteration touches are compile-time constants.
-template <typename T, int S, int C>
+//
+// W: the stored grid has contact-angle walls (w in device memory).  A halo cell
+// on a ghost layer is then read from its interior neighbour and mapped by Eq. 7
+// with the composed coefficient of its ghost class as it is staged; ghost planes
+// of a walled z axis are read from their interior neighbour planes.  Points on
+// ghost layers are computed too, and their values are never read.
+template <typename T, int S, int C, bool W>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
-                                           T* __restrict__ sphi, T* __restrict__ spsi) {
+                                           T* __restrict__ sphi, T* __restrict__ spsi,
+                                           const WallCoef<T>* __restrict__ w) {
     // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
     // wave computes a kWaveX x (64 / kWaveX) patch of the tile.
     constexpr int TX = tile_x(sizeof(T) == 4, C), TY = kTileY;
@@ -103,33 +110,57 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         v %= n;
         return v < 0 ? v + n : v;
     };
+    // Walls: a ghost cell is read from its interior neighbour, and wa*[c] is the
+    // Eq. 7 coefficient of its class on a plane of z class c - 1 (0 inside).
+    const int walls = W ? w->walls : 0;
+    T wa0[3] = {T(0), T(0), T(0)}, wa1[3] = {T(0), T(0), T(0)};
+    auto mirror = [&](int& gx, int& gy, T (&a)[3]) {
+        const int cx = (walls & 1) ? (gx == 0 ? -1 : (gx == nx - 1 ? 1 : 0)) : 0;
+        const int cy = (walls & 2) ? (gy == 0 ? -1 : (gy == ny - 1 ? 1 : 0)) : 0;
+        gx -= cx;
+        gy -= cy;
+        const int base = (cx + 1) + 3 * (cy + 1);
+        a[0] = w->a[base];
+        a[1] = w->a[base + 9];
+        a[2] = w->a[base + 18];
+    };
     int loff0, loff1, soff0, soff1;
     {
-        const int gx = wrap(x0 - 1 + tid % HX, nx, HX), gy = wrap(y0 - 1 + tid / HX, ny, HY);
+        int gx = wrap(x0 - 1 + tid % HX, nx, HX), gy = wrap(y0 - 1 + tid / HX, ny, HY);
+        if (W) mirror(gx, gy, wa0);
         soff0 = (tid / HX) * LX + tid % HX;
         loff0 = (gy * nx + gx) * (int)sizeof(T);
         const int c1 = tid + NT;
         soff1 = (c1 / HX) * LX + c1 % HX;
-        const int hx = wrap(x0 - 1 + c1 % HX, nx, HX), hy = wrap(y0 - 1 + c1 / HX, ny, HY);
+        int hx = wrap(x0 - 1 + c1 % HX, nx, HX), hy = wrap(y0 - 1 + c1 / HX, ny, HY);
+        if (W) mirror(hx, hy, wa1);
         loff1 = c1 < NC ? (hy * nx + hx) * (int)sizeof(T) : 0;
     }
     const bool has1 = tid + NT < NC;
     const int nout = min(zlen, nz - z0);   // output planes z0 .. z0+nout-1
     const int last = nout + 1;             // relative index of the last plane needed
 
-    struct Pair { T v0, v1; };
-    auto fetch_at = [&](__amdgpu_buffer_rsrc_t src, Pair& v) {
+    // Two fetched halo cells, with (W) the Eq. 7 coefficients of their classes
+    // on the fetched plane.
+    struct Pair { T v0, v1, a0, a1; };
+    auto fetch_at = [&](__amdgpu_buffer_rsrc_t src, int zc, Pair& v) {
         v.v0 = buf_load(src, loff0, (T*)nullptr);
         v.v1 = buf_load(src, loff1, (T*)nullptr);   // loff1 = 0 where the cell does not exist
+        if (W) {
+            v.a0 = zc == 0 ? wa0[0] : (zc == 2 ? wa0[2] : wa0[1]);
+            v.a1 = zc == 0 ? wa1[0] : (zc == 2 ? wa1[2] : wa1[1]);
+        }
     };
     auto stage_slot = [&](int slot, const Pair& v) {
         T* dphi = sphi + slot * HP;
         T* dpsi = spsi + slot * HP;
-        dphi[soff0] = v.v0;
-        if (C == kLocal) dpsi[soff0] = psi2(v.v0, k.eps);
+        const T u0 = W ? wall_map(v.v0, v.a0) : v.v0;
+        dphi[soff0] = u0;
+        if (C == kLocal) dpsi[soff0] = psi2(u0, k.eps);
         if (has1) {
-            dphi[soff1] = v.v1;
-            if (C == kLocal) dpsi[soff1] = psi2(v.v1, k.eps);
+            const T u1 = W ? wall_map(v.v1, v.a1) : v.v1;
+            dphi[soff1] = u1;
+            if (C == kLocal) dpsi[soff1] = psi2(u1, k.eps);
         }
     };
     // The 3 x 3 neighbourhood of this thread's point, from the corner cell b:
@@ -175,10 +206,18 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     // Descriptors of the input planes, fetched strictly in order r = 0, 1, ...
     // (plane z0 - 1 + r with periodic wrap), and of the output planes, written
     // in order z0, z0 + 1, ...: running byte pointers advanced one plane per use.
+    // With a walled z axis the ghost planes 0 and nz - 1 are read from planes 1
+    // and nz - 2 (z class zc = 0 and 2; 1 elsewhere).
     int fetch_z = wrap_once(z0 - 1, nz);
     const char* fetch_ptr = reinterpret_cast<const char*>(in) + (size_t)fetch_z * plane_bytes;
-    auto next_in = [&]() {
-        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(fetch_ptr, plane_bytes);
+    auto next_in = [&](int& zc) {
+        const char* ptr = fetch_ptr;
+        zc = 1;
+        if (W && (walls & 4)) {
+            if (fetch_z == 0) { ptr += plane_bytes; zc = 0; }
+            else if (fetch_z == nz - 1) { ptr -= plane_bytes; zc = 2; }
+        }
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(ptr, plane_bytes);
         fetch_ptr += plane_bytes;
         if (++fetch_z == nz) {
             fetch_z = 0;
@@ -210,8 +249,9 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         if (!G || r + 2 <= last) load_slot(rd + 1, P3);
         if (!G || r + 3 <= last) stage_slot(wr, Q0);
         if (!G || r + 4 <= last) stage_slot(wr + 1, Q1);
-        if (!G || r + 7 <= last) fetch_at(next_in(), Q0);
-        if (!G || r + 8 <= last) fetch_at(next_in(), Q1);
+        int zc;
+        if (!G || r + 7 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, Q0); }
+        if (!G || r + 8 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, Q1); }
         if (!G || r <= nout) point(next_out(), P0, P1, P2);
         if (!G || r + 1 <= nout) point(next_out(), P1, P2, P3);
     };
@@ -226,13 +266,14 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         // All prologue loads in flight at once: planes 0..3 are staged now,
         // 4, 5 and 6, 7 are staged by the first two iterations.
         Pair v[4];
+        int zc;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (r <= last) fetch_at(next_in(), v[r]);
-        if (4 <= last) fetch_at(next_in(), qa0);
-        if (5 <= last) fetch_at(next_in(), qa1);
-        if (6 <= last) fetch_at(next_in(), qb0);
-        if (7 <= last) fetch_at(next_in(), qb1);
+            if (r <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, v[r]); }
+        if (4 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qa0); }
+        if (5 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qa1); }
+        if (6 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qb0); }
+        if (7 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qb1); }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (r <= last) stage_slot(r, v[r]);
@@ -268,38 +309,42 @@ struct Smem {
 #endif
 // Waves per SIMD the tiled kernels are compiled for: FP32 TI_n fits in 72 VGPRs
 // (7 waves; left free, the compiler takes 79 and 6 waves, which ran 1.5%
-// slower); FP64 needs about twice as many registers.
+// slower); FP64 TI_n needs more than twice as many (2 waves, no spills).  The
+// walled variants (small grids, never many waves) are compiled for fewer waves,
+// which keeps them free of spills.
 template <typename T>
 struct WavesPerSimd {
-    static constexpr int value = sizeof(T) == 4 ? SPFM_WAVES_F32 : 4;
+    static constexpr int value = sizeof(T) == 4 ? SPFM_WAVES_F32 : 2;
+    static constexpr int walled = sizeof(T) == 4 ? 4 : 2;
 };
 
 // One block per work item of a tile schedule (see the host-side schedule
 // builder): the item gives the tile column origin and its z-chunk; items with
-// zlen = 0 pad the table and exit at once.
-template <typename T, int S, int C>
-__global__ __launch_bounds__((Smem<T, C>::NT), WavesPerSimd<T>::value) void k_step_tiled(
-    const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items) {
+// zlen = 0 pad the table and exit at once.  W: walled grid, coefficients at w.
+template <typename T, int S, int C, bool W>
+__global__ __launch_bounds__((Smem<T, C>::NT), (W ? WavesPerSimd<T>::walled : WavesPerSimd<T>::value)) void k_step_tiled(
+    const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items,
+    const WallCoef<T>* __restrict__ w) {
     __shared__ T sphi[4 * Smem<T, C>::HP];
     __shared__ T spsi[C == kLocal ? 4 * Smem<T, C>::HP : 1];
     const TileItem it = items[blockIdx.x];
     if (it.zlen <= 0) return;
-    tile_sweep<T, S, C>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi);
+    tile_sweep<T, S, C, W>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi, w);
 }
 
-template <int S, int C>
-__global__ __launch_bounds__((Smem<float, C>::NT), WavesPerSimd<float>::value) void k_step_batched(
+template <int S, int C, bool W>
+__global__ __launch_bounds__((Smem<float, C>::NT), (W ? WavesPerSimd<float>::walled : WavesPerSimd<float>::value)) void k_step_batched(
     const float* __restrict__ buf_in, float* __restrict__ buf_out,
     const StepCoef<float>* __restrict__ coef, const int64_t* __restrict__ offset,
-    const TileItem* __restrict__ items) {
+    const TileItem* __restrict__ items, const WallCoef<float>* __restrict__ wall) {
     __shared__ float sphi[4 * Smem<float, C>::HP];
     __shared__ float spsi[C == kLocal ? 4 * Smem<float, C>::HP : 1];
     const TileItem it = items[blockIdx.x];
     if (it.zlen <= 0) return;   // padding of the schedule
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
-    tile_sweep<float, S, C>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, it.zlen, sphi,
-                            spsi);
+    tile_sweep<float, S, C, W>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, it.zlen, sphi,
+                               spsi, W ? wall + it.inst : nullptr);
 }
 
 template <typename T, template <typename, int, int> class Launch, typename... Args>
@@ -330,10 +375,14 @@ struct PlainLaunch {
 template <typename T, int S, int C>
 struct TiledLaunch {
     static hipError_t run(const T* in, T* out, const StepCoef<T>& k, const TileItem* items,
-                          int nitems, hipStream_t s) {
+                          int nitems, const WallCoef<T>* wall, hipStream_t s) {
         if (nitems <= 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_tiled<T, S, C>), dim3((unsigned)nitems), dim3(Smem<T, C>::NT), 0, s,
-                           in, out, k, items);
+        if (wall)
+            hipLaunchKernelGGL((k_step_tiled<T, S, C, true>), dim3((unsigned)nitems),
+                               dim3(Smem<T, C>::NT), 0, s, in, out, k, items, wall);
+        else
+            hipLaunchKernelGGL((k_step_tiled<T, S, C, false>), dim3((unsigned)nitems),
+                               dim3(Smem<T, C>::NT), 0, s, in, out, k, items, wall);
         return hipGetLastError();
     }
 };
@@ -341,10 +390,15 @@ struct TiledLaunch {
 template <typename T, int S, int C>
 struct BatchedLaunch {
     static hipError_t run(const float* in, float* out, const StepCoef<float>* coef,
-                          const int64_t* offset, const TileItem* items, int nitems, hipStream_t s) {
+                          const int64_t* offset, const TileItem* items, int nitems,
+                          const WallCoef<float>* wall, hipStream_t s) {
         if (nitems <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_step_batched<S, C>), dim3(nitems), dim3(Smem<float, C>::NT), 0, s, in,
-                           out, coef, offset, items);
+        if (wall)
+            hipLaunchKernelGGL((k_step_batched<S, C, true>), dim3(nitems), dim3(Smem<float, C>::NT),
+                               0, s, in, out, coef, offset, items, wall);
+        else
+            hipLaunchKernelGGL((k_step_batched<S, C, false>), dim3(nitems), dim3(Smem<float, C>::NT),
+                               0, s, in, out, coef, offset, items, wall);
         return hipGetLastError();
     }
 };
@@ -359,15 +413,17 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             const TileItem* d_items, int nitems, hipStream_t s) {
-    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, d_items, nitems, s);
+                             const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
+                             hipStream_t s) {
+    return dispatch<T, TiledLaunch>(stencil, coupling, in, out, k, d_items, nitems, d_wall, s);
 }
 
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
-                               int stencil, int coupling, hipStream_t s) {
+                               const WallCoef<float>* d_wall, int stencil, int coupling,
+                               hipStream_t s) {
     return dispatch<float, BatchedLaunch>(stencil, coupling, buf_in, buf_out, d_coef, d_offset,
-                                          d_items, nitems, s);
+                                          d_items, nitems, d_wall, s);
 }
 
 template hipError_t launch_step_plain<float>(const float*, float*, const StepCoef<float>&, int, int,
@@ -375,8 +431,10 @@ template hipError_t launch_step_plain<float>(const float*, float*, const StepCoe
 template hipError_t launch_step_plain<double>(const double*, double*, const StepCoef<double>&, int,
                                               int, hipStream_t);
 template hipError_t launch_step_tiled<float>(const float*, float*, const StepCoef<float>&, int, int,
-                                             const TileItem*, int, hipStream_t);
+                                             const TileItem*, int, const WallCoef<float>*,
+                                             hipStream_t);
 template hipError_t launch_step_tiled<double>(const double*, double*, const StepCoef<double>&, int,
-                                              int, const TileItem*, int, hipStream_t);
+                                              int, const TileItem*, int, const WallCoef<double>*,
+                                              hipStream_t);
 
 }  // namespace spfm

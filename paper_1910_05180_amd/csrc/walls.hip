@@ -1,4 +1,6 @@
 // Contact-angle walls (Sec. 2.4, Eq. 7) and the interior <-> padded copies.
+// (The tiled step kernels compute the ghosts they need as they stage them; the
+// fill below serves the plain kernel.)
 //
 // A walled axis keeps one ghost layer at each end of the stored field.  Before
 // every step the ghosts are set from the nearest interior point by the tanh
@@ -52,25 +54,12 @@ __device__ __forceinline__ void fill_ghost(T* __restrict__ phi, const WallCoef<T
     const int cz = (gz && Z == 0) ? -1 : ((gz && Z == SZ - 1) ? 1 : 0);
     const int64_t src = ((int64_t)(Z - cz) * SY + (Y - cy)) * SX + (X - cx);
     const int64_t dst = ((int64_t)Z * SY + Y) * SX + X;
-    const T a = w.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)];
-    const T v = phi[src];
-    phi[dst] = (T(1) - a) * v / (T(1) - a * (T(2) * v - T(1)));
+    phi[dst] = wall_map(phi[src], w.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill_walls(T* __restrict__ phi, WallCoef<T> w) {
     fill_ghost(phi, w, (int64_t)blockIdx.x * 256 + threadIdx.x);
-}
-
-// The ghosts of every grid of a batch: blockIdx.y selects the grid (its field
-// at buf + offset[g], its coefficients w[g]); blocks past its ghost count exit.
-template <typename T>
-__global__ __launch_bounds__(256) void k_fill_walls_batched(T* __restrict__ buf,
-                                                            const WallCoef<T>* __restrict__ w,
-                                                            const int64_t* __restrict__ offset) {
-    const int g = blockIdx.y;
-    const WallCoef<T> wc = w[g];
-    fill_ghost(buf + offset[g], wc, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // dst box origin (dx0, dy0, dz0) in a dst field of dims (dnx, dny), src likewise;
@@ -121,15 +110,6 @@ template <typename T>
 hipError_t launch_fill_walls(T* phi, const WallCoef<T>& w, int64_t nghost, hipStream_t s) {
     if (nghost <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_fill_walls<T>), dim3(blocks_for(nghost)), dim3(256), 0, s, phi, w);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_walls_batched(float* buf, const WallCoef<float>* d_w, const int64_t* d_offset,
-                                     int n, int64_t max_ghost, hipStream_t s) {
-    if (n <= 0 || max_ghost <= 0) return hipSuccess;
-    if (n > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_fill_walls_batched<float>), dim3(blocks_for(max_ghost), (unsigned)n), dim3(256),
-                       0, s, buf, d_w, d_offset);
     return hipGetLastError();
 }
 

@@ -249,3 +249,35 @@ def test_walled_batch_of_uneven_grids_matches_the_oracle(S, walls):
         p.dt = dt
         ref = oracle.step_walls(p, fields[i], walls, sas[i], steps)
         assert float(np.abs(got[i] - ref).max()) <= 1e-5, i
+
+
+@pytest.mark.parametrize("coupling", ["local", "cf"])
+def test_walled_batch_results_do_not_depend_on_the_zchunk(S, coupling):
+    """The kernel computes the wall ghosts as it stages each plane, whatever
+    z-chunk a block starts at: a small walled batch (chunks of 4 planes by the
+    size rule) and the same batch with 32-plane and 7-plane chunks give bitwise
+    the same fields."""
+    shapes = [(9, 11, 37), (5, 6, 20), (12, 3, 70)]
+    lam, mu = 2.5, 0.02
+    rng = np.random.default_rng(11)
+    sas, fields = [], []
+    for shape in shapes:
+        n = rng.normal(size=3)
+        n[0] = abs(n[0]) + 0.5
+        n = n / np.linalg.norm(n)
+        sas.append(oracle.front_sin_alpha(n))
+        fields.append(as_f32_input(oracle.front(shape, n, 0.7, lam=lam)))
+    p = oracle.params(shapes[0], lam=lam, mu=mu, stencil=26, coupling=coupling, eps=1e-30)
+    dt = stable_dt(p)
+    out = {}
+    for zc in (0, 32, 7):
+        print(f"case walled batch {coupling} zchunk={zc}", flush=True)
+        with S.SpfmBatch(shapes, lam=lam, mu=mu, stencil=26, coupling=coupling, dt=dt, walls=7,
+                         wall_sin=sas, zchunk=zc) as b:
+            for i, f in enumerate(fields):
+                b.set_field(i, f)
+            b.step(40)
+            out[zc] = [b.get_field(i) for i in range(len(shapes))]
+    for zc in (32, 7):
+        for i in range(len(shapes)):
+            assert np.array_equal(out[zc][i], out[0][i]), (zc, i)
