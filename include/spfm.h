@@ -238,8 +238,10 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * launch per step covers every tile of every grid, and spfm_batch_step
  * captures the launches of n steps in one HIP graph.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
- * eps, tau, allow_unstable, walls, zchunk) apply to every grid (zchunk 0: 32
- * planes, halved down to 4 while the batch gives fewer than 2^19 threads); each grid gets its own
+ * eps, tau, allow_unstable, walls, zchunk) apply to every grid.  zchunk 0
+ * with kernel TILED: 32 planes, halved down to 4 while the batch gives fewer
+ * than 2^19 threads; with kernel AUTO the first spfm_batch_step also times
+ * chunks of 4, 8, 16, 32 and 64 planes and keeps the fastest.  Each grid gets its own
  * lambda, Gamma, M, mu and, with walls, its own wall angles from
  * batch_wall_sin (the orientation sweeps of Sec. 3.2 in one launch; the
  * kernel computes the ghost values of Eq. 7 as it reads them); d_phi must be
@@ -263,6 +265,8 @@ spfm_status spfm_batch_step(spfm_batch *b, int64_t n);
 spfm_status spfm_batch_diagnostics(spfm_batch *b, spfm_diag *out /* n entries */);
 /* Total points over all grids. */
 int64_t spfm_batch_points(const spfm_batch *b);
+/* Leading z-chunk of the batch's work items (after tuning, if any); 0 for NULL. */
+int32_t spfm_batch_zchunk(const spfm_batch *b);
 
 /* Host-only helpers (no HIP call): the calibration C_Gamma(lambda/dx) used
  * when C_Gamma <= 0, and the explicit stability bound for a parameter set

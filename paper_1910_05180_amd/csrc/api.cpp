@@ -41,6 +41,11 @@ spfm_status fail(spfm_status s, const char* fmt, ...) {
 
 constexpr int kGraphSteps = 16;
 
+// Dimensions of a stored grid, as the tile schedules see it.
+struct GridDims {
+    int nx, ny, nz;
+};
+
 struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
@@ -360,6 +365,8 @@ struct spfm_ctx {
     TileItem* d_items = nullptr;
     int nitems = 0;
     size_t items_cap = 0;
+    // One grid: tile rows are dealt to the XCDs round robin.
+    static constexpr bool kSpreadRows = true;
 
     // Steps per launch of launch_unit.
     int unit() const { return r.tsteps; }
@@ -434,8 +441,18 @@ struct spfm_batch {
     int64_t nsteps = 0;
     StepCoef<float>* d_coef = nullptr;
     int64_t* d_offset = nullptr;
+    // Work items of the batched kernel: tile_schedule of the stored grids for
+    // leading z-chunks of zlen planes, with tile width tx; with SPFM_KERNEL_AUTO
+    // and no zchunk the length is timed at the first step.
     TileItem* d_items = nullptr;
     int nitems = 0;
+    size_t items_cap = 0;
+    std::vector<GridDims> dims;
+    int tx = 16, zlen = kTileZ;
+    bool auto_zlen = false, tuned = false;
+    // Many grids, often larger than the last-level cache together: tile rows
+    // are dealt to the XCDs in contiguous groups.
+    static constexpr bool kSpreadRows = false;
     int stencil = 26, coupling = 0;
     // Walls (the same axes on every grid): per-grid coefficients on the device,
     // read by the batched kernel, which computes the ghosts it needs itself.
@@ -505,11 +522,6 @@ int tail_planes(int nz, int64_t total_points) {
     const double f = std::min(0.35, 1.4 * resident / (double)std::max<int64_t>(total_points, 1));
     return std::min(nz, (int)std::lround(f * nz));
 }
-
-// Tile grids of a schedule (stored dimensions).
-struct GridDims {
-    int nx, ny, nz;
-};
 
 // Planes per block: the longest z-chunk (kTileZ, halved down to zmin) that
 // still gives at least min_threads threads for tiles tx x ty over all grids,
@@ -599,59 +611,72 @@ std::vector<TileItem> tile_schedule(const std::vector<GridDims>& grids, int tx, 
     return out;
 }
 
-spfm_status set_schedule(spfm_ctx* c, int zb) {
-    HIP_TRY(hipStreamSynchronize(c->stream));   // no launch may still read the old table
-    const int tx = tile_x(c->r.dtype == SPFM_F32, c->r.p.coupling);
-    const std::vector<TileItem> items =
-        tile_schedule({GridDims{c->r.sx, c->r.sy, c->r.sz}}, tx, kTileY, zb, true);
+// Builds and uploads the work items of a context or batch for leading
+// z-chunks of zb planes (after the stream has drained: no launch may still read
+// the old table); captured graphs hold the old table and are dropped.
+template <typename Obj>
+spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tx, int zb) {
+    HIP_TRY(hipStreamSynchronize(o->stream));
+    const std::vector<TileItem> items = tile_schedule(dims, tx, kTileY, zb, Obj::kSpreadRows);
     if (items.size() > 0x7fffffff) return fail(SPFM_E_INVAL, "too many tiles");
-    if (items.size() > c->items_cap) {
-        if (c->d_items) (void)hipFree(c->d_items);
-        c->d_items = nullptr;
-        c->items_cap = 0;
-        if (hipMalloc(&c->d_items, items.size() * sizeof(TileItem)) != hipSuccess) {
+    if (items.size() > o->items_cap) {
+        if (o->d_items) (void)hipFree(o->d_items);
+        o->d_items = nullptr;
+        o->items_cap = 0;
+        if (hipMalloc(&o->d_items, items.size() * sizeof(TileItem)) != hipSuccess) {
             (void)hipGetLastError();
-            c->d_items = nullptr;
+            o->d_items = nullptr;
             return fail(SPFM_E_NOMEM, "device allocation of the tile schedule failed");
         }
-        c->items_cap = items.size();
+        o->items_cap = items.size();
     }
-    HIP_TRY(hipMemcpyAsync(c->d_items, items.data(), items.size() * sizeof(TileItem),
-                           hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    c->nitems = (int)items.size();
-    c->zlen = zb;
-    c->graphs.clear();
+    HIP_TRY(hipMemcpyAsync(o->d_items, items.data(), items.size() * sizeof(TileItem),
+                           hipMemcpyHostToDevice, o->stream));
+    HIP_TRY(hipStreamSynchronize(o->stream));
+    o->nitems = (int)items.size();
+    o->zlen = zb;
+    o->graphs.clear();
     return SPFM_OK;
 }
+spfm_status set_schedule(spfm_ctx* c, int zb) {
+    return set_schedule(c, {GridDims{c->r.sx, c->r.sy, c->r.sz}},
+                        tile_x(c->r.dtype == SPFM_F32, c->r.p.coupling), zb);
+}
+spfm_status set_schedule(spfm_batch* b, int zb) { return set_schedule(b, b->dims, b->tx, zb); }
 
-// SPFM_KERNEL_AUTO: time the tiled kernel for several z-chunk lengths on the
-// current field (reading the current buffer and writing the other one, which
-// the next step overwrites anyway) and keep the fastest.  The result of a step
-// does not depend on the chunk length.
-spfm_status autotune(spfm_ctx* c) {
-    c->tuned = true;
-    if (c->r.kernel != SPFM_KERNEL_TILED) return SPFM_OK;
-    const int cand[4] = {8, 16, 32, 64};
+// SPFM_KERNEL_AUTO: time the step for the candidate z-chunk lengths (those up
+// to twice the deepest grid) on the current field, reading the current buffer
+// and writing the other one, which the next step overwrites anyway.  The length
+// of the size rule (the current one) is kept unless another is at least 2%
+// faster: the first steps of a process run while the clocks still ramp up, and
+// differences below that are within the noise of these short timings.  The
+// result of a step does not depend on the chunk length.
+template <typename Obj>
+spfm_status tune_zchunk(Obj* o, const int* cand, int ncand, int nz) {
+    o->tuned = true;
+    const int rule = o->zlen;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
-    float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    float best[8];
+    for (float& v : best) v = 1e30f;
+    ncand = std::min(ncand, 8);
     spfm_status st = SPFM_OK;
-    // Two sweeps over the candidates (the first also warms clocks and caches);
-    // each candidate: two untimed launches, then five timed ones.
-    for (int sweep = 0; sweep < 2 && st == SPFM_OK; ++sweep) {
-        for (int ci = 0; ci < 4; ++ci) {
+    // Three sweeps over the candidates (the first also warms clocks and caches);
+    // each candidate: two untimed launches, then five timed ones; the best of
+    // the sweeps counts.
+    for (int sweep = 0; sweep < 3 && st == SPFM_OK; ++sweep) {
+        for (int ci = 0; ci < ncand; ++ci) {
             const int z = cand[ci];
-            if (ci > 0 && z > 2 * c->r.p.nz) break;
-            st = set_schedule(c, z);   // also sets zlen, which the temporal kernel takes
+            if (ci > 0 && z > 2 * nz) break;
+            st = set_schedule(o, z);   // also sets zlen, which the temporal kernel takes
             if (st != SPFM_OK) break;
             hipError_t e = hipSuccess;
             for (int i = 0; i < 7 && e == hipSuccess; ++i) {
-                if (i == 2) e = hipEventRecord(e0, c->stream);
-                if (e == hipSuccess) e = c->launch_unit(c->cur);
+                if (i == 2) e = hipEventRecord(e0, o->stream);
+                if (e == hipSuccess) e = o->launch_unit(o->cur);
             }
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, o->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -660,12 +685,29 @@ spfm_status autotune(spfm_ctx* c) {
         }
     }
     int bi = 0;
-    for (int ci = 1; ci < 4; ++ci)
+    for (int ci = 1; ci < ncand; ++ci)
         if (best[ci] < best[bi]) bi = ci;
+    for (int ci = 0; ci < ncand; ++ci)
+        if (cand[ci] == rule && best[ci] <= 1.02f * best[bi]) bi = ci;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SPFM_OK) return st;
-    return set_schedule(c, cand[bi]);
+    return set_schedule(o, cand[bi]);
+}
+
+spfm_status autotune(spfm_ctx* c) {
+    c->tuned = true;
+    if (c->r.kernel != SPFM_KERNEL_TILED) return SPFM_OK;
+    static const int cand[4] = {8, 16, 32, 64};
+    return tune_zchunk(c, cand, 4, c->r.p.nz);
+}
+
+// Batches: small grids gain from chunks down to 4 planes.
+spfm_status autotune(spfm_batch* b) {
+    static const int cand[5] = {4, 8, 16, 32, 64};
+    int nz = 1;
+    for (const GridDims& d : b->dims) nz = std::max(nz, d.nz);
+    return tune_zchunk(b, cand, 5, nz);
 }
 
 template <typename Obj>
@@ -1080,17 +1122,15 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         dims[i] = GridDims{ri.sx, ri.sy, ri.sz};
         if (o.walls) wall[i] = wall_coef<float>(ri);
     }
-    const int btx = tile_x(true, o.coupling);
-    const int zb = o.zchunk > 0 ? o.zchunk : default_zlen(dims, btx, kTileY, true, (int64_t)1 << 19, 4);
-    const std::vector<TileItem> items = tile_schedule(dims, btx, kTileY, zb, false);
-    if (items.size() > 0x7fffffff) { spfm_batch_destroy(b); return fail(SPFM_E_INVAL, "too many tiles"); }
+    b->dims = dims;
+    b->tx = tile_x(true, o.coupling);
+    b->auto_zlen = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0;
+    const int zb = o.zchunk > 0 ? o.zchunk : default_zlen(dims, b->tx, kTileY, true, (int64_t)1 << 19, 4);
     b->total = off;
-    b->nitems = (int)items.size();
     const size_t bytes = (size_t)off * sizeof(float);
     if (hipMalloc(&b->buf[0], bytes) != hipSuccess || hipMalloc(&b->buf[1], bytes) != hipSuccess ||
         hipMalloc(&b->d_coef, sizeof(StepCoef<float>) * n) != hipSuccess ||
         hipMalloc(&b->d_offset, sizeof(int64_t) * n) != hipSuccess ||
-        hipMalloc(&b->d_items, sizeof(TileItem) * items.size()) != hipSuccess ||
         (o.walls && hipMalloc(&b->d_wall, sizeof(WallCoef<float>) * n) != hipSuccess)) {
         (void)hipGetLastError();
         spfm_batch_destroy(b);
@@ -1100,13 +1140,14 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (st != SPFM_OK) { spfm_batch_destroy(b); return st; }
     if (hipMemcpy(b->d_coef, coef.data(), sizeof(StepCoef<float>) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_offset, b->offset.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_items, items.data(), sizeof(TileItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (o.walls && hipMemcpy(b->d_wall, wall.data(), sizeof(WallCoef<float>) * n,
                               hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemset(b->buf[0], 0, bytes) != hipSuccess || hipMemset(b->buf[1], 0, bytes) != hipSuccess) {
         spfm_batch_destroy(b);
         return fail(SPFM_E_HIP, "batch upload failed");
     }
+    st = set_schedule(b, zb);
+    if (st != SPFM_OK) { spfm_batch_destroy(b); return st; }
     *out = b;
     return SPFM_OK;
 }
@@ -1178,6 +1219,10 @@ spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on
 
 spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
     if (!b) return fail(SPFM_E_INVAL, "batch is NULL");
+    if (n > 0 && b->auto_zlen && !b->tuned) {
+        spfm_status st = autotune(b);
+        if (st != SPFM_OK) return st;
+    }
     return run_steps(b, n);
 }
 
@@ -1198,6 +1243,8 @@ spfm_status spfm_batch_diagnostics(spfm_batch* b, spfm_diag* out) {
 }
 
 int64_t spfm_batch_points(const spfm_batch* b) { return b ? b->points : 0; }
+
+int32_t spfm_batch_zchunk(const spfm_batch* b) { return b ? b->zlen : 0; }
 
 double spfm_calibrate_cgamma(double lambda_over_dx, int coupling) {
     return calibrate_cgamma(lambda_over_dx, coupling);

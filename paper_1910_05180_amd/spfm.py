@@ -121,6 +121,7 @@ def load():
         "spfm_batch_step": ([vp, i64], ctypes.c_int),
         "spfm_batch_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
         "spfm_batch_points": ([vp], i64),
+        "spfm_batch_zchunk": ([vp], i32),
         "spfm_calibrate_cgamma": ([d, ctypes.c_int], d),
         "spfm_stable_dt": ([ctypes.c_int, ctypes.c_int, dp, dp, d, d, d, d, d, d], d),
         "spfm_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -373,6 +374,11 @@ class SpfmBatch:
     @property
     def points(self) -> int:
         return int(load().spfm_batch_points(self._h))
+
+    @property
+    def zchunk(self) -> int:
+        """Leading z-chunk of the work items (chosen at the first step with kernel="auto")."""
+        return int(load().spfm_batch_zchunk(self._h))
 
     def init_planar(self, hkls, offsets):
         h = np.ascontiguousarray(np.asarray(hkls, dtype=np.int32).reshape(-1, 3))

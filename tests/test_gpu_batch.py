@@ -97,3 +97,31 @@ def test_full_batch_prefix_matches_single_grids(S):
             single = s.get_field()
         assert np.array_equal(b.get_field(i), single), i
     b.close()
+
+
+def test_batch_zchunk_choice_does_not_change_results(S):
+    """kernel="auto" times z-chunks of 4..64 planes at the first step and keeps
+    the fastest; an explicit zchunk is kept as given; kernel="tiled" takes the
+    size rule (this small batch gives too few threads for 32-plane chunks).  The
+    fields after the same steps are bitwise equal whatever was chosen."""
+    cases = small_batch()
+    shapes = [c["shape"] for c in cases]
+    lam = [c["lam"] for c in cases]
+    mu = [c["mu"] for c in cases]
+    fields = [oracle.init_planar(c["shape"], c["hkl"], c["off"], lam=c["lam"]) for c in cases]
+    out, chosen = {}, {}
+    for name, opts in [("auto", dict(kernel="auto")), ("tiled", dict(kernel="tiled")),
+                       ("auto_z7", dict(kernel="auto", zchunk=7)), ("z32", dict(kernel="tiled", zchunk=32))]:
+        print(f"case batch {name}", flush=True)
+        with S.SpfmBatch(shapes, lam=lam, mu=mu, stencil=26, coupling="local", **opts) as b:
+            for i, f in enumerate(fields):
+                b.set_field(i, f)
+            b.step(30)
+            chosen[name] = b.zchunk
+            out[name] = [b.get_field(i) for i in range(len(cases))]
+    assert chosen["auto"] in (4, 8, 16, 32, 64)
+    assert chosen["auto_z7"] == 7 and chosen["z32"] == 32
+    assert chosen["tiled"] == 4   # 278824 points: 32 planes would give 2^16 threads
+    for name in ("tiled", "auto_z7", "z32"):
+        for i in range(len(cases)):
+            assert np.array_equal(out[name][i], out["auto"][i]), (name, i)
