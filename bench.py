@@ -132,19 +132,20 @@ def batch_leg(spfm, torch, inputs, steps, warmup):
             / HBM_PEAK_GBS}
 
 
-def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0):
-    """FP32 TI_n 26-neighbour step on the 512^3 box with 300 grains (1 GiB
-    ping-pong); with tsteps > 1 the temporally blocked kernel fuses that many
-    steps per pass over the field (z-chunk 32)."""
+def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0, coupling="local"):
+    """FP32 26-neighbour step (TI_n unless coupling says otherwise) on the 512^3
+    box with 300 grains (1 GiB ping-pong, far beyond the last-level cache); with
+    tsteps > 1 the temporally blocked kernel fuses that many steps per pass over
+    the field (z-chunk 32)."""
     w = inputs.grains512()
     zc = 32 if tsteps > 1 else ZCHUNK
     steps -= steps % max(tsteps, 1)
     wall, ev_ms, _ = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled", steps=steps,
-                               warmup=warmup, zchunk=zc, tsteps=tsteps)
+                               warmup=warmup, zchunk=zc, tsteps=tsteps, coupling=coupling)
     n = w.shape[0] * w.shape[1] * w.shape[2]
     bytes_per_point = ALG_BYTES_F32 / max(tsteps, 1)
     return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "points": n, "grains": len(w.radii),
-            "steps": steps, "tsteps": max(tsteps, 1), "zchunk": zc,
+            "coupling": coupling, "steps": steps, "tsteps": max(tsteps, 1), "zchunk": zc,
             "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
             "pct_hbm_peak": 100.0 * bytes_per_point * n / (ev_ms / steps * 1e-3) / 1e9
             / HBM_PEAK_GBS}
@@ -384,6 +385,10 @@ def main():
         out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
     if args.only in ("", "temporal"):
         out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
+        # CF: the HBM-bound step, where fusing steps pays
+        out["grains512_cf"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, coupling="cf")
+        out["grains512_cf_temporal3"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=3,
+                                                   coupling="cf")
     if args.only in ("", "walls"):
         out["orientation120_walls"] = walls_leg(spfm, torch)
     if args.only in ("", "models"):

@@ -103,8 +103,9 @@ typedef struct {
                            steps (tsteps > 1) use zchunk planes throughout */
     int32_t tsteps;     /* temporal blocking: steps fused into one pass over the field, 0 or 1 =
                            none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
-                           equal tsteps steps of the PLAIN kernel bit for bit; spfm_step(n) runs
-                           n / tsteps fused launches and n % tsteps single steps */
+                           equal tsteps single steps of the TILED kernel bit for bit; spfm_step(n)
+                           runs n / tsteps fused launches and n % tsteps single tiled steps, so
+                           any n equals n tiled steps */
     int32_t walls;      /* bit d (d = 0, 1, 2 for x, y, z): contact-angle walls at both ends of
                            axis d instead of periodic wrap (not with tsteps > 1) */
     double wall_sin[6]; /* faces -x, +x, -y, +y, -z, +z: sin(alpha) of Eq. 7, in [-1, 1]: a ghost

@@ -330,6 +330,57 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
     return p + upd;
 }
 
+// Per-column values a thread of a z-marching sweep keeps for one plane: the
+// plane's contribution to the shell sums of the column's points, read once
+// from the staged plane and used by the three points z-1, z, z+1.
+template <typename T>
+struct PlaneRegs {
+    T c;        // phi at the column
+    T fc;       // sum of phi over the 4 in-plane face neighbours
+    T dc;       // sum of phi over the 4 in-plane diagonal neighbours
+    T gx, gy;   // LOCAL: in-plane central differences of psi' at the column
+    T pc;       // LOCAL: psi' at the column
+};
+
+// PlaneRegs of one column from a staged plane (phi at P, psi' at Q, row stride
+// LX), both pointing at the corner cell of the column's 3 x 3 neighbourhood:
+// every offset lies within 2 LX + 2 elements of it, so one base address serves
+// all the paired LDS reads.
+template <typename T, int S, int C, int LX>
+__device__ __forceinline__ void plane_sums(const T* P, const T* Q, PlaneRegs<T>& R) {
+    R.c = P[LX + 1];
+    R.fc = (P[LX + 2] + P[LX]) + (P[2 * LX + 1] + P[1]);
+    if (S >= 18) R.dc = (P[2 * LX + 2] + P[0]) + (P[2 * LX] + P[2]);
+    if (C == kLocal) {
+        R.gx = Q[LX + 2] - Q[LX];
+        R.gy = Q[2 * LX + 1] - Q[1];
+        R.pc = Q[LX + 1];
+    }
+}
+
+// New value of phi at a point from the PlaneRegs of its column on the planes
+// below (Rm), at (R0) and above (Rp) it.  The shell sums of second differences
+// come from the raw plane sums, each with its own multiple of the centre value
+// taken off (exactly 0 where phi is 0 or 1 throughout; elsewhere the rounding
+// of the sums stays well below half an ulp of the new value):
+//   s1 = F(z) + c(z-1) + c(z+1) - 6p, s2 = D(z) + F(z-1) + F(z+1) - 12p,
+//   s3 = D(z-1) + D(z+1) - 8p.
+template <typename T, int S, int C>
+__device__ __forceinline__ T point_from_planes(const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
+                                               const PlaneRegs<T>& Rp, const StepCoef<T>& k) {
+    const T p = R0.c;
+    const T s1 = fma(T(-6), p, R0.fc + (Rm.c + Rp.c));
+    T s2 = T(0), s3 = T(0);
+    if (S >= 18) s2 = fma(T(-12), p, R0.dc + (Rm.fc + Rp.fc));
+    if (S >= 26) s3 = fma(T(-8), p, Rm.dc + Rp.dc);
+    auto grad = [&](T& gx, T& gy, T& gz) {
+        gx = R0.gx;
+        gy = R0.gy;
+        gz = Rp.pc - Rm.pc;
+    };
+    return point_core<T, S, C>(p, s1, s2, s3, grad, k);
+}
+
 // New value of phi at one point.  at(dx,dy,dz) returns phi at the offset
 // (dx,dy,dz in {-1,0,1}); grad as in point_core.
 template <typename T, int S, int C, typename At, typename Grad>

@@ -44,16 +44,6 @@ __global__ __launch_bounds__(256) void k_step_plain(const T* __restrict__ in, T*
     out[((size_t)z * ny + y) * nx + x] = point_update<T, S, C>(at, grad, k);
 }
 
-// Per-column values a thread keeps for one plane q of its z-march.
-template <typename T>
-struct PlaneRegs {
-    T c;        // phi at the column
-    T fc;       // sum of phi over the 4 in-plane face neighbours
-    T dc;       // sum of phi over the 4 in-plane diagonal neighbours
-    T gx, gy;   // LOCAL: in-plane central differences of psi' at the column
-    T pc;       // LOCAL: psi' at the column
-};
-
 // One block sweeps the tile [x0, x0+TX) x [y0, y0+TY) x [z0, z0+zlen)
 // (clipped to the grid).  Each plane of the tile plus a one-cell halo is read
 // from global memory once (coalesced rows) two iterations before it is staged
@@ -163,44 +153,16 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             if (C == kLocal) dpsi[soff1] = psi2(u1, k.eps);
         }
     };
-    // The 3 x 3 neighbourhood of this thread's point, from the corner cell b:
-    // every offset lies within 2 LX + 2 < 256 elements of b, so a slot needs one
-    // base address for all its paired LDS reads.
+    // The 3 x 3 neighbourhood of this thread's point, from the corner cell b.
     const int b = ty * LX + tx;
     auto load_slot = [&](int slot, PlaneRegs<T>& R) {
-        const T* P = sphi + slot * HP + b;
-        const T c = P[LX + 1];
-        R.c = c;
-        R.fc = (P[LX + 2] + P[LX]) + (P[2 * LX + 1] + P[1]);
-        if (S >= 18) R.dc = (P[2 * LX + 2] + P[0]) + (P[2 * LX] + P[2]);
-        if (C == kLocal) {
-            const T* Q = spsi + slot * HP + b;
-            R.gx = Q[LX + 2] - Q[LX];
-            R.gy = Q[2 * LX + 1] - Q[1];
-            R.pc = Q[LX + 1];
-        }
+        plane_sums<T, S, C, LX>(sphi + slot * HP + b, spsi + slot * HP + b, R);
     };
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const int dst_off = ((y0 + ty) * nx + (x0 + tx)) * (int)sizeof(T);
     auto point = [&](__amdgpu_buffer_rsrc_t dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
                      const PlaneRegs<T>& Rp) {
-        // Shell sums of second differences from the raw plane sums, each with its
-        // own multiple of the centre value taken off (exactly 0 where phi is 0 or
-        // 1 throughout; elsewhere the rounding of the sums stays well below half
-        // an ulp of the new value):
-        //   s1 = F(z) + c(z-1) + c(z+1) - 6p, s2 = D(z) + F(z-1) + F(z+1) - 12p,
-        //   s3 = D(z-1) + D(z+1) - 8p.
-        const T p = R0.c;
-        const T s1 = fma(T(-6), p, R0.fc + (Rm.c + Rp.c));
-        T s2 = T(0), s3 = T(0);
-        if (S >= 18) s2 = fma(T(-12), p, R0.dc + (Rm.fc + Rp.fc));
-        if (S >= 26) s3 = fma(T(-8), p, Rm.dc + Rp.dc);
-        auto grad = [&](T& gx, T& gy, T& gz) {
-            gx = R0.gx;
-            gy = R0.gy;
-            gz = Rp.pc - Rm.pc;
-        };
-        const T v = point_core<T, S, C>(p, s1, s2, s3, grad, k);
+        const T v = point_from_planes<T, S, C>(Rm, R0, Rp, k);
         if (active) buf_store<(C == kLocal && sizeof(T) == 4) ? kStoreThrough : 0>(v, dst, dst_off);
     };
     // Descriptors of the input planes, fetched strictly in order r = 0, 1, ...
