@@ -523,11 +523,15 @@ int tail_planes(int nz, int64_t total_points) {
     return std::min(nz, (int)std::lround(f * nz));
 }
 
-// Planes per block: the longest z-chunk (kTileZ, halved down to zmin) that
-// still gives at least min_threads threads for tiles tx x ty over all grids,
-// counting the guided chunks of the single-step schedule (guided) or uniform
-// chunks (the temporal kernel).  Grids too small to fill the GPU get shorter
-// chunks: more blocks, each with a shorter dependent chain of plane loads.
+// Planes per block: the longest z-chunk (kTileZ for single steps, 2 kTileZ for
+// fused ones, halved down to zmin) that still gives at least min_threads
+// threads for tiles tx x ty over all grids, counting the guided chunks of the
+// single-step schedule (guided) or uniform chunks (the temporal kernel).  A
+// fused chunk also computes 2 T - 2 extra planes of its intermediate levels
+// and reads 2 T extra input planes, which longer chunks amortise (CF, 3 fused
+// steps on the 512^3 grains: 752 GLUPS with 64 planes, 710 with 32).  Grids too
+// small to fill the GPU get shorter chunks: more blocks, each with a shorter
+// dependent chain of plane loads.
 int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided,
                  int64_t min_threads, int zmin) {
     int64_t total = 0;
@@ -542,7 +546,7 @@ int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided
         }
         return t;
     };
-    int z = kTileZ;
+    int z = guided ? kTileZ : 2 * kTileZ;
     while (z > zmin && threads(z) < min_threads) z /= 2;
     return z;
 }

@@ -112,7 +112,7 @@ def test_fused_grains512_bitwise_in_bench_configuration(S):
     st = torch.cuda.Stream()
     for coupling in ("local", "cf"):
         fields = []
-        for kw in (dict(kernel="tiled", zchunk=32), dict(kernel="tiled", tsteps=2, zchunk=32)):
+        for kw in (dict(kernel="tiled", zchunk=32), dict(kernel="tiled", tsteps=2, zchunk=64)):
             print(f"case grains512 {coupling} {kw}", flush=True)
             with torch.cuda.stream(st):
                 with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, coupling=coupling, stream=st,
