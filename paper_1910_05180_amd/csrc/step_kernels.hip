@@ -1,13 +1,16 @@
-// Step kernels of the SPFM GPU library (forward Euler of Eq. 2, periodic grid).
+// Step kernels of the SPFM GPU library (forward Euler of Eq. 2; periodic grid,
+// or contact-angle walls on chosen axes).
 //
 //  k_step_plain  one thread per point; the 27-point neighbourhood is read
 //                straight from global memory with periodic index wrap.
-//  k_step_tiled  a 512-thread block owns a 64 x 8 column of the grid and
-//                marches it along z over zlen planes (see tile_sweep): every
-//                plane is read from HBM once with coalesced rows, one plane ahead
-//                of its use, staged with its halo in LDS, and reduced by each
-//                thread to a few per-plane partial sums kept in registers.  For
-//                TI_n the log-ratio psi' of every staged cell is computed once.
+//  k_step_tiled  a block owns a tile column of the grid (16 x 8 with 128 threads
+//                for FP32 TI_n, 64 x 8 with 512 threads otherwise) and marches it
+//                along z over the work items of a schedule (see tile_sweep):
+//                every plane is read from HBM once with coalesced rows, ahead of
+//                its use, staged with its halo in LDS, and reduced by each thread
+//                to a few per-plane partial sums kept in registers.  For TI_n the
+//                log-ratio psi' of every staged cell is computed once.  On walled
+//                grids the ghost values are computed as planes are staged.
 //  k_step_batched the tiled sweep over a flat list of (grid, tile) items that
 //                covers many independent grids in one launch.
 #include <type_traits>
