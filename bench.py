@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | walls | models | "
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | models | "
                          "cube | friction")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
@@ -149,6 +149,64 @@ def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0, coupling="local"):
             "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
             "pct_hbm_peak": 100.0 * bytes_per_point * n / (ev_ms / steps * 1e-3) / 1e9
             / HBM_PEAK_GBS}
+
+
+def mu_sweep_leg(spfm, torch, inputs, warm=20, steps=120, f64_every=3):
+    """The 128^3 (1,2,3) slab at lambda = 5 dx under 16 driving forces evenly
+    spaced in [-0.1, 0.1] (TI_n, 26 neighbours, dt = 0.1): all 16 as one FP32
+    batch (one launch per step), then every f64_every-th driving force alone
+    on the FP64 tiled path.  Reports the FP32 and FP64 step rates, the
+    velocity against v = -M mu / Gamma (Sec. 2.1: frictionless, no pinning
+    threshold), the fitted slope and intercept of v(mu), and the FP32-FP64
+    velocity difference.  The slab is 17.1 cells thick, so at |mu| = 0.1 its
+    two fronts meet after about 855 steps and feel each other's tails well
+    before: velocities and rates are taken over 120 steps (at most 1.2 cells
+    of travel per front)."""
+    import numpy as np
+    sweep = inputs.planar128_mu_sweep()
+    n = sweep[0].shape[0] * sweep[0].shape[1] * sweep[0].shape[2]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = spfm.SpfmBatch([w.shape for w in sweep], lam=[w.lam for w in sweep],
+                           mu=[w.mu for w in sweep], stencil=26, coupling="local", dt=sweep[0].dt,
+                           stream=stream)
+        b.init_planar([w.hkl for w in sweep], [w.offset for w in sweep])
+        b.step(warm)
+        b.diagnostics()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        d32 = b.diagnostics()
+        ms32 = e0.elapsed_time(e1)
+        b.close()
+    v32 = np.array([d["velocity"] for d in d32])
+    mu = np.array([w.mu for w in sweep])
+    slope, icpt = np.polyfit(mu, v32, 1)
+    v64, ms64 = {}, 0.0
+    for i in range(0, len(sweep), f64_every):
+        w = sweep[i]
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, coupling="local", dtype="f64",
+                          kernel="tiled", dt=w.dt, stream=stream)
+            s.init_planar(w.hkl, w.offset)
+            s.step(warm)
+            s.diagnostics()
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            v64[i] = s.diagnostics()["velocity"]
+            ms64 += e0.elapsed_time(e1)
+            s.close()
+    rel64 = max(abs(v32[i] - v) / abs(v) for i, v in v64.items())
+    return {"value": n * len(sweep) * steps / (ms32 * 1e-3) / 1e9, "unit": "GLUPS",
+            "grid": "128^3, (1,2,3) slab, lambda = 5", "driving_forces": len(sweep),
+            "grids_per_launch": len(sweep), "steps": steps, "ms_per_step": ms32 / steps,
+            "fp64_tiled_glups": n * len(v64) * steps / (ms64 * 1e-3) / 1e9,
+            "max_rel_velocity_error": float(np.max(np.abs(v32 / (-mu) - 1.0))),
+            "fit_slope": float(slope), "fit_intercept": float(icpt),
+            "max_rel_fp32_fp64_velocity": float(rel64)}
 
 
 def walls_leg(spfm, torch, warm=400, steps=1600):
@@ -389,6 +447,8 @@ def main():
         out["grains512_cf"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, coupling="cf")
         out["grains512_cf_temporal3"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=3,
                                                    coupling="cf")
+    if args.only in ("", "musweep"):
+        out["mu_sweep128"] = mu_sweep_leg(spfm, torch, inputs)
     if args.only in ("", "walls"):
         out["orientation120_walls"] = walls_leg(spfm, torch)
     if args.only in ("", "models"):
