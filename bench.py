@@ -75,10 +75,28 @@ def copy_reference(torch):
     return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
+def grain_shape(d, lam):
+    """Size and isotropy of the shrinking grain after the timed steps: the
+    volume-equivalent radius R_V of the ideal profile's phase volume (the
+    sphere of radius R holds (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) of phi),
+    and the phi = 1/2 contour statistics of Sec. 3.4 (mean, extreme radii and
+    eps_eff = (R_max - R_min) / (2 R_mean))."""
+    import math
+    c = d["contour"]
+    v = d["phase_volume"]
+    k = math.pi ** 2 * lam ** 2 / 16.0
+    r = (3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0)
+    for _ in range(50):   # Newton on R^3 + k R = 3 V / (4 pi)
+        r -= (r ** 3 + k * r - 3.0 * v / (4.0 * math.pi)) / (3.0 * r * r + k)
+    return {"time": d["time"], "R_V": r, "R_mean": c["R_mean"], "R_min": c["R_min"],
+            "R_max": c["R_max"], "eps_eff": c["eps_eff"], "contour_points": c["points"]}
+
+
 def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0,
-              tsteps=0):
+              tsteps=0, contour=False):
     """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
-    Returns (wall seconds, event milliseconds) of the timed region."""
+    Returns (wall seconds, event milliseconds) of the timed region and the
+    diagnostics after it (with contour: the phi = 1/2 contour statistics)."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = spfm.Spfm(shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx,
@@ -98,6 +116,8 @@ def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="
         ev_ms = e0.elapsed_time(e1)
         d = s.diagnostics()
         d["zchunk"] = s.info()["zchunk"]
+        if contour:
+            d["contour"] = s.contour_stats()
         s.close()
     return wall, ev_ms, d
 
@@ -391,7 +411,7 @@ def main():
     if args.only in ("", "f32"):
         wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
                                    steps=args.steps, warmup=args.warmup, coupling=args.coupling,
-                                   zchunk=ZCHUNK)
+                                   zchunk=ZCHUNK, contour=True)
         f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
     if args.only in ("", "f64"):
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",
@@ -427,6 +447,7 @@ def main():
             "roofline": roofline,
             "kernel_ms_per_step": kern_ms,
             "phi_range": [f32["diag"]["phi_min"], f32["diag"]["phi_max"]],
+            "grain": grain_shape(f32["diag"], w.lam),
         })
     if f64 is not None:
         s64 = args.fp64_steps
