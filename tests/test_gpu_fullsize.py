@@ -87,3 +87,41 @@ def test_grain256_fp64_plain_one_step_everywhere(S):
         s.step(1)
         got = s.get_field()
     assert np.abs(got - ref).max() <= 1e-12
+
+
+def test_grains512_reductions_full_field_and_crop(S):
+    """The FP64 compensated reductions of the diagnostics on the 512^3 grains
+    after a few steps: against a long-double sum of the whole field (its error
+    bound, about log2(N) 2^-64 of the sum, is far below the bar) and, on a
+    128^3 crop stepped as a grid of its own, against the oracle's exactly
+    rounded sums."""
+    from paper_1910_05180_amd import inputs
+    w = inputs.grains512()
+    print(f"reductions {w.shape} grains={len(w.radii)}", flush=True)
+    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f32", coupling="local",
+                kernel="tiled", zchunk=ZCHUNK, dt=w.dt) as s:
+        s.init_spheres(w.centers, w.radii)
+        s.step(4)
+        d = s.diagnostics()
+        f = s.get_field()
+    v = f.astype(np.float64)
+    ref_phi = float(np.sum(v.astype(np.longdouble)))
+    ref_x = float(np.sum((v * (1.0 - v)).astype(np.longdouble)))
+    del v
+    assert abs(d["sum_phi"] - ref_phi) <= 1e-15 * ref_phi
+    assert abs(d["sum_x"] - ref_x) <= 1e-15 * ref_x
+    assert d["phase_volume"] == pytest.approx(ref_phi, rel=1e-15)
+    assert d["interface_area"] == pytest.approx(4.0 / w.lam * ref_x, rel=1e-15)
+    # a 128^3 crop holding grains and matrix, as a periodic grid of its own
+    crop = np.ascontiguousarray(f[128:256, 192:320, 256:384])
+    del f
+    with S.Spfm(crop.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f32", coupling="local",
+                kernel="tiled", dt=w.dt) as s:
+        s.set_field(crop)
+        s.step(3)
+        dc = s.diagnostics()
+        g = s.get_field().astype(np.float64)
+    s1, s2 = oracle.exact_sums(g)
+    assert 0.0 < s1 < g.size and s2 > 0.0
+    assert abs(dc["sum_phi"] - s1) <= 1e-15 * s1
+    assert abs(dc["sum_x"] - s2) <= 1e-15 * s2
