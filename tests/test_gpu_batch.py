@@ -125,3 +125,27 @@ def test_batch_zchunk_choice_does_not_change_results(S):
     for name in ("tiled", "auto_z7", "z32"):
         for i in range(len(cases)):
             assert np.array_equal(out[name][i], out["auto"][i]), (name, i)
+
+
+def test_full_batch_instances_match_oracle(S):
+    """The 64-grid workload from the oracle's own FP32-rounded initial fields:
+    after 100 steps the 8 smallest grids (edges 48 and 64, where the FP64 oracle
+    finishes in seconds) are within 1e-5 of the oracle."""
+    from paper_1910_05180_amd import inputs
+    ws = inputs.batch64()
+    steps = 100
+    fields = [as_f32_input(oracle.init_planar(w.shape, w.hkl, w.offset, lam=w.lam)) for w in ws]
+    with S.SpfmBatch([w.shape for w in ws], lam=[w.lam for w in ws], mu=[w.mu for w in ws],
+                     stencil=26, coupling="local") as b:
+        for i, f in enumerate(fields):
+            b.set_field(i, f)
+        b.step(steps)
+        picks = sorted(range(len(ws)), key=lambda i: (np.prod(ws[i].shape), i))[:8]
+        got = {i: b.get_field(i).astype(np.float64) for i in picks}
+    for i in picks:
+        w = ws[i]
+        print(f"batch64 instance {i} shape={w.shape} hkl={w.hkl} lam={w.lam:.3f} mu={w.mu:+.4f}",
+              flush=True)
+        p = oracle.params(w.shape, lam=w.lam, mu=w.mu, stencil=26, coupling="local", eps=1e-30)
+        ref = oracle.step(p, fields[i], steps)
+        assert float(np.abs(got[i] - ref).max()) <= 1e-5, i
