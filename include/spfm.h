@@ -242,7 +242,8 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * eps, tau, allow_unstable, walls, zchunk) apply to every grid.  zchunk 0
  * with kernel TILED: 32 planes, halved down to 4 while the batch gives fewer
  * than 2^19 threads; with kernel AUTO the first spfm_batch_step also times
- * chunks of 4, 8, 16, 32 and 64 planes and keeps the fastest.  Each grid gets its own
+ * chunks of 4, 8, 16, 32 and 64 planes and keeps the fastest (that call
+ * synchronises the stream, so it must not be captured).  Each grid gets its own
  * lambda, Gamma, M, mu and, with walls, its own wall angles from
  * batch_wall_sin (the orientation sweeps of Sec. 3.2 in one launch; the
  * kernel computes the ghost values of Eq. 7 as it reads them); d_phi must be
