@@ -1,0 +1,110 @@
+"""Degenerate and extreme cases of the step API on the device: zero steps,
+one-grid batches, z-chunks of one plane and of the whole grid, and batches
+that mix the smallest grid with large ones.  The step's result never depends
+on how the work is cut, so these compare library paths bit for bit; the mixed
+batch is also held to the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import as_f32_input, noisy_field, slab111, sphere12, stable_dt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_05180_amd import spfm
+    spfm.load()
+    return spfm
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_zero_steps_change_nothing(S, dtype):
+    phi0 = slab111(3.0)
+    print(f"case zero steps {dtype}", flush=True)
+    with S.Spfm(phi0.shape, lam=3.0, mu=0.02, stencil=26, dtype=dtype, kernel="tiled") as s:
+        s.set_field(phi0)
+        before = s.get_field()
+        s.step(0)
+        d = s.diagnostics()
+        after = s.get_field()
+    assert d["step"] == 0
+    assert np.array_equal(before, after)
+
+
+@pytest.mark.parametrize("coupling", ["local", "global", "cf"])
+@pytest.mark.parametrize("zchunk", [1, 4096])
+def test_extreme_zchunks_equal_the_default(S, coupling, zchunk):
+    """One plane per block, and one block per tile column (zchunk above nz)."""
+    phi0 = sphere12(2.0)
+    p = oracle.params(phi0.shape, lam=2.0, mu=0.01, stencil=26, coupling=coupling, u=(1.0, 2.0, 0.0))
+    dt = stable_dt(p)
+    out = []
+    for zc in (0, zchunk):
+        print(f"case zchunk={zc} {coupling}", flush=True)
+        with S.Spfm(phi0.shape, lam=2.0, mu=0.01, stencil=26, dtype="f32", coupling=coupling,
+                    u=(1.0, 2.0, 0.0), dt=dt, kernel="tiled", zchunk=zc) as s:
+            s.set_field(phi0)
+            s.step(12)
+            out.append(s.get_field())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))
+
+
+def test_fp64_whole_column_blocks_equal_the_default(S):
+    phi0 = slab111(3.0)
+    out = []
+    for zc in (0, 4096):
+        with S.Spfm(phi0.shape, lam=3.0, mu=0.02, stencil=26, dtype="f64", kernel="tiled",
+                    zchunk=zc) as s:
+            s.set_field(phi0)
+            s.step(10)
+            out.append(s.get_field())
+    assert np.array_equal(out[0].view(np.uint64), out[1].view(np.uint64))
+
+
+@pytest.mark.parametrize("coupling", ["local", "cf"])
+def test_one_grid_batch_equals_the_context(S, coupling):
+    phi0 = as_f32_input(sphere12(2.0))
+    p = oracle.params(phi0.shape, lam=2.0, mu=0.01, stencil=26, coupling=coupling)
+    dt = stable_dt(p)
+    print(f"case one-grid batch {coupling}", flush=True)
+    with S.SpfmBatch([phi0.shape], lam=2.0, mu=0.01, stencil=26, coupling=coupling, dt=dt) as b:
+        b.set_field(0, phi0)
+        b.step(20)
+        got = b.get_field(0)
+    with S.Spfm(phi0.shape, lam=2.0, mu=0.01, stencil=26, dtype="f32", coupling=coupling, dt=dt,
+                kernel="tiled") as s:
+        s.set_field(phi0)
+        s.step(20)
+        ref = s.get_field()
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_batch_mixing_the_smallest_grid_with_large_ones(S):
+    """A 3^3 grid (every halo wraps onto itself) beside grids of several tiles,
+    each grid bitwise equal to its own context and within 1e-5 of the oracle."""
+    shapes = [(3, 3, 3), (40, 33, 70), (5, 70, 9), (3, 3, 3), (33, 4, 65)]
+    lam, mu = 3.0, 0.02
+    fields = [as_f32_input(noisy_field(sh, lam, 21 + i)) for i, sh in enumerate(shapes)]
+    ps = [oracle.params(sh, lam=lam, mu=mu, stencil=26, coupling="local", eps=1e-30) for sh in shapes]
+    dt = min(stable_dt(p) for p in ps)
+    steps = 4
+    print(f"case mixed batch {shapes}", flush=True)
+    with S.SpfmBatch(shapes, lam=lam, mu=mu, stencil=26, coupling="local", dt=dt) as b:
+        for i, f in enumerate(fields):
+            b.set_field(i, f)
+        b.step(steps)
+        got = [b.get_field(i) for i in range(len(shapes))]
+    for i, sh in enumerate(shapes):
+        with S.Spfm(sh, lam=lam, mu=mu, stencil=26, dtype="f32", coupling="local", dt=dt,
+                    kernel="tiled") as s:
+            s.set_field(fields[i])
+            s.step(steps)
+            single = s.get_field()
+        assert np.array_equal(got[i].view(np.uint32), single.view(np.uint32)), i
+        ps[i].dt = dt
+        ref = oracle.step(ps[i], fields[i], steps)
+        assert float(np.abs(got[i].astype(np.float64) - ref).max()) <= 1e-5, i
