@@ -95,7 +95,9 @@ typedef struct {
     int32_t kernel;     /* spfm_kernel */
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
-                           library (timed at the first step for AUTO, a size rule for TILED).
+                           library: a size rule (32 planes, 64 for fused steps, shorter for
+                           grids too small to fill the GPU); for AUTO on a grid that fills
+                           it, timed among 8..64 at the first step.
                            Single steps cut each tile column into blocks of at most zchunk
                            planes, except a tail (about 1.4 rounds of the work the GPU keeps
                            resident, at most 35% of the column) in blocks of halving length
@@ -241,9 +243,10 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
  * eps, tau, allow_unstable, walls, zchunk) apply to every grid.  zchunk 0
  * with kernel TILED: 32 planes, halved down to 4 while the batch gives fewer
- * than 2^19 threads; with kernel AUTO the first spfm_batch_step also times
- * chunks of 4, 8, 16, 32 and 64 planes and keeps the fastest (that call
- * synchronises the stream, so it must not be captured).  Each grid gets its own
+ * than 2^19 threads; with kernel AUTO and a batch that fills the GPU (32
+ * planes kept) the first spfm_batch_step also times chunks of 4, 8, 16, 32 and
+ * 64 planes and keeps the fastest (that call synchronises the stream, so it
+ * must not be captured).  Each grid gets its own
  * lambda, Gamma, M, mu and, with walls, its own wall angles from
  * batch_wall_sin (the orientation sweeps of Sec. 3.2 in one launch; the
  * kernel computes the ghost values of Eq. 7 as it reads them); d_phi must be

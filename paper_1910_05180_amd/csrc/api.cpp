@@ -653,12 +653,17 @@ spfm_status set_schedule(spfm_batch* b, int zb) { return set_schedule(b, b->dims
 // and writing the other one, which the next step overwrites anyway.  The length
 // of the size rule (the current one) is kept unless another is at least 2%
 // faster: the first steps of a process run while the clocks still ramp up, and
-// differences below that are within the noise of these short timings.  The
-// result of a step does not depend on the chunk length.
+// differences below that are within the noise of these short timings.  When
+// the size rule has already shortened the chunks below full (zlen < zfull),
+// the work cannot fill the GPU, a launch takes about as long as the host needs
+// to issue it, and timing single launches would measure the host: the rule's
+// length is kept untimed.  The result of a step does not depend on the chunk
+// length.
 template <typename Obj>
-spfm_status tune_zchunk(Obj* o, const int* cand, int ncand, int nz) {
+spfm_status tune_zchunk(Obj* o, const int* cand, int ncand, int nz, int zfull) {
     o->tuned = true;
     const int rule = o->zlen;
+    if (rule < zfull) return SPFM_OK;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
@@ -703,7 +708,7 @@ spfm_status autotune(spfm_ctx* c) {
     c->tuned = true;
     if (c->r.kernel != SPFM_KERNEL_TILED) return SPFM_OK;
     static const int cand[4] = {8, 16, 32, 64};
-    return tune_zchunk(c, cand, 4, c->r.p.nz);
+    return tune_zchunk(c, cand, 4, c->r.p.nz, c->r.tsteps > 1 ? 2 * kTileZ : kTileZ);
 }
 
 // Batches: small grids gain from chunks down to 4 planes.
@@ -711,7 +716,7 @@ spfm_status autotune(spfm_batch* b) {
     static const int cand[5] = {4, 8, 16, 32, 64};
     int nz = 1;
     for (const GridDims& d : b->dims) nz = std::max(nz, d.nz);
-    return tune_zchunk(b, cand, 5, nz);
+    return tune_zchunk(b, cand, 5, nz, kTileZ);
 }
 
 template <typename Obj>
