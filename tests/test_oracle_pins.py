@@ -478,3 +478,34 @@ def test_slab_init_periodic_and_symmetric(orc):
         same = np.abs(np.diff(sv)) < 1e-9
         assert np.all(np.abs(np.diff(pv))[same] < 1e-12)
         assert abs(phi.mean() - 0.5) < 1e-3
+
+
+def _ideal_sphere_radius(volume, lam):
+    """R of the ideal radial profile holding `volume` of phi:
+    (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) = volume, by Newton's method."""
+    k = math.pi ** 2 * lam ** 2 / 16.0
+    target = 3.0 * volume / (4.0 * math.pi)
+    r = target ** (1.0 / 3.0)
+    for _ in range(60):
+        r -= (r ** 3 + k * r - target) / (3.0 * r * r + k)
+    return r
+
+
+def test_grain_shrinks_by_the_curvature_law(orc):
+    """P10 (approximate): at mu = 0 a grain's R^2 falls linearly in time at
+    4 M sigma / Gamma with sigma = 2 Gamma / (3 C_Gamma) of the discrete model,
+    up to corrections of order lambda / R.  A TI_n grain of R = 24 at lambda = 3
+    over 200 steps (R ends near 22.3) must meet the law within lambda / R_end;
+    a dropped shell, a wrong sign or a wrong C_Gamma scaling breaks it."""
+    shape, r0, lam = (64, 64, 64), 24.0, 3.0
+    phi = orc.init_spheres(shape, [(31.7, 32.2, 31.9)], [r0], lam=lam)
+    p = orc.params(shape, lam=lam, mu=0.0, stencil=26, coupling="local")
+    ts, radii = [0.0], [_ideal_sphere_radius(orc.phase_volume(phi), lam)]
+    for i in range(2):
+        phi = orc.step(p, phi, 100)
+        ts.append((i + 1) * 100 * p.dt)
+        radii.append(_ideal_sphere_radius(orc.phase_volume(phi), lam))
+    assert abs(radii[0] - r0) < 1e-4
+    rate = np.polyfit(ts, np.square(radii), 1)[0]
+    law = -4.0 * p.M * (2.0 * p.Gamma / (3.0 * p.C_Gamma)) / p.Gamma
+    assert abs(rate / law - 1.0) < lam / radii[-1], (rate, law)
