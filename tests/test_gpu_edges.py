@@ -108,3 +108,30 @@ def test_batch_mixing_the_smallest_grid_with_large_ones(S):
         ps[i].dt = dt
         ref = oracle.step(ps[i], fields[i], steps)
         assert float(np.abs(got[i].astype(np.float64) - ref).max()) <= 1e-5, i
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-6)])
+@pytest.mark.parametrize("op", ["swap_xy", "swap_xz", "reflect_x", "reflect_yz"])
+def test_cubic_symmetry_on_the_device(S, dtype, tol, op):
+    """A cubic rotation or reflection of the input permutes the output (the
+    oracle's symmetry pin, on the device).  The kernels add neighbour pairs in
+    a fixed order, so the result agrees to rounding, not bit for bit."""
+    lam = 3.0
+    shape = (36, 36, 36)   # cube: the axis swaps keep the shape
+    phi0 = oracle.init_spheres(shape, [(14.3, 19.1, 16.7)], [8.5], lam=lam)
+    if dtype == "f32":
+        phi0 = as_f32_input(phi0)
+    ops = {"swap_xy": lambda a: np.ascontiguousarray(np.swapaxes(a, 1, 2)),
+           "swap_xz": lambda a: np.ascontiguousarray(np.swapaxes(a, 0, 2)),
+           "reflect_x": lambda a: np.ascontiguousarray(a[:, :, ::-1]),
+           "reflect_yz": lambda a: np.ascontiguousarray(a[::-1, ::-1, :])}
+    T = ops[op]
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    out = []
+    for f in (phi0, T(phi0)):
+        with S.Spfm(shape, lam=lam, mu=0.01, stencil=26, dtype=dtype, coupling="local", eps=eps,
+                    kernel="tiled") as s:
+            s.set_field(f)
+            s.step(10)
+            out.append(s.get_field().astype(np.float64))
+    assert float(np.abs(T(out[0]) - out[1]).max()) <= tol
