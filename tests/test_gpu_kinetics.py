@@ -81,3 +81,27 @@ def test_grain_shrinks_by_the_curvature_law_and_stays_spherical(S):
     assert abs(rs[0] - r0) < 1e-3
     assert abs(rate / law - 1.0) < lam / rs[-1]
     assert c["eps_eff"] < 1e-3
+
+
+def test_euler_error_is_first_order_and_extrapolates(S):
+    """P6 on the device (FP64, TI_n, 26 neighbours): a [100] slab moves at
+    v = -M mu / Gamma up to the forward-Euler error, which halves with dt, and
+    Richardson extrapolation of dt/2 and dt/4 removes most of it."""
+    lam, mu = 4.0, 0.08
+
+    def v(dt, steps):
+        with S.Spfm((3, 3, 160), lam=lam, mu=mu, stencil=26, dtype="f64", coupling="local",
+                    kernel="tiled", dt=dt) as s:
+            s.init_planar((1, 0, 0), 0.3)
+            s.step(steps // 4)
+            s.diagnostics()
+            s.step(steps - steps // 4)
+            return s.diagnostics()["velocity"]
+
+    v1, v2, v4 = v(0.2, 800), v(0.1, 1600), v(0.05, 3200)
+    vth = -mu
+    e1, e2, e4 = v1 - vth, v2 - vth, v4 - vth
+    print(f"errors {e1 / vth:+.3e} {e2 / vth:+.3e} {e4 / vth:+.3e}", flush=True)
+    assert abs(e2 / vth) < 1e-3
+    assert 1.7 < e1 / e2 < 2.3 and 1.7 < e2 / e4 < 2.3
+    assert abs((2 * v4 - v2) / vth - 1) < abs(e4 / vth) / 5
