@@ -79,8 +79,9 @@ def grain_shape(d, lam):
     """Size and isotropy of the shrinking grain after the timed steps: the
     volume-equivalent radius R_V of the ideal profile's phase volume (the
     sphere of radius R holds (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) of phi),
-    and the phi = 1/2 contour statistics of Sec. 3.4 (mean, extreme radii and
-    eps_eff = (R_max - R_min) / (2 R_mean))."""
+    the phi = 1/2 contour statistics of Sec. 3.4 (mean, extreme radii and
+    eps_eff = (R_max - R_min) / (2 R_mean)), and, when given, the same from the
+    radii along the configuration's seeded rays."""
     import math
     c = d["contour"]
     v = d["phase_volume"]
@@ -88,12 +89,18 @@ def grain_shape(d, lam):
     r = (3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0)
     for _ in range(50):   # Newton on R^3 + k R = 3 V / (4 pi)
         r -= (r ** 3 + k * r - 3.0 * v / (4.0 * math.pi)) / (3.0 * r * r + k)
-    return {"time": d["time"], "R_V": r, "R_mean": c["R_mean"], "R_min": c["R_min"],
-            "R_max": c["R_max"], "eps_eff": c["eps_eff"], "contour_points": c["points"]}
+    out = {"time": d["time"], "R_V": r, "R_mean": c["R_mean"], "R_min": c["R_min"],
+           "R_max": c["R_max"], "eps_eff": c["eps_eff"], "contour_points": c["points"]}
+    if "rays" in d:   # the same shape along the configuration's seeded rays
+        rr = d["rays"]
+        out.update({"rays": int(len(rr)), "ray_R_mean": float(sum(rr) / len(rr)),
+                    "ray_R_min": float(min(rr)), "ray_R_max": float(max(rr)),
+                    "ray_eps": float((max(rr) - min(rr)) / (2.0 * sum(rr) / len(rr)))})
+    return out
 
 
 def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0,
-              tsteps=0, contour=False):
+              tsteps=0, contour=False, rays=None):
     """Steps `steps` times after `warmup` untimed steps on a dedicated stream.
     Returns (wall seconds, event milliseconds) of the timed region and the
     diagnostics after it (with contour: the phi = 1/2 contour statistics)."""
@@ -118,6 +125,8 @@ def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="
         d["zchunk"] = s.info()["zchunk"]
         if contour:
             d["contour"] = s.contour_stats()
+            if rays is not None:
+                d["rays"] = s.ray_radii(rays, centre=d["contour"]["centre"])
         s.close()
     return wall, ev_ms, d
 
@@ -415,7 +424,7 @@ def main():
     if args.only in ("", "f32"):
         wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
                                    steps=args.steps, warmup=args.warmup, coupling=args.coupling,
-                                   zchunk=ZCHUNK, contour=True)
+                                   zchunk=ZCHUNK, contour=True, rays=w.rays)
         f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
     if args.only in ("", "f64"):
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",

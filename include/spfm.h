@@ -228,6 +228,20 @@ spfm_status spfm_init_box(spfm_ctx *ctx, const double lo[3], const double hi[3])
 /* Contour statistics of the current field (FP64 reductions on the device;
  * synchronises).  SPFM_E_STATE for walled grids. */
 spfm_status spfm_contour_stats(spfm_ctx *ctx, spfm_contour *out);
+/* Radii of a particle's phi = 1/2 surface along n rays from centre, the
+ * isotropy of its shape (Sec. 3.4) sampled along seeded directions: psi =
+ * ln((1-phi)/phi) of the field with phi clamped to [1e-12, 1 - 1e-12] (the
+ * inverse of Eq. 3 up to the factor lambda/4, which does not move its zero),
+ * trilinear between grid points of the periodic box, marched in steps of dx/4
+ * from the centre to the first sample with psi >= 0 and bisected 44 times.
+ * centre: 3 host doubles (x, y, z, units of length = dx * grid index); dirs:
+ * 3n host doubles, normalised here; radii: n host doubles, units of length, NaN
+ * where the centre is outside the particle or the ray runs half the smallest
+ * box edge without crossing.  Synchronises.  SPFM_E_INVAL for n < 1, NULL
+ * arrays, a non-finite centre or a zero direction; SPFM_E_STATE for walled
+ * grids. */
+spfm_status spfm_ray_radii(spfm_ctx *ctx, const double centre[3], int32_t n, const double *dirs,
+                           double *radii);
 
 /* Change the driving force (re-checks the stability bound). */
 spfm_status spfm_set_mu(spfm_ctx *ctx, double mu);

@@ -1000,6 +1000,42 @@ spfm_status spfm_contour_stats(spfm_ctx* c, spfm_contour* out) {
     return SPFM_OK;
 }
 
+spfm_status spfm_ray_radii(spfm_ctx* c, const double centre[3], int32_t n, const double* dirs,
+                           double* radii) {
+    if (!c || !centre || !dirs || !radii) return fail(SPFM_E_INVAL, "NULL argument");
+    if (n < 1) return fail(SPFM_E_INVAL, "n must be positive");
+    if (c->r.walls) return fail(SPFM_E_STATE, "ray radii need a periodic grid");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(centre[k])) return fail(SPFM_E_INVAL, "centre not finite");
+    for (int32_t i = 0; i < n; ++i) {
+        const double* d = dirs + 3 * (size_t)i;
+        const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!std::isfinite(nn) || nn == 0.0) return fail(SPFM_E_INVAL, "ray %d: zero or non-finite direction", i);
+    }
+    const Params& p = c->r.p;
+    const double cg[3] = {centre[0] / p.dx, centre[1] / p.dx, centre[2] / p.dx};
+    double* d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * 4 * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPFM_E_NOMEM, "device allocation for %d rays failed", n);
+    }
+    hipError_t e = hipMemcpyAsync(d, dirs, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = c->r.dtype == SPFM_F64
+                ? launch_ray_radii<double>((const double*)c->buf[c->cur], p.nx, p.ny, p.nz, cg, d, n,
+                                           d + 3 * (size_t)n, c->stream)
+                : launch_ray_radii<float>((const float*)c->buf[c->cur], p.nx, p.ny, p.nz, cg, d, n,
+                                          d + 3 * (size_t)n, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(radii, d + 3 * (size_t)n, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "ray radii: %s", hipGetErrorString(e));
+    for (int32_t i = 0; i < n; ++i) radii[i] *= p.dx;
+    return SPFM_OK;
+}
+
 spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");

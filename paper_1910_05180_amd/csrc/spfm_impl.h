@@ -482,6 +482,11 @@ hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp
 template <typename T>
 hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
                                 hipStream_t s);
+// Radii of the phi = 1/2 surface along n rays (d_dirs: 3n device doubles) from
+// centre (host, grid units) into d_radii (n device doubles, grid units).
+template <typename T>
+hipError_t launch_ray_radii(const T* phi, int nx, int ny, int nz, const double* centre,
+                           const double* d_dirs, int n, double* d_radii, hipStream_t s);
 template <typename T>
 hipError_t launch_init_box(T* phi, int nx, int ny, int nz, double dx, double lambda,
                            const double lo[3], const double hi[3], hipStream_t s);

@@ -250,6 +250,68 @@ __global__ __launch_bounds__(256) void k_init_box(T* __restrict__ phi, int nx, i
     phi[i] = (T)v;
 }
 
+// Radius of the phi = 1/2 surface along one ray from the centre (grid units):
+// psi = ln((1-phi)/phi) of the clamped field (the inverse of Eq. 3 up to the
+// factor lambda/4, which does not move its zero), trilinear between grid
+// points of the periodic box, marched in steps of 1/4 from the centre to the
+// first sample with psi >= 0, then bisected 44 times.  NaN where the centre is
+// outside or the ray runs half the smallest box edge without crossing.  One
+// thread per ray; FP64 throughout.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ray_radii(const T* __restrict__ phi, int nx, int ny, int nz,
+                                                   double cx, double cy, double cz,
+                                                   const double* __restrict__ dirs, int n,
+                                                   double* __restrict__ radii) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double ux = dirs[3 * i], uy = dirs[3 * i + 1], uz = dirs[3 * i + 2];
+    const double norm = sqrt(ux * ux + uy * uy + uz * uz);
+    ux /= norm;
+    uy /= norm;
+    uz /= norm;
+    auto wrap = [](long v, int m) { v %= m; return (int)(v < 0 ? v + m : v); };
+    auto psi_at = [&](long x, long y, long z) {
+        const size_t at = ((size_t)wrap(z, nz) * ny + wrap(y, ny)) * nx + wrap(x, nx);
+        const double f = fmin(fmax((double)phi[at], 1e-12), 1.0 - 1e-12);
+        return log((1.0 - f) / f);
+    };
+    auto sample = [&](double t) {
+        const double qx = cx + t * ux, qy = cy + t * uy, qz = cz + t * uz;
+        const double fx = floor(qx), fy = floor(qy), fz = floor(qz);
+        const double wx1 = qx - fx, wy1 = qy - fy, wz1 = qz - fz;
+        const long ix = (long)fx, iy = (long)fy, iz = (long)fz;
+        double val = 0.0;
+        for (int dz = 0; dz < 2; ++dz) {
+            const double wz = dz ? wz1 : 1.0 - wz1;
+            for (int dy = 0; dy < 2; ++dy) {
+                const double wy = dy ? wy1 : 1.0 - wy1;
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double wx = dx ? wx1 : 1.0 - wx1;
+                    val += wz * wy * wx * psi_at(ix + dx, iy + dy, iz + dz);
+                }
+            }
+        }
+        return val;
+    };
+    const double step = 0.25;
+    const int kmax = (int)floor(0.5 * (double)min(nx, min(ny, nz)) / step);
+    double r = __builtin_nan("");
+    if (sample(0.0) < 0.0) {
+        for (int k = 1; k <= kmax; ++k) {
+            if (sample(k * step) >= 0.0) {
+                double a = (k - 1) * step, b = k * step;
+                for (int it = 0; it < 44; ++it) {
+                    const double m = 0.5 * (a + b);
+                    if (sample(m) >= 0.0) b = m; else a = m;
+                }
+                r = 0.5 * (a + b);
+                break;
+            }
+        }
+    }
+    radii[i] = r;
+}
+
 }  // namespace
 
 template <typename T>
@@ -265,6 +327,15 @@ hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_cv_apply<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi_new,
                        phi_old, n, interp, d_state);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ray_radii(const T* phi, int nx, int ny, int nz, const double* centre,
+                           const double* d_dirs, int n, double* d_radii, hipStream_t s) {
+    if (n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_ray_radii<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi, nx, ny,
+                       nz, centre[0], centre[1], centre[2], d_dirs, n, d_radii);
     return hipGetLastError();
 }
 
@@ -306,6 +377,10 @@ template hipError_t launch_contour_stats<float>(const float*, int, int, int, dou
                                                 hipStream_t);
 template hipError_t launch_contour_stats<double>(const double*, int, int, int, double*, double*,
                                                  hipStream_t);
+template hipError_t launch_ray_radii<float>(const float*, int, int, int, const double*,
+                                            const double*, int, double*, hipStream_t);
+template hipError_t launch_ray_radii<double>(const double*, int, int, int, const double*,
+                                             const double*, int, double*, hipStream_t);
 template hipError_t launch_init_box<float>(float*, int, int, int, double, double, const double*,
                                            const double*, hipStream_t);
 template hipError_t launch_init_box<double>(double*, int, int, int, double, double, const double*,

@@ -107,6 +107,7 @@ def load():
         "spfm_init_front": ([vp, dp, d], ctypes.c_int),
         "spfm_init_box": ([vp, dp, dp], ctypes.c_int),
         "spfm_contour_stats": ([vp, ctypes.POINTER(Contour)], ctypes.c_int),
+        "spfm_ray_radii": ([vp, dp, i32, dp, dp], ctypes.c_int),
         "spfm_set_mu": ([vp, d], ctypes.c_int),
         "spfm_step": ([vp, i64], ctypes.c_int),
         "spfm_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
@@ -294,6 +295,18 @@ class Spfm:
         _check(load().spfm_contour_stats(self._h, ctypes.byref(c)))
         out = {n: getattr(c, n) for n, _ in Contour._fields_}
         out["centre"] = tuple(c.centre)
+        return out
+
+    def ray_radii(self, dirs, centre=None) -> np.ndarray:
+        """Radii of the phi = 1/2 surface along the rays `dirs` (n x 3) from
+        `centre` (default: the barycentre of contour_stats)."""
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        c = np.ascontiguousarray(np.asarray(centre if centre is not None
+                                            else self.contour_stats()["centre"], dtype=np.float64))
+        out = np.empty(d.shape[0])
+        dptr = ctypes.POINTER(ctypes.c_double)
+        _check(load().spfm_ray_radii(self._h, c.ctypes.data_as(dptr), int(d.shape[0]),
+                                     d.ctypes.data_as(dptr), out.ctypes.data_as(dptr)))
         return out
 
     def init_front(self, n, offset: float = 0.0):

@@ -128,3 +128,58 @@ def test_cf_cube_stays_anisotropic_where_ti_relaxes(S):
     print(f"cube lam=2: TI_n eps={c_ti['eps_eff']:.3e}, CF eps={c_cf['eps_eff']:.3e}", flush=True)
     assert c_ti["eps_eff"] < 1e-3
     assert c_cf["eps_eff"] > 10 * c_ti["eps_eff"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ray_radii_match_the_oracle(S, dtype):
+    """Radii along 500 seeded rays from the barycentre of a grain built by the
+    oracle, on the device and in the oracle from the same (for FP32, the same
+    FP32-rounded) field: the same march and bisection, so within 1e-9."""
+    shape, R, cen = (48, 44, 52), 13.0, (25.3, 21.6, 23.9)
+    phi = oracle.init_spheres(shape, [cen], [R], lam=3.0)
+    if dtype == "f32":
+        phi = phi.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(17)
+    d = rng.normal(size=(500, 3))
+    with S.Spfm(shape, lam=3.0, stencil=26, dtype=dtype) as s:
+        s.set_field(phi)
+        got = s.ray_radii(d, centre=cen)
+        dflt = s.ray_radii(d[:10])     # centre: the contour barycentre
+        same = s.ray_radii(d[:10], centre=s.contour_stats()["centre"])
+    ref = oracle.ray_radii(phi, cen, d)
+    assert not np.isnan(ref).any()
+    assert float(np.abs(got - ref).max()) <= 1e-9
+    assert np.array_equal(dflt, same)
+
+
+def test_ray_radii_exact_for_a_linear_psi_on_the_device(S):
+    shape = (40, 40, 40)
+    n = np.array([1.0, 0.4, -0.3])
+    n /= np.linalg.norm(n)
+    centre = np.array([20.3, 19.7, 20.1])
+    c0 = float(n @ centre) + 9.3
+    nz, ny, nx = shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = 1.0 / (1.0 + np.exp(n[0] * xx + n[1] * yy + n[2] * zz - c0))
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    d = d[d @ n >= 0.55][:100]
+    with S.Spfm(shape, lam=4.0, stencil=26, dtype="f64") as s:
+        s.set_field(phi)
+        got = s.ray_radii(d, centre=centre)
+        outside = s.ray_radii(-d[:3], centre=centre + 12.0 * n)
+    assert float(np.abs(got - (c0 - n @ centre) / (d @ n)).max()) < 1e-9
+    assert np.isnan(outside).all()
+
+
+def test_ray_radii_reject_bad_arguments(S):
+    with S.Spfm((16, 16, 16), lam=3.0, stencil=26, dtype="f32") as s:
+        with pytest.raises(S.SpfmError):
+            s.ray_radii(np.array([[0.0, 0.0, 0.0]]), centre=(8.0, 8.0, 8.0))
+        with pytest.raises(S.SpfmError):
+            s.ray_radii(np.array([[1.0, 0.0, 0.0]]), centre=(8.0, float("nan"), 8.0))
+    with S.Spfm((16, 16, 16), lam=3.0, stencil=26, dtype="f32", walls=1,
+                wall_sin=(0, 0, 0, 0, 0, 0)) as s:
+        with pytest.raises(S.SpfmError):
+            s.ray_radii(np.array([[1.0, 0.0, 0.0]]), centre=(8.0, 8.0, 8.0))

@@ -95,3 +95,45 @@ def test_box_particle_faces():
         got = sorted(on_axis[:, d])
         assert len(got) == 2
         assert abs(got[0] - lo[d]) < 1e-3 and abs(got[1] - hi[d]) < 1e-3
+
+
+def _linear_psi_field(shape, n, c0):
+    """phi = 1 / (1 + e^s) with s = n.x - c0: psi = ln((1-phi)/phi) = s is
+    linear, so trilinear interpolation reproduces it exactly."""
+    nz, ny, nx = shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = n[0] * xx + n[1] * yy + n[2] * zz - c0
+    return 1.0 / (1.0 + np.exp(s))
+
+
+def test_ray_radii_exact_for_a_linear_psi():
+    """Where psi is linear (an ideal planar front) the ray meets psi = 0 at
+    t = (c0 - n.centre) / (n.d) exactly; the oracle finds it to the bisection
+    tolerance."""
+    shape = (40, 40, 40)
+    n = np.array([1.0, 0.4, -0.3])
+    n /= np.linalg.norm(n)
+    centre = np.array([20.3, 19.7, 20.1])
+    c0 = float(n @ centre) + 9.3
+    phi = _linear_psi_field(shape, n, c0)
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    d = d[d @ n >= 0.55][:100]     # crossings within 17 cells: no wrap before them
+    r = oracle.ray_radii(phi, centre, d)
+    exact = (c0 - n @ centre) / (d @ n)
+    assert np.all(np.abs(r - exact) < 1e-9)
+
+
+def test_ray_radii_of_an_ideal_grain():
+    """For the ideal radial profile psi is linear in r = |x - c| but not in x:
+    trilinear interpolation errs by at most (3/8) max|d2 r| = 3 / (8 R) over a
+    unit cell, and only inwards (r is convex).  A ray from outside the grain
+    gives NaN."""
+    shape, R, cen = (40, 40, 40), 12.0, (19.6, 20.2, 20.1)
+    phi = oracle.init_spheres(shape, [cen], [R], lam=3.0)
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=(300, 3))
+    r = oracle.ray_radii(phi, cen, d)
+    assert np.all(r <= R + 1e-9) and np.all(r >= R - 3.0 / (8.0 * R))
+    assert np.isnan(oracle.ray_radii(phi, (2.0, 2.0, 2.0), d[:5])).all()
