@@ -228,6 +228,15 @@ spfm_status spfm_init_box(spfm_ctx *ctx, const double lo[3], const double hi[3])
 /* Contour statistics of the current field (FP64 reductions on the device;
  * synchronises).  SPFM_E_STATE for walled grids. */
 spfm_status spfm_contour_stats(spfm_ctx *ctx, spfm_contour *out);
+/* Free energy of Eq. 1 of the current field (FP64 on the device, compensated
+ * sums; synchronises): F = dx^3 sum_p Gamma/(C_Gamma lambda) sum_k gamma_j
+ * nu_j [lambda^2/2 ((phi_{p+r_k} - phi_p)/|r_k|)^2 + g_k(phi_p)], one r_k of
+ * each opposite pair over the stencil's directions, g_k of Eq. 6 with a_k =
+ * tanh(2 r_k.n dx / lambda) (TI_n: n from central differences of psi, as in
+ * the step; TI_<hkl>: n = u) or 8 phi^2 (1-phi)^2 / 3 (CF); with with_mu
+ * nonzero plus dx^3 sum_p mu h(phi_p) with the context's mu and h.
+ * SPFM_E_STATE for walled grids. */
+spfm_status spfm_energy(spfm_ctx *ctx, int with_mu, double *out);
 /* Radii of a particle's phi = 1/2 surface along n rays from centre, the
  * isotropy of its shape (Sec. 3.4) sampled along seeded directions: psi =
  * ln((1-phi)/phi) of the field with phi clamped to [1e-12, 1 - 1e-12] (the

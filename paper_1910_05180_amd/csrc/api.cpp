@@ -1036,6 +1036,25 @@ spfm_status spfm_ray_radii(spfm_ctx* c, const double centre[3], int32_t n, const
     return SPFM_OK;
 }
 
+spfm_status spfm_energy(spfm_ctx* c, int with_mu, double* out) {
+    if (!c || !out) return fail(SPFM_E_INVAL, "NULL argument");
+    if (c->r.walls) return fail(SPFM_E_STATE, "the energy needs a periodic grid");
+    const Params& p = c->r.p;
+    const EnergyCoef ec = make_energy_coef(p);
+    // partials (2 per block of the energy kernel) and the total in the reduction scratch
+    static_assert(2 * 1024 + 1 <= kReduceBlocks * 8, "energy partials fit the scratch");
+    double* d_total = c->d_part() + 2 * 1024;
+    const hipError_t e = c->r.dtype == SPFM_F64
+                             ? launch_energy<double>((const double*)c->buf[c->cur], p.nx, p.ny, p.nz, ec,
+                                                     with_mu ? 1 : 0, c->d_part(), d_total, c->stream)
+                             : launch_energy<float>((const float*)c->buf[c->cur], p.nx, p.ny, p.nz, ec,
+                                                    with_mu ? 1 : 0, c->d_part(), d_total, c->stream);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "energy: %s", hipGetErrorString(e));
+    HIP_TRY(hipMemcpyAsync(out, d_total, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SPFM_OK;
+}
+
 spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");

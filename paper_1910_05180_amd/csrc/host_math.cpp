@@ -183,6 +183,29 @@ StepCoef<T> make_coef(const Params& p) {
     return k;
 }
 
+EnergyCoef make_energy_coef(const Params& p) {
+    EnergyCoef c{};
+    const int nsh = p.stencil == 6 ? 1 : (p.stencil == 18 ? 2 : 3);
+    for (int j = 1; j <= 3; ++j) c.w[j - 1] = j <= nsh ? p.gamma[j - 1] * nu_of(j) : 0.0;
+    c.pref = p.Gamma / (p.C_Gamma * p.lambda);
+    c.lambda = p.lambda;
+    c.dx = p.dx;
+    c.mu = p.mu;
+    c.eps = p.eps;
+    c.tau = p.tau;
+    c.ndir = ndirs(p.stencil);
+    c.coupling = p.coupling;
+    c.interp = p.interp;
+    const double un = sqrt(p.u[0] * p.u[0] + p.u[1] * p.u[1] + p.u[2] * p.u[2]);
+    for (int d = 0; d < 13; ++d) {
+        double rn = 0.0;
+        if (p.coupling == kGlobal && un > 0.0)
+            rn = (kDir[d][0] * p.u[0] + kDir[d][1] * p.u[1] + kDir[d][2] * p.u[2]) / un;
+        c.ag[d] = tanh(2.0 * rn * p.dx / p.lambda);
+    }
+    return c;
+}
+
 template StepCoef<float> make_coef<float>(const Params&);
 template StepCoef<double> make_coef<double>(const Params&);
 

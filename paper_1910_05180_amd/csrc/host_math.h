@@ -21,5 +21,6 @@ double stable_dt(int stencil, int coupling, const double u[3], const double gamm
                  int interp = 0);
 template <typename T>
 StepCoef<T> make_coef(const Params& p);
+EnergyCoef make_energy_coef(const Params& p);
 
 }  // namespace spfm

@@ -482,6 +482,23 @@ hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp
 template <typename T>
 hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
                                 hipStream_t s);
+// Coefficients of the free energy of Eq. 1 (FP64): per-shell weights
+// gamma_j nu_j (0 beyond the stencil), the prefactor Gamma / (C_Gamma lambda),
+// and for TI_<hkl> the a_k = tanh(2 r_k.u dx / lambda) of its fixed direction.
+struct EnergyCoef {
+    double w[3];
+    double pref;
+    double lambda, dx, mu, eps, tau;
+    double ag[13];
+    int ndir;       // 3, 9 or 13 directions
+    int coupling;   // 0 TI_n, 1 TI_<hkl>, 2 CF (the spfm_coupling values)
+    int interp;     // kH3, kH5 or kHAbel (for the mu h(phi) term)
+};
+// F = dx^3 sum_p f_p of Eq. 1 (with mu h(phi) when with_mu), compensated FP64
+// sums: per-block partials in d_part (2 x 1024 doubles), the total in *d_out.
+template <typename T>
+hipError_t launch_energy(const T* phi, int nx, int ny, int nz, const EnergyCoef& c, int with_mu,
+                         double* d_part, double* d_out, hipStream_t s);
 // Radii of the phi = 1/2 surface along n rays (d_dirs: 3n device doubles) from
 // centre (host, grid units) into d_radii (n device doubles, grid units).
 template <typename T>

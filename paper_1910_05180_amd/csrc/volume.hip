@@ -250,6 +250,143 @@ __global__ __launch_bounds__(256) void k_init_box(T* __restrict__ phi, int nx, i
     phi[i] = (T)v;
 }
 
+// ---- free energy of Eq. 1 (diagnostic, FP64) ----
+
+// Directions r_k of Tab. 1 (one of each opposite pair), shell by shell.
+__constant__ int kEdir[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+                                 {1, 1, 0}, {1, -1, 0}, {0, 1, 1}, {0, 1, -1}, {1, 0, 1}, {1, 0, -1},
+                                 {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+
+// Eq. 6 for one direction: g_k = (lambda^2 / rho^2) x T(z) with x = phi(1-phi),
+// u = 1 - 2 phi, z = 4 a^2 x / (1 - a^2 u^2) and T(z) = 1 + (1-z) ln(1-z) / z,
+// the printed expression with its two cancelling terms gathered (A2).  For
+// z < 0.1 T is summed from its series sum_{m>=1} z^m / (m (m+1)), Horner,
+// m <= 14 (truncation below 1e-17).
+__device__ __forceinline__ double eq6_g(double x, double u, double a, double r2_over_l2) {
+    const double q = a * a;
+    if (q == 0.0 || x == 0.0) return 0.0;
+    const double z = 4.0 * q * x / (1.0 - q * u * u);
+    double t;
+    if (z < 0.1) {
+        t = 1.0 / (14.0 * 15.0);
+        for (int m = 13; m >= 1; --m) t = 1.0 / (m * (m + 1.0)) + z * t;
+        t *= z;
+    } else {
+        t = 1.0 + (1.0 - z) * log1p(-z) / z;
+    }
+    return x * t / r2_over_l2;
+}
+
+// Interpolation functions h(phi) of Tab. 2 for the mu h(phi) term.
+__device__ __forceinline__ double interp_h(int which, double p) {
+    if (which == kH5) return p * p * p * (10.0 - 15.0 * p + 6.0 * p * p);
+    if (which == kHAbel) return p * p / (p * p + (1.0 - p) * (1.0 - p));
+    return p * p * (3.0 - 2.0 * p);
+}
+
+// Energy density f_p of Eq. 1 at one point of the periodic grid: forward
+// differences over the stencil's directions, the TI potential of Eq. 6 with
+// a_k = tanh(2 r_k.n dx / lambda) (TI_n: n = grad psi / |grad psi| from
+// central differences of psi = (lambda/4) ln((1-phi)/phi), both logarithm
+// arguments floored at eps, n = (1,0,0) where |grad psi| < tau; TI_<hkl>: the
+// fixed a_k), or the CF potential 8 x^2 / 3 per direction.
+template <typename T>
+__device__ double energy_density(const T* __restrict__ phi, int nx, int ny, int nz, int x, int y,
+                                 int z, const EnergyCoef& c, int with_mu) {
+    auto at = [&](int xx, int yy, int zz) {
+        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        return (double)phi[((size_t)zz * ny + yy) * nx + xx];
+    };
+    const double p0 = at(x, y, z);
+    const double xx0 = p0 * (1.0 - p0), u = 1.0 - 2.0 * p0;
+    double n[3] = {1.0, 0.0, 0.0};
+    if (c.coupling == kLocal) {
+        auto psi = [&](double v) {
+            return 0.25 * c.lambda * (log(fmax(1.0 - v, c.eps)) - log(fmax(v, c.eps)));
+        };
+        const double g0 = (psi(at(x + 1, y, z)) - psi(at(x - 1, y, z))) / (2.0 * c.dx);
+        const double g1 = (psi(at(x, y + 1, z)) - psi(at(x, y - 1, z))) / (2.0 * c.dx);
+        const double g2 = (psi(at(x, y, z + 1)) - psi(at(x, y, z - 1))) / (2.0 * c.dx);
+        const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+        if (!(gn < c.tau)) {
+            n[0] = g0 / gn;
+            n[1] = g1 / gn;
+            n[2] = g2 / gn;
+        }
+    }
+    double s = 0.0;
+    for (int k = 0; k < c.ndir; ++k) {
+        const int j = k < 3 ? 1 : (k < 9 ? 2 : 3);
+        const double rho2 = j * c.dx * c.dx;
+        const double d = at(x + kEdir[k][0], y + kEdir[k][1], z + kEdir[k][2]) - p0;
+        double g;
+        if (c.coupling == kCF) {
+            g = 8.0 * xx0 * xx0 / 3.0;
+        } else {
+            const double a = c.coupling == kGlobal
+                                 ? c.ag[k]
+                                 : tanh(2.0 * (kEdir[k][0] * n[0] + kEdir[k][1] * n[1] + kEdir[k][2] * n[2]) *
+                                        c.dx / c.lambda);
+            g = eq6_g(xx0, u, a, rho2 / (c.lambda * c.lambda));
+        }
+        s += c.w[j - 1] * (0.5 * c.lambda * c.lambda * d * d / rho2 + g);
+    }
+    double f = c.pref * s;
+    if (with_mu) f += c.mu * interp_h(c.interp, p0);
+    return f;
+}
+
+// Neumaier's compensated sum, and the exact combination of two (sum, error) pairs.
+__device__ __forceinline__ void comp_add(double& s, double& e, double v) {
+    const double t = s + v;
+    e += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+}
+
+constexpr int kEnergyBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_partial(const T* __restrict__ phi, int nx, int ny, int nz,
+                                                        EnergyCoef c, int with_mu, double* __restrict__ part) {
+    __shared__ double ss[256], se[256];
+    double s = 0.0, e = 0.0;
+    const int64_t total = (int64_t)nx * ny * nz;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        comp_add(s, e, energy_density(phi, nx, ny, nz, x, y, z, c, with_mu));
+    }
+    ss[threadIdx.x] = s;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            double a = ss[threadIdx.x], ea = se[threadIdx.x];
+            comp_add(a, ea, ss[threadIdx.x + h]);
+            ss[threadIdx.x] = a;
+            se[threadIdx.x] = ea + se[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss[0];
+        part[2 * blockIdx.x + 1] = se[0];
+    }
+}
+
+// One thread: the block partials in order, compensated.
+__global__ __launch_bounds__(64) void k_energy_final(const double* __restrict__ part, int nb, double dx3,
+                                                     double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, e = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        comp_add(s, e, part[2 * b]);
+        e += part[2 * b + 1];
+    }
+    out[0] = (s + e) * dx3;
+}
+
 // Radius of the phi = 1/2 surface along one ray from the centre (grid units):
 // psi = ln((1-phi)/phi) of the clamped field (the inverse of Eq. 3 up to the
 // factor lambda/4, which does not move its zero), trilinear between grid
@@ -331,6 +468,16 @@ hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp
 }
 
 template <typename T>
+hipError_t launch_energy(const T* phi, int nx, int ny, int nz, const EnergyCoef& c, int with_mu,
+                         double* d_part, double* d_out, hipStream_t s) {
+    hipLaunchKernelGGL((k_energy_partial<T>), dim3(kEnergyBlocks), dim3(256), 0, s, phi, nx, ny, nz, c,
+                       with_mu, d_part);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, s, d_part, kEnergyBlocks,
+                       c.dx * c.dx * c.dx, d_out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_ray_radii(const T* phi, int nx, int ny, int nz, const double* centre,
                            const double* d_dirs, int n, double* d_radii, hipStream_t s) {
     if (n < 1) return hipErrorInvalidValue;
@@ -377,6 +524,10 @@ template hipError_t launch_contour_stats<float>(const float*, int, int, int, dou
                                                 hipStream_t);
 template hipError_t launch_contour_stats<double>(const double*, int, int, int, double*, double*,
                                                  hipStream_t);
+template hipError_t launch_energy<float>(const float*, int, int, int, const EnergyCoef&, int, double*,
+                                        double*, hipStream_t);
+template hipError_t launch_energy<double>(const double*, int, int, int, const EnergyCoef&, int, double*,
+                                         double*, hipStream_t);
 template hipError_t launch_ray_radii<float>(const float*, int, int, int, const double*,
                                             const double*, int, double*, hipStream_t);
 template hipError_t launch_ray_radii<double>(const double*, int, int, int, const double*,

@@ -108,6 +108,7 @@ def load():
         "spfm_init_box": ([vp, dp, dp], ctypes.c_int),
         "spfm_contour_stats": ([vp, ctypes.POINTER(Contour)], ctypes.c_int),
         "spfm_ray_radii": ([vp, dp, i32, dp, dp], ctypes.c_int),
+        "spfm_energy": ([vp, ctypes.c_int, dp], ctypes.c_int),
         "spfm_set_mu": ([vp, d], ctypes.c_int),
         "spfm_step": ([vp, i64], ctypes.c_int),
         "spfm_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
@@ -296,6 +297,12 @@ class Spfm:
         out = {n: getattr(c, n) for n, _ in Contour._fields_}
         out["centre"] = tuple(c.centre)
         return out
+
+    def energy(self, with_mu: bool = False) -> float:
+        """Free energy of Eq. 1 of the current field (with mu h(phi) if with_mu)."""
+        out = ctypes.c_double()
+        _check(load().spfm_energy(self._h, 1 if with_mu else 0, ctypes.byref(out)))
+        return out.value
 
     def ray_radii(self, dirs, centre=None) -> np.ndarray:
         """Radii of the phi = 1/2 surface along the rays `dirs` (n x 3) from
