@@ -89,6 +89,20 @@ def test_create_rejects_planes_beyond_32_bit_byte_offsets(S):
     assert st == -1 and "2^31" in msg
 
 
+@pytest.mark.parametrize("shape", [(65536, 3, 3), (3, 262141, 3), (1 << 20, 3, 3)])
+def test_create_rejects_axes_beyond_the_launch_grid(S, shape):
+    # shapes are (nz, ny, nx); nz <= 65535 and ny <= 262140 keep the plain
+    # kernel's launch grid within its limits
+    st, msg = S.try_create(shape)
+    assert st == -1 and "grid too large" in msg
+
+
+def test_walled_axes_count_their_ghosts_against_the_axis_limits(S):
+    # 65534 interior planes and two ghost planes make 65536 stored planes
+    st, msg = S.try_create((65534, 3, 3), walls=4)
+    assert st == -1 and "grid too large" in msg
+
+
 def test_walls_on_other_axes_ignore_their_faces(S):
     """wall_sin of an unwalled axis is not looked at (here a NaN on the x faces
     with only z walled); validation then fails only for the dt bound."""
@@ -135,6 +149,12 @@ def try_batch(S, shapes, **kw):
 def test_walled_batch_validates_each_grid(S, kw, needle):
     st, msg = try_batch(S, [(8, 8, 20), (8, 8, 24)], **kw)
     assert st == -1 and needle in msg, msg
+
+
+@pytest.mark.parametrize("shapes", [[(16, 16, 16), (65536, 3, 3)], [(3, 262141, 3)]])
+def test_batch_rejects_grids_beyond_the_launch_grid(S, shapes):
+    st, msg = try_batch(S, shapes)
+    assert st == -1, (st, msg)
 
 
 def test_walled_batch_accepts_short_walled_axes(S):
