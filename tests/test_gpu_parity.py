@@ -88,6 +88,28 @@ def test_small_and_ragged_grids(S, shape):
             assert err <= tol, (dtype, kernel, err)
 
 
+@pytest.mark.parametrize("shape", [(65535, 3, 3), (3, 262140, 3)])
+def test_axes_at_their_maximum_length(S, shape):
+    """nz = 65535 and ny = 262140, the longest axes spfm_create accepts (shape
+    is (nz, ny, nx)): plain and tiled kernels against the oracle over a short
+    noisy window, and two fused steps bitwise equal to two tiled steps."""
+    phi0 = noisy_field(shape, 1.5, 13)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        for kernel in ("plain", "tiled"):
+            print(f"case max axis {shape} {dtype} {kernel}", flush=True)
+            err, _, _ = run_pair(S, 5, dtype=dtype, kernel=kernel, stencil=26,
+                                 coupling="local", phi0=phi0, lam=1.5)
+            assert err <= tol, (dtype, kernel, err)
+    out = []
+    for kw in (dict(), dict(tsteps=2)):
+        print(f"case max axis {shape} f32 tiled {kw}", flush=True)
+        with S.Spfm(shape, lam=1.5, mu=0.0, stencil=26, kernel="tiled", dt=0.05, **kw) as s:
+            s.set_field(phi0.astype(np.float32))
+            s.step(2)
+            out.append(s.get_field())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))
+
+
 def test_planar32_fp64_full_run(S):
     """32^3 periodic [100] slab, lambda = 4, mu = 0.05, 6 neighbours, 500 steps (FP64)."""
     from paper_1910_05180_amd import inputs
