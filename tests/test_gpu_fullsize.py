@@ -26,14 +26,18 @@ def S():
     return spfm
 
 
-def sample_points(rng, shape, centers, radii, n, lam):
-    """Half uniform, half inside the interface bands of the grains."""
+def sample_points(rng, shape, centers, radii, n, lam, flat=False):
+    """Half uniform, half inside the interface bands of the grains (with flat,
+    along directions in the x-y plane: on a grid a few planes thick a grain is
+    a disc)."""
     nz, ny, nx = shape
     pts = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz)))
            for _ in range(n // 2)]
     while len(pts) < n:
         i = int(rng.integers(len(radii)))
         v = rng.normal(size=3)
+        if flat:
+            v[2] = 0.0
         v /= np.linalg.norm(v)
         r = radii[i] + rng.uniform(-3 * lam, 3 * lam)
         p = np.asarray(centers[i]) + r * v
@@ -41,7 +45,7 @@ def sample_points(rng, shape, centers, radii, n, lam):
     return pts
 
 
-def run_grains(S, w, steps, nsamples, seed):
+def run_grains(S, w, steps, nsamples, seed, flat=False):
     rng = np.random.default_rng(seed)
     print(f"full size {w.shape} grains={len(w.radii)} steps={steps}", flush=True)
     with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f32", coupling="local",
@@ -50,7 +54,7 @@ def run_grains(S, w, steps, nsamples, seed):
         s.init_spheres(w.centers, w.radii)
         s.step(steps)
         got = s.get_field()
-    pts = sample_points(rng, w.shape, w.centers, w.radii, nsamples, w.lam)
+    pts = sample_points(rng, w.shape, w.centers, w.radii, nsamples, w.lam, flat)
     p = oracle.params((3, 3, 3), lam=w.lam, mu=w.mu, dt=w.dt, stencil=26, coupling="local",
                       eps=1e-30)
     field_at = lambda xyz: oracle.spheres_at(w.shape, w.centers, w.radii, xyz, lam=w.lam)
@@ -70,6 +74,21 @@ def test_grain256_bench_configuration(S):
 def test_grains512_bench_configuration(S):
     from paper_1910_05180_amd import inputs
     err = run_grains(S, inputs.grains512(), 3, 1000, 12)
+    assert err <= 1e-5
+
+
+def test_plane_at_the_32_bit_offset_limit(S):
+    """The largest FP32 z-plane spfm_create accepts: 32767 x 16384 points,
+    2^31 - 2^16 bytes, so in-plane byte offsets reach the top of their 32-bit
+    range (3 planes, 1.6e9 points).  Grains sit at the corners of the plane
+    and in its middle; sampled outputs after 2 steps against the oracle's
+    dependency cones."""
+    from types import SimpleNamespace
+    w = SimpleNamespace(shape=(3, 16384, 32767), lam=4.0, mu=0.02, dt=0.1,
+                        centers=[(32740.0, 16360.0, 1.0), (25.0, 16350.0, 0.0), (32700.0, 30.0, 2.0),
+                                 (16000.0, 8000.0, 1.0)],
+                        radii=[30.0, 24.0, 28.0, 40.0])
+    err = run_grains(S, w, 2, 1000, 14, flat=True)
     assert err <= 1e-5
 
 
