@@ -45,10 +45,10 @@ def sample_points(rng, shape, centers, radii, n, lam, flat=False):
     return pts
 
 
-def run_grains(S, w, steps, nsamples, seed, flat=False):
+def run_grains(S, w, steps, nsamples, seed, flat=False, dtype="f32"):
     rng = np.random.default_rng(seed)
     print(f"full size {w.shape} grains={len(w.radii)} steps={steps}", flush=True)
-    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype="f32", coupling="local",
+    with S.Spfm(w.shape, lam=w.lam, mu=w.mu, stencil=26, dtype=dtype, coupling="local",
                 kernel="tiled", zchunk=ZCHUNK, dt=w.dt) as s:
         assert s.info()["zchunk"] == ZCHUNK
         s.init_spheres(w.centers, w.radii)
@@ -56,7 +56,7 @@ def run_grains(S, w, steps, nsamples, seed, flat=False):
         got = s.get_field()
     pts = sample_points(rng, w.shape, w.centers, w.radii, nsamples, w.lam, flat)
     p = oracle.params((3, 3, 3), lam=w.lam, mu=w.mu, dt=w.dt, stencil=26, coupling="local",
-                      eps=1e-30)
+                      eps=1e-300 if dtype == "f64" else 1e-30)
     field_at = lambda xyz: oracle.spheres_at(w.shape, w.centers, w.radii, xyz, lam=w.lam)
     ref = oracle.cone_step(p, w.shape, field_at, pts, steps)
     g = np.array([got[z, y, x] for x, y, z in pts], dtype=np.float64)
@@ -77,19 +77,20 @@ def test_grains512_bench_configuration(S):
     assert err <= 1e-5
 
 
-def test_plane_at_the_32_bit_offset_limit(S):
-    """The largest FP32 z-plane spfm_create accepts: 32767 x 16384 points,
-    2^31 - 2^16 bytes, so in-plane byte offsets reach the top of their 32-bit
-    range (3 planes, 1.6e9 points).  Grains sit at the corners of the plane
-    and in its middle; sampled outputs after 2 steps against the oracle's
-    dependency cones."""
+@pytest.mark.parametrize("dtype,nx,tol", [("f32", 32767, 1e-5), ("f64", 16383, 1e-12)])
+def test_plane_at_the_32_bit_offset_limit(S, dtype, nx, tol):
+    """The largest z-plane spfm_create accepts: nx x 16384 points, just under
+    2^31 bytes, so in-plane byte offsets reach the top of their 32-bit range
+    (3 planes; 1.6e9 FP32 or 8.1e8 FP64 points).  Grains sit at the corners
+    of the plane and in its middle; sampled outputs after 2 steps against the
+    oracle's dependency cones."""
     from types import SimpleNamespace
-    w = SimpleNamespace(shape=(3, 16384, 32767), lam=4.0, mu=0.02, dt=0.1,
-                        centers=[(32740.0, 16360.0, 1.0), (25.0, 16350.0, 0.0), (32700.0, 30.0, 2.0),
-                                 (16000.0, 8000.0, 1.0)],
+    w = SimpleNamespace(shape=(3, 16384, nx), lam=4.0, mu=0.02, dt=0.1,
+                        centers=[(nx - 27.0, 16360.0, 1.0), (25.0, 16350.0, 0.0), (nx - 67.0, 30.0, 2.0),
+                                 (nx / 2, 8000.0, 1.0)],
                         radii=[30.0, 24.0, 28.0, 40.0])
-    err = run_grains(S, w, 2, 1000, 14, flat=True)
-    assert err <= 1e-5
+    err = run_grains(S, w, 2, 1000, 14, flat=True, dtype=dtype)
+    assert err <= tol
 
 
 def test_grain256_fp64_plain_one_step_everywhere(S):
