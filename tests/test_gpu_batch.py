@@ -149,3 +149,29 @@ def test_full_batch_instances_match_oracle(S):
         p = oracle.params(w.shape, lam=w.lam, mu=w.mu, stencil=26, coupling="local", eps=1e-30)
         ref = oracle.step(p, fields[i], steps)
         assert float(np.abs(got[i] - ref).max()) <= 1e-5, i
+
+
+def test_grids_beyond_32_bit_element_offsets(S):
+    """Two grids with the largest accepted z-plane (3 x 16384 x 32767 each,
+    3.2e9 points together) ahead of two small ones, so the small grids start
+    beyond 2^31 elements (2^33 bytes) into the batch buffers: after 20 steps
+    each small grid equals a single-grid context bit for bit."""
+    big = (3, 16384, 32767)
+    cases = [dict(shape=big, hkl=(1, 0, 0), lam=4.0, mu=0.02, off=0.3),
+             dict(shape=big, hkl=(0, 1, 0), lam=4.0, mu=-0.02, off=0.6),
+             dict(shape=(40, 36, 52), hkl=(0, 0, 1), lam=3.0, mu=0.03, off=0.2),
+             dict(shape=(33, 17, 40), hkl=(0, 0, 1), lam=2.5, mu=-0.04, off=0.7)]
+    steps = 20
+    with S.SpfmBatch([c["shape"] for c in cases], lam=[c["lam"] for c in cases],
+                     mu=[c["mu"] for c in cases], stencil=26, kernel="tiled") as b:
+        b.init_planar([c["hkl"] for c in cases], [c["off"] for c in cases])
+        b.step(steps)
+        got = {i: b.get_field(i) for i in (2, 3)}
+    for i in (2, 3):
+        c = cases[i]
+        print(f"batch beyond 2^31 elements: instance {i} {c}", flush=True)
+        with S.Spfm(c["shape"], lam=c["lam"], mu=c["mu"], stencil=26, dtype="f32",
+                    kernel="tiled") as s:
+            s.init_planar(c["hkl"], c["off"])
+            s.step(steps)
+            assert np.array_equal(got[i], s.get_field()), i
