@@ -145,3 +145,34 @@ def test_grains512_reductions_full_field_and_crop(S):
     assert 0.0 < s1 < g.size and s2 > 0.0
     assert abs(dc["sum_phi"] - s1) <= 1e-15 * s1
     assert abs(dc["sum_x"] - s2) <= 1e-15 * s2
+
+
+def test_reductions_beyond_2_31_points(S):
+    """The FP64 compensated reductions over 2.7e9 points (5 planes of the
+    largest FP32 z-plane): the sum of phi agrees with an accurate host sum of
+    the downloaded field, and min and max are exact."""
+    import math
+    shape = (5, 16384, 32767)
+    with S.Spfm(shape, lam=4.0, mu=0.0, stencil=26, dtype="f32", kernel="tiled", dt=0.1) as s:
+        s.init_spheres([(32740.0, 16360.0, 1.0), (16000.0, 8000.0, 1.0), (900.0, 300.0, 0.0)],
+                       [300.0, 2500.0, 700.0])
+        s.step(2)
+        d = s.diagnostics()
+        phi = s.get_field()
+    # float32 values are exact in float64; numpy sums each 2^12-element chunk
+    # pairwise (error below 12 ulps of the chunk's sum for these nonnegative
+    # values) and fsum adds the chunk sums exactly rounded, so the reference is
+    # within 1.4e-15 of the exact sum, relative
+    flat = phi.reshape(-1)
+    n = flat.size
+    assert n > 2 ** 31
+    parts = []
+    for i in range(0, n, 1 << 26):
+        ch = flat[i:i + (1 << 26)].astype(np.float64)
+        m = ch.size - ch.size % 4096
+        parts.extend(ch[:m].reshape(-1, 4096).sum(axis=1).tolist())
+        parts.extend(ch[m:].tolist())
+    exact = math.fsum(parts)
+    print(f"reductions over {n} points: device {d['sum_phi']!r} exact {exact!r}", flush=True)
+    assert d["sum_phi"] == pytest.approx(exact, rel=2e-15)
+    assert d["phi_min"] == float(flat.min()) and d["phi_max"] == float(flat.max())
