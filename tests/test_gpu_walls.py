@@ -104,6 +104,19 @@ def test_walls_on_small_grids(S, shape, walls):
             assert err <= tol, (dtype, kernel, err)
 
 
+@pytest.mark.parametrize("shape,walls,n", [((65533, 3, 3), 4, (0.0, 0.0, 1.0)),
+                                           ((3, 262138, 3), 2, (0.0, 1.0, 0.0))])
+def test_walled_axes_at_their_maximum_length(S, shape, walls, n):
+    """A walled axis whose two ghost layers make the stored length the
+    largest accepted (nz = 65535, ny = 262140); the front varies along it."""
+    phi0 = np.clip(oracle.front(shape, n, 0.0, lam=3.0) * 0.9 + 0.05, 0, 1)
+    sa = oracle.front_sin_alpha((0.8, -0.5, 0.3))
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        for kernel in ("plain", "tiled"):
+            err = run_pair(S, phi0, 5, walls=walls, sa=sa, dtype=dtype, kernel=kernel, lam=3.0)
+            assert err <= tol, (dtype, kernel, err)
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 2e-6)])
 def test_walled_front_stays_put_for_ti_along_its_normal(S, dtype, tol):
     """TI with u = n at mu = 0 keeps the ideal tilted front (Sec. 2.2), walls included."""
