@@ -79,7 +79,7 @@ def grain_shape(d, lam):
     """Size and isotropy of the shrinking grain after the timed steps: the
     volume-equivalent radius R_V of the ideal profile's phase volume (the
     sphere of radius R holds (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) of phi),
-    the phi = 1/2 contour statistics of Sec. 3.4 (mean, extreme radii and
+    the phi = 1/2 contour statistics of Sec. 3.3 (mean, extreme radii and
     eps_eff = (R_max - R_min) / (2 R_mean)), and, when given, the same from the
     radii along the configuration's seeded rays."""
     import math
@@ -239,7 +239,7 @@ def mu_sweep_leg(spfm, torch, inputs, warm=20, steps=120, f64_every=3):
 
 
 def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
-    """The orientation study of the paper's Sec. 3.3 on its 120 x 10 x 10 grid:
+    """The orientation study of the paper's Sec. 3.2 on its 120 x 10 x 10 grid:
     planar fronts rotated about [001] (0, 15, 30, 45 degrees) and [011] (15, 30,
     45 degrees) between contact-angle walls (Eq. 7) that hold their
     orientation, 26 neighbours, lambda = 4 dx, mu = mu0 cos(theta), dt = 0.05,
@@ -289,7 +289,7 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
 
 
 def models_leg(spfm, torch, warm=2000, steps=4000):
-    """The 1D model comparison of the paper's Fig. 6 as batched [100] slabs
+    """The 1D model comparison of the paper's Fig. 7 as batched [100] slabs
     (3 x 3 x 256 periodic, two interfaces 128 dx apart, 6 neighbours, dt = 0.05,
     FP32): for each model one launch per step steps the slabs of every
     lambda~ in {4, 3, 2.5} and mu~ in {0.005, 0.01, 0.02, 0.05}.  Reports the
@@ -488,7 +488,7 @@ def main():
         # the continuum-field control at the paper's mu0: friction makes it orientation dependent
         out["orientation120_walls_cf"] = walls_leg(spfm, torch, coupling="cf", mu0=0.1)
     if args.only in ("", "models"):
-        out["fig6_models"] = models_leg(spfm, torch)
+        out["fig7_models"] = models_leg(spfm, torch)
     if args.only in ("", "cube"):
         out["fig9_cube60"] = cube_leg(spfm, torch)
     if args.only in ("", "friction"):

@@ -17,7 +17,7 @@
  * (TI_n model, Tab. 2); the continuum-field model (CF, potential
  * 8 phi^2 (1-phi)^2 / 3 per direction) is available as a control.
  * Time integration is forward Euler; the grid is periodic on every axis that
- * has no walls.  Walls (Sec. 2.4) hold a contact angle by Eq. 7: one ghost
+ * has no walls.  Walls (Sec. 2.2) hold a contact angle by Eq. 7: one ghost
  * layer beyond each walled end takes, before every step, the value of its
  * inward neighbour moved along the ideal profile by dx sin(alpha).
  *
@@ -121,7 +121,7 @@ typedef struct {
                            2 = h_Abel = phi^2 / (phi^2 + (1 - phi)^2); 1 and 2 only with
                            coupling CF (the comparisons of Sec. 3.1), else SPFM_E_INVAL */
     int32_t conserve_volume; /* nonzero: the homogeneous driving force is chosen at every step so
-                           that sum phi stays constant (Sec. 3.4; mu at create only sets the
+                           that sum phi stays constant (Sec. 3.3; mu at create only sets the
                            stability check); periodic grids, tsteps <= 1, not in batches */
     const double *batch_wall_sin; /* batches with walls: 6 values per grid, wall_sin of grid i at
                            6 i (read at spfm_batch_create only); NULL = wall_sin for every grid.
@@ -159,7 +159,7 @@ typedef struct {
     int32_t conserve_volume;
 } spfm_info;
 
-/* Shape of a particle from its phi = 1/2 contour (Sec. 3.4, Eq. 8-10 at
+/* Shape of a particle from its phi = 1/2 contour (Sec. 3.3, Eq. 8-10 at
  * l = 1/2): contour points on the grid edges, distances from the barycentre
  * sum phi x / sum phi, eps_eff = (R_max - R_min) / (2 R_mean).  Lengths in
  * units of dx * (grid index); one particle not crossing the periodic box
@@ -238,7 +238,7 @@ spfm_status spfm_contour_stats(spfm_ctx *ctx, spfm_contour *out);
  * SPFM_E_STATE for walled grids. */
 spfm_status spfm_energy(spfm_ctx *ctx, int with_mu, double *out);
 /* Radii of a particle's phi = 1/2 surface along n rays from centre, the
- * isotropy of its shape (Sec. 3.4) sampled along seeded directions: psi =
+ * isotropy of its shape (Sec. 3.3) sampled along seeded directions: psi =
  * ln((1-phi)/phi) of the field with phi clamped to [1e-12, 1 - 1e-12] (the
  * inverse of Eq. 3 up to the factor lambda/4, which does not move its zero),
  * trilinear between grid points of the periodic box, marched in steps of dx/4
@@ -252,17 +252,29 @@ spfm_status spfm_energy(spfm_ctx *ctx, int with_mu, double *out);
 spfm_status spfm_ray_radii(spfm_ctx *ctx, const double centre[3], int32_t n, const double *dirs,
                            double *radii);
 
-/* Change the driving force (re-checks the stability bound). */
+/* Change the homogeneous driving force mu of the mu h(phi) term of Eq. 1
+ * (Sec. 2.1; it enters the step of Eq. 2 as -2 M mu h'(phi) / (3 lambda Gamma)).
+ * Re-checks the explicit stability bound (SPFM_E_UNSTABLE, mu unchanged) and
+ * waits for the context stream first: steps already enqueued finish with the
+ * old mu, later ones use the new one. */
 spfm_status spfm_set_mu(spfm_ctx *ctx, double mu);
-/* Enqueue n >= 0 forward-Euler steps (Eq. 2) on the context stream. */
+/* Enqueue n >= 0 forward-Euler steps of Eq. 2 (the functional derivative of
+ * Eq. 1 with the potential of Eq. 6, Sec. 2.1) on the context stream. */
 spfm_status spfm_step(spfm_ctx *ctx, int64_t n);
-/* FP64 compensated reductions of the current field (synchronises). */
+/* FP64 compensated reductions of the current field (synchronises): the phase
+ * volume dx^3 sum phi and the interface measures of the spfm_diag fields.
+ * The paper defines no area or position for these set-ups; the area is
+ * (4/lambda) dx^3 sum phi(1-phi), which the ideal profile of Eq. 3 gives
+ * exactly per unit interface area, and the position is the volume change over
+ * that area (slabs, fronts) or the radius whose ideal radial profile holds the
+ * volume (one sphere), both exact for Eq. 3 profiles (the interface position
+ * of Sec. 2.3 as a volume measure; Fig. 1b tracks the same position). */
 spfm_status spfm_diagnostics(spfm_ctx *ctx, spfm_diag *out);
 spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
 
-/* Many independent grids of different sizes stepped together: one kernel
- * launch per step covers every tile of every grid, and spfm_batch_step
- * captures the launches of n steps in one HIP graph.  Arrays have n entries.
+/* Many independent grids of different sizes stepped together (the problem of
+ * Sec. 2.1 for each): one kernel launch per step covers every tile of every
+ * grid.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
  * eps, tau, allow_unstable, walls, zchunk) apply to every grid.  zchunk 0
  * with kernel TILED: 32 planes, halved down to 4 while the batch gives fewer
@@ -289,7 +301,14 @@ spfm_status spfm_batch_init_front(spfm_batch *b, const double *n /* 3n */,
                                   const double *offset /* n */);
 spfm_status spfm_batch_set_field(spfm_batch *b, int32_t i, const void *src, int src_on_device);
 spfm_status spfm_batch_get_field(spfm_batch *b, int32_t i, void *dst, int dst_on_device);
+/* Enqueue n >= 0 forward-Euler steps of Eq. 2 (Sec. 2.1) of every grid of
+ * the batch, each with its own coefficients: one launch per step covering all
+ * grids, issued as replays of captured HIP graphs of 16 launches for long
+ * runs.  The same sweeps of Sec. 3.1-3.2 (driving forces, orientations) that
+ * the paper runs one grid at a time. */
 spfm_status spfm_batch_step(spfm_batch *b, int64_t n);
+/* spfm_diagnostics for every grid of the batch (out: n entries; the FP64
+ * compensated sums and interface measures of each grid's interior). */
 spfm_status spfm_batch_diagnostics(spfm_batch *b, spfm_diag *out /* n entries */);
 /* Total points over all grids. */
 int64_t spfm_batch_points(const spfm_batch *b);

@@ -257,7 +257,7 @@ def num_threads() -> int:
 
 
 # ---------------------------------------------------------------------------
-# Walls with a contact angle (Sec. 2.4, Eq. 7).  A walled axis d (bit d of
+# Walls with a contact angle (Sec. 2.2, Eq. 7).  A walled axis d (bit d of
 # `walls`) has one ghost layer at each end; sin_alpha[2d] and [2d+1] belong to
 # the low and high face of axis d and are n . e of the front normal n the wall
 # imposes, e the outward normal of the face.
@@ -275,7 +275,7 @@ def interp_prime(which, phi: float) -> float:
 
 def step_constant_volume(p: Params, phi: np.ndarray, nsteps: int):
     """nsteps forward-Euler steps with the driving force chosen at every step so
-    that sum phi stays constant (Sec. 3.4).  Returns (phi, mu per step)."""
+    that sum phi stays constant (Sec. 3.3).  Returns (phi, mu per step)."""
     _check(p, phi)
     out = phi.copy()
     mu = np.empty(int(nsteps))
@@ -304,7 +304,7 @@ def contour_points(p: Params, phi: np.ndarray) -> np.ndarray:
 
 
 def sphericity(p: Params, phi: np.ndarray):
-    """Residual anisotropy of a particle (Sec. 3.4): barycentre c = sum phi x / sum phi,
+    """Residual anisotropy of a particle (Sec. 3.3): barycentre c = sum phi x / sum phi,
     R_i = |contour point - c|, eps_eff = (R_max - R_min) / (2 R_mean).
     Returns (eps_eff, R_mean, R_min, R_max, c, number of points)."""
     nz, ny, nx = phi.shape
@@ -322,7 +322,7 @@ def ray_radii(phi: np.ndarray, centre, rays, *, dx: float = 1.0, eps: float = 1e
               step: float = 0.25, bisections: int = 44) -> np.ndarray:
     """Radii of a particle's phi = 1/2 surface along seeded rays from `centre`
     (the isotropy measure along rays of the 256^3 grain configuration; the
-    particle shape of Sec. 3.4 sampled along directions).  psi = ln((1-phi)/phi)
+    particle shape of Sec. 3.3 sampled along directions).  psi = ln((1-phi)/phi)
     (the inverse of Eq. 3 up to the factor lambda/4, which does not move its
     zero), phi clamped to [eps, 1-eps], is interpolated trilinearly between grid
     points of the periodic box.  Each ray is marched in steps of `step` grid

@@ -486,7 +486,7 @@ void orc_spheres_at(int nx, int ny, int nz, double dx, double lambda, int n,
     }
 }
 
-/* ---- Walls with a contact angle (Sec. 2.4, Eq. 7) ----
+/* ---- Walls with a contact angle (Sec. 2.2, Eq. 7) ----
  * A walled axis carries one ghost layer at each end: the padded field has
  * nx + 2 (ny + 2, nz + 2) points along a walled axis, interior index i at
  * padded index i + 1.  Eq. 7 sets a ghost point b from its inward neighbour
@@ -558,7 +558,7 @@ void orc_init_front(int nx, int ny, int nz, double dx, double lambda, const doub
             }
 }
 
-/* ---- Constant particle volume (Sec. 3.4) ----
+/* ---- Constant particle volume (Sec. 3.3) ----
  * The rate of Eq. 2 is affine in the homogeneous driving force:
  * rate_p(mu) = rate_p(0) - beta mu h'(phi_p), beta = 2M / (3 lambda Gamma).
  * Reading: the paper imposes mu(t) "such that the integral volume neither
@@ -606,7 +606,7 @@ void orc_init_box(int nx, int ny, int nz, double dx, double lambda, const double
             }
 }
 
-/* phi = 1/2 contour points (Sec. 2.5, Eq. 8-10 at l = 1/2): on every grid edge
+/* phi = 1/2 contour points (Sec. 2.3, Eq. 8-10 at l = 1/2): on every grid edge
  * (p, p + e_d) of a periodic field whose end values bracket 1/2, the point
  * p + t e_d with t the zero of the linear interpolation of
  * psi = (lambda/4) ln((1 - phi)/phi) (R18).  Fills up to maxpts points

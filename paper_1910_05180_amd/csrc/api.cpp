@@ -409,6 +409,8 @@ struct spfm_ctx {
                    : launch_cv_correct<float>((const float*)in, (float*)out, points(), r.p.interp,
                                               dt_beta, d_part(), d_state(), stream);
     }
+    // New step coefficients from r; drops the cached graphs, so no replay may
+    // still be queued (callers synchronise the stream first).
     void refresh_coef() {
         kf = make_coef<float>(r.p);
         kd = make_coef<double>(r.p);
@@ -1064,6 +1066,9 @@ spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
                                  p.C_Gamma, p.interp);
     if (!c->r.allow_unstable && p.dt > dtm)
         return fail(SPFM_E_UNSTABLE, "dt = %g exceeds the explicit stability bound %g", p.dt, dtm);
+    // Enqueued steps (and replays of the cached graphs, which hold the old
+    // coefficients) finish first: the graphs are destroyed below.
+    HIP_TRY(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     c->r.p = p;
     c->r.dt_max = dtm;
     c->refresh_coef();

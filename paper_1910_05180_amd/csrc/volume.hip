@@ -1,4 +1,4 @@
-// Constant particle volume (Sec. 3.4) and the phi = 1/2 contour statistics
+// Constant particle volume (Sec. 3.3) and the phi = 1/2 contour statistics
 // that measure the residual anisotropy of a relaxed particle.
 //
 // Constant volume.  The rate of Eq. 2 is affine in the homogeneous driving

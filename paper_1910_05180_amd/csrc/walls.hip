@@ -1,4 +1,4 @@
-// Contact-angle walls (Sec. 2.4, Eq. 7) and the interior <-> padded copies.
+// Contact-angle walls (Sec. 2.2, Eq. 7) and the interior <-> padded copies.
 // (The tiled step kernels compute the ghosts they need as they stage them; the
 // fill below serves the plain kernel.)
 //

@@ -1,5 +1,5 @@
 """GPU parity of the CF models with the interpolation functions h5 and h_Abel
-(Tab. 2), and the model comparison of Fig. 6 on the device."""
+(Tab. 2), and the model comparison of Fig. 7 on the device."""
 import numpy as np
 import pytest
 
@@ -109,8 +109,8 @@ def slab_velocities(S, coupling, interp, lams, mu, *, n=64, dt=0.05, warm=4000, 
 
 
 @pytest.mark.parametrize("interp", ["h3", "h5", "habel"])
-def test_fig6_cf_pins_at_low_resolution_and_drags_at_lambda_4(S, interp):
-    """Fig. 6 on the device: CF is pinned at lambda~ = 2.5 (mu~ = 0.01) and about
+def test_fig7_cf_pins_at_low_resolution_and_drags_at_lambda_4(S, interp):
+    """Fig. 7 on the device: CF is pinned at lambda~ = 2.5 (mu~ = 0.01) and about
     2e-2 slow at lambda~ = 4, in FP32 as in the FP64 oracle."""
     v = slab_velocities(S, "cf", interp, (2.5, 4.0), 0.01)
     print(f"CF+{interp}: v(2.5) = {v[0]:.3e}, err(4) = {v[1] / -0.01 - 1:+.3e}", flush=True)
@@ -118,7 +118,7 @@ def test_fig6_cf_pins_at_low_resolution_and_drags_at_lambda_4(S, interp):
     assert -4e-2 < v[1] / -0.01 - 1.0 < -1e-2
 
 
-def test_fig6_ti_moves_where_cf_pins(S):
+def test_fig7_ti_moves_where_cf_pins(S):
     v = slab_velocities(S, "local", "h3", (2.5, 4.0), 0.01)
     print(f"TI_n: err(2.5) = {v[0] / -0.01 - 1:+.3e}, err(4) = {v[1] / -0.01 - 1:+.3e}", flush=True)
     for x in v:

@@ -1,4 +1,4 @@
-"""GPU parity of the constant-volume stepping (Sec. 3.4), the box particle and
+"""GPU parity of the constant-volume stepping (Sec. 3.3), the box particle and
 the phi = 1/2 contour statistics against the oracle, and the cube relaxation
 study of Fig. 9 on the device."""
 import math

@@ -1,5 +1,5 @@
-"""GPU parity of the contact-angle walls (Sec. 2.4, Eq. 7) against the oracle,
-and the kinetics of the paper's orientation study (Sec. 3.3) on the device.
+"""GPU parity of the contact-angle walls (Sec. 2.2, Eq. 7) against the oracle,
+and the kinetics of the paper's orientation study (Sec. 3.2) on the device.
 
 The oracle fills the ghost layers wall after wall (Eq. 7 as printed); the
 library applies the composed shift of a ghost's walls at once.  The two agree
@@ -164,7 +164,7 @@ def test_init_front_needs_walls_where_the_front_varies(S):
 
 def front_velocity(S, n, *, dtype, mu0=0.05, lam=4.0, shape=(10, 10, 120), dt=0.05, warm=400,
                    steps=1600):
-    """x-velocity of a walled planar front driven by mu = mu0 n_x (Sec. 3.3)."""
+    """x-velocity of a walled planar front driven by mu = mu0 n_x (Sec. 3.2)."""
     import torch
     nv = np.asarray(n) / np.linalg.norm(n)
     st = torch.cuda.Stream()

@@ -1,5 +1,5 @@
 """Pins of the interpolation functions of Tab. 2 (h3, h5, h_Abel) in the oracle,
-and of the model comparison of Sec. 3.1 / Fig. 6 that they enter."""
+and of the model comparison of Sec. 3.1 / Fig. 7 that they enter."""
 import math
 
 import numpy as np
@@ -93,7 +93,7 @@ def slab_velocity(coupling, interp, lam, mu, dt=0.05, n=64, warm=4000, steps=800
 
 @pytest.mark.parametrize("interp", INTERPS)
 def test_cf_models_pin_at_low_resolution(interp):
-    """Fig. 6: every CF model is pinned at lambda~ = 2.5 for mu~ < 0.02."""
+    """Fig. 7: every CF model is pinned at lambda~ = 2.5 for mu~ < 0.02."""
     assert abs(slab_velocity("cf", interp, 2.5, 0.01)) < 1e-7
 
 
@@ -104,7 +104,7 @@ def test_ti_moves_where_cf_pins():
 
 @pytest.mark.parametrize("interp", INTERPS)
 def test_cf_friction_at_lambda_4(interp):
-    """Fig. 6: at lambda~ = 4 the CF models run with a nearly constant relative
+    """Fig. 7: at lambda~ = 4 the CF models run with a nearly constant relative
     velocity error of about 2e-2 at small driving forces (grid friction)."""
     err = slab_velocity("cf", interp, 4.0, 0.01) / -0.01 - 1.0
     assert -4e-2 < err < -1e-2

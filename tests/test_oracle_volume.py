@@ -1,5 +1,5 @@
 """Pins of the oracle's constant-volume stepping, box particle and contour
-statistics (Sec. 3.4), against facts that do not come from the oracle:
+statistics (Sec. 3.3), against facts that do not come from the oracle:
 exact volume conservation, the Gibbs-Thomson equilibrium of a sphere
 (mu = -Gamma kappa, kappa = 2/R, the sharp-interface limit of Eq. 2 whose
 planar form v = -M mu / Gamma is Sec. 2.1), linearity of psi on an ideal

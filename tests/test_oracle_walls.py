@@ -1,4 +1,4 @@
-"""Pins of the oracle's contact-angle walls (Sec. 2.4, Eq. 7) against facts
+"""Pins of the oracle's contact-angle walls (Sec. 2.2, Eq. 7) against facts
 that do not come from the oracle: the tanh addition law, the analytic tilted
 front of Eq. 3, the stationarity of a translationally invariant model on its
 ideal profile, and the kinetics v_n = -M mu / Gamma of Sec. 2.1."""
@@ -88,7 +88,7 @@ def test_cf_front_is_not_stationary():
 
 @pytest.mark.parametrize("axis,theta", [("001", 0.45), ("011", 0.6)])
 def test_tilted_front_moves_at_the_kinetic_velocity(axis, theta):
-    """Sec. 3.3 set-up on a small box: with mu = mu0 cos(theta) the front's
+    """Sec. 3.2 set-up on a small box: with mu = mu0 cos(theta) the front's
     x-velocity is -M mu0 / Gamma for every orientation (TI_n, 26 neighbours)."""
     n = rot001(theta) if axis == "001" else rot011(theta)
     shape, lam, mu0, dt = (6, 6, 24), 4.0, 0.05, 0.05
