@@ -23,32 +23,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ALG_BYTES_F32 = 8              # read phi^n + write phi^{n+1} per point per step
 ALG_BYTES_F64 = 16
-# FP32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# lane-operations per second (one FP32 add, mul, fma, compare, select or
-# transcendental per lane per cycle).
+# FP32 VALU issue peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz lane-operations per second (one FP32 add, mul, fma, compare, select
+# or transcendental per lane per cycle).  A secondary figure: the step is
+# priced against the HBM roof, as the metric asks.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic FP32 operations per point update of the TI_n 26-neighbour step on
-# the grain workload, counted from the per-point formulas the kernel evaluates:
-# 28 where phi(1-phi) = 0 (psi' 6, plane sums 6, shell sums 8, update 7, test 1),
-# 64 in the tail branch (plus the normal 9, the exponentials and c_i 15, the
-# tail sums 9, u and its term 2, test 1) and 157 with the full coupling (93
-# more: 2 sinh 6, x-scaled terms 4, the shell-2 and shell-3 y_k 40, three running
-# fractions 39, their sum 3, select 1).  The point mix over the timed steps
-# (2050 to 3050 of the run) is 13.1% / 79.8% / 7.1%.
-ALG_OPS_LOCAL26 = 0.131 * 28 + 0.798 * 64 + 0.071 * 157
+# Algorithmic FP32 operations per point update of the TI_n 26-neighbour step,
+# counted from the per-point formulas the kernel evaluates, by the class of the
+# point: 28 where phi(1-phi) = 0 (psi' 6, plane sums 6, shell sums 8, update 7,
+# test 1), 64 in the tail branch (plus the normal 9, the exponentials and c_i
+# 15, the tail sums 9, u and its term 2, test 1) and 157 with the full coupling
+# (93 more: 2 sinh 6, x-scaled terms 4, the shell-2 and shell-3 y_k 40, three
+# running fractions 39, their sum 3, select 1).  The mix is measured on the
+# field at the start and the end of the timed window.
+OPS_BULK, OPS_TAIL, OPS_FULL = 28, 64, 157
 ZCHUNK = 32                    # leading planes per block (the fastest in sweeps of 16..64)
-# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by the factors the same counters give for the copy
-# reference; None whenever the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_LOCAL26 = (44131.4 * 2.0 + 65536.0) * 1024
+REPEATS = 5                    # timed windows of the headline; the median is reported
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=2000,
-                    help="untimed steps first (the clocks settle over the first few hundred)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed steps of the measured field before each timed window (the "
+                         "clocks are warmed on a scratch context of the same workload)")
+    ap.add_argument("--repeats", type=int, default=REPEATS,
+                    help="timed windows of the headline (field re-initialised each time); median")
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -59,9 +60,14 @@ def parse():
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
                     help="coupling of the timed legs (the headline is local, TI_n)")
+    ap.add_argument("--no-traffic", action="store_true",
+                    help="skip the two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) that measure "
+                         "the headline kernel's HBM bytes per launch")
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain copy of 2^26 floats (256 MiB read + 256 MiB written), "
                          "the reference that scales hardware byte counters")
+    ap.add_argument("--traffic-child", action="store_true",
+                    help="internal: the headline kernel alone, once, for a counter pass")
     return ap.parse_args()
 
 
@@ -97,6 +103,240 @@ def grain_shape(d, lam):
                     "ray_R_min": float(min(rr)), "ray_R_max": float(max(rr)),
                     "ray_eps": float((max(rr) - min(rr)) / (2.0 * sum(rr) / len(rr)))})
     return out
+
+
+def xtail_local(lam, dx=1.0, stencil=26):
+    """The FP32 step's tail threshold for TI_n: below x = phi(1-phi) = 2^-24 / m_max
+    every y_k = m_k x is under one ulp of 1 (m_max = 2 cosh(4 dx sqrt(j) / lambda)
+    - 2 over the stencil's shells j <= 1, 2, 3), and the step takes the closed-form
+    tail branch; at or above it the full coupling."""
+    import math
+    import numpy as np
+    nsh = {6: 1, 18: 2, 26: 3}[stencil]
+    h = math.sinh(2.0 * dx * math.sqrt(nsh) / lam)
+    return float(np.float32(2.0 ** -24 / (4.0 * h * h)))
+
+
+def point_mix(phi, xtail):
+    """Fractions of points in the step's three branches, from an FP32 field (numpy
+    or torch): x = phi (1 - phi) rounded as the kernel rounds it; bulk where
+    x == 0, full coupling where |x| >= xtail, the tail branch elsewhere."""
+    try:
+        import torch
+        is_t = isinstance(phi, torch.Tensor)
+    except Exception:  # pragma: no cover - torch is part of the image
+        is_t = False
+    if is_t:
+        x = phi * (1.0 - phi)
+        n = x.numel()
+        bulk = int((x == 0).sum().item())
+        full = int((x.abs() >= xtail).sum().item())
+    else:
+        import numpy as np
+        p = np.asarray(phi, dtype=np.float32)
+        x = p * (np.float32(1.0) - p)
+        n = x.size
+        bulk = int(np.count_nonzero(x == 0))
+        full = int(np.count_nonzero(np.abs(x) >= np.float32(xtail)))
+    return {"bulk": bulk / n, "tail": (n - bulk - full) / n, "full": full / n}
+
+
+def ops_per_point(mix):
+    """Algorithmic FP32 operations per point update for a branch mix."""
+    return OPS_BULK * mix["bulk"] + OPS_TAIL * mix["tail"] + OPS_FULL * mix["full"]
+
+
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def host_cpu():
+    """Model name and usable cores of the host, from /proc/cpuinfo and the
+    process's CPU affinity."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 0
+    return {"cpu_model": model, "host_cores": usable, "host_cpus_total": os.cpu_count() or 0}
+
+
+def warm_clocks(torch, stream, step, chunk=200, min_s=1.0, max_s=4.0, tol=0.01):
+    """Run step(chunk) repeatedly until at least min_s seconds have passed and two
+    consecutive chunks took the same time within tol (at most max_s seconds): the
+    GPU's clocks ramp up over the first fraction of a second of sustained work.
+    Returns (seconds, steps, microseconds per step of the last chunk)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0, n, last = time.perf_counter(), 0, None
+    while True:
+        e0.record(stream)
+        step(chunk)
+        e1.record(stream)
+        e1.synchronize()
+        n += chunk
+        ms = e0.elapsed_time(e1)
+        el = time.perf_counter() - t0
+        if el >= max_s or (el >= min_s and last is not None and abs(ms - last) <= tol * last):
+            return el, n, ms * 1e3 / chunk
+        last = ms
+
+
+def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", zchunk=ZCHUNK,
+                 rewarm_steps=300):
+    """The FP32 tiled step on the grain workload.  The clocks are first brought
+    to their steady state on a scratch context of the same workload (its steps
+    are not measured, see warm_clocks); then `repeats` times: the measured field
+    is initialised (R = 60), stepped `warmup` times untimed, and exactly `steps`
+    steps are timed, bracketed by stream synchronisation (wall clock) and by HIP
+    events on the kernel's stream.  The scratch context steps `rewarm_steps`
+    more before each window so that the GPU never idles between them.  The
+    branch mix of the step is counted on the field at both ends of every
+    window."""
+    stream = torch.cuda.Stream()
+    xt = xtail_local(w.lam, w.dx, w.stencil)
+    reps = []
+    with torch.cuda.stream(stream):
+        kw = dict(lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil, dtype="f32",
+                  coupling=coupling, kernel="tiled", dt=w.dt, zchunk=zchunk, stream=stream)
+        scratch = spfm.Spfm(w.shape, **kw)
+        scratch.init_spheres(w.centers, w.radii)
+        warm = warm_clocks(torch, stream, scratch.step)
+        s = spfm.Spfm(w.shape, **kw)
+        bufs = {b.data_ptr(): b for b in s._buffers}
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for _ in range(repeats):
+            scratch.step(rewarm_steps)
+            s.init_spheres(w.centers, w.radii)
+            s.step(warmup)
+            d0 = s.diagnostics()           # synchronises the stream
+            m0 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            d1 = s.diagnostics()
+            m1 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
+            reps.append({"wall": wall, "ev_ms": e0.elapsed_time(e1), "R0": d0["interface_position"],
+                         "R1": d1["interface_position"], "mix": (m0, m1)})
+        d = s.diagnostics()
+        d["zchunk"] = s.info()["zchunk"]
+        d["warm"] = {"seconds": warm[0], "steps": warm[1], "us_per_step_last": warm[2]}
+        d["contour"] = s.contour_stats()
+        if w.rays is not None:
+            d["rays"] = s.ray_radii(w.rays, centre=d["contour"]["centre"])
+        s.close()
+        scratch.close()
+    return reps, d
+
+
+def parse_counter_csv(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 counter-collection CSV:
+    a list of (dispatch id, kernel name, value) in dispatch order."""
+    import csv
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            did = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or len(rows))
+            rows.append((did, r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    rows.sort(key=lambda t: t[0])
+    return rows
+
+
+def traffic_from_counters(fetch_rows, write_rows, steps, copy_bytes, kernel_tag="k_step_tiled",
+                          copy_tag="MulFunctor"):
+    """HBM bytes per launch of the step kernel: the mean FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) of its last `steps` dispatches, each scaled by what the
+    same counter reads for the plain copy kernel of known size (copy_bytes read
+    and copy_bytes written per dispatch).  None when a kernel is missing."""
+    def mean_last(rows, tag, k):
+        v = [x for _, name, x in rows if tag in name]
+        return sum(v[-k:]) / len(v[-k:]) if v else None
+    f_step, w_step = mean_last(fetch_rows, kernel_tag, steps), mean_last(write_rows, kernel_tag, steps)
+    f_copy, w_copy = mean_last(fetch_rows, copy_tag, 3), mean_last(write_rows, copy_tag, 3)
+    if None in (f_step, w_step, f_copy, w_copy) or f_copy <= 0 or w_copy <= 0:
+        return None
+    kib = copy_bytes / 1024.0
+    fs, ws = kib / f_copy, kib / w_copy
+    return {"bytes": (f_step * fs + w_step * ws) * 1024.0, "fetch_kib": f_step, "write_kib": w_step,
+            "fetch_scale": fs, "write_scale": ws}
+
+
+def measure_traffic(args):
+    """Two rocprofv3 counter passes over a child run of the headline kernel (the
+    same window: --warmup untimed steps, then --steps), FETCH_SIZE then WRITE_SIZE,
+    with the copy reference in the same process.  Run before this process touches
+    the GPU; returns None (with the reason on stderr) if anything fails."""
+    import glob
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3")
+    if prof is None:
+        print("traffic: rocprofv3 not found", file=sys.stderr, flush=True)
+        return None
+    env = dict(os.environ, TMPDIR="/tmp")
+    rows = {}
+    tmp = tempfile.mkdtemp(prefix="spfm_traffic_", dir="/tmp")
+    try:
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            out = os.path.join(tmp, counter)
+            cmd = [prof, "--pmc", counter, "--output-format", "csv", "-d", out, "-o", "run", "--",
+                   sys.executable, os.path.abspath(__file__), "--traffic-child", "--steps", str(args.steps),
+                   "--warmup", str(args.warmup), "--coupling", args.coupling]
+            print(f"traffic: {counter} pass", file=sys.stderr, flush=True)
+            r = subprocess.run(cmd, cwd="/tmp", env=env, capture_output=True, text=True, timeout=240)
+            files = glob.glob(os.path.join(out, "**", "*counter_collection.csv"), recursive=True)
+            if r.returncode != 0 and not files:
+                print(f"traffic: {counter} pass failed (rc {r.returncode}): {r.stderr[-400:]}",
+                      file=sys.stderr, flush=True)
+                return None
+            if not files:
+                print(f"traffic: no counter file for {counter}", file=sys.stderr, flush=True)
+                return None
+            rows[counter] = parse_counter_csv(files[0], counter)
+    except (subprocess.TimeoutExpired, OSError, ValueError, KeyError) as e:
+        print(f"traffic: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
+        return None
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return traffic_from_counters(rows["FETCH_SIZE"], rows["WRITE_SIZE"], args.steps, 4 * (1 << 26))
+
+
+def traffic_child(args):
+    """One window of the headline kernel and the copy reference, for a counter pass."""
+    import torch
+
+    from paper_1910_05180_amd import inputs, spfm
+    spfm.load()
+    w = inputs.sphere256(mu=0.0)
+    copy_reference(torch)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = spfm.Spfm(w.shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil,
+                      dtype="f32", coupling=args.coupling, kernel="tiled", dt=w.dt, zchunk=ZCHUNK,
+                      stream=stream)
+        s.init_spheres(w.centers, w.radii)
+        s.step(args.warmup)
+        s.step(args.steps)
+        torch.cuda.synchronize()
+        s.close()
 
 
 def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0,
@@ -398,7 +638,7 @@ def cpu_baseline(w, steps):
     dt = time.perf_counter() - t0
     n = int(np.prod(shape))
     return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
             "sample": f"{steps} FP64 steps of the full {shape[2]}^3 grain workload "
                       f"(26 neighbours, TI_n), {dt:.1f} s wall"}
 
@@ -409,6 +649,13 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.traffic_child:
+        traffic_child(args)
+        return
+    # counter passes first, in child processes, before this process uses the GPU
+    traffic = None
+    if args.only in ("", "f32") and not args.no_traffic:
+        traffic = measure_traffic(args)
     import torch
 
     from paper_1910_05180_amd import inputs, spfm
@@ -422,32 +669,42 @@ def main():
         out["copy_reference"] = copy_reference(torch)
     f32 = f64 = None
     if args.only in ("", "f32"):
-        wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled",
-                                   steps=args.steps, warmup=args.warmup, coupling=args.coupling,
-                                   zchunk=ZCHUNK, contour=True, rays=w.rays)
-        f32 = {"wall": wall, "ev_ms": ev_ms, "diag": d}
+        print("leg: f32 headline", file=sys.stderr, flush=True)
+        reps, d = headline_leg(spfm, torch, w, steps=args.steps, warmup=args.warmup,
+                               repeats=max(1, args.repeats), coupling=args.coupling)
+        f32 = {"reps": reps, "diag": d}
     if args.only in ("", "f64"):
+        print("leg: f64 plain", file=sys.stderr, flush=True)
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",
                                       steps=args.fp64_steps, warmup=min(args.warmup, 5),
                                       coupling=args.coupling)
         f64 = {"wall": wall64, "ev_ms": ev64, "diag": d64}
 
     if f32 is not None:
-        steps = args.steps
-        ms_per_step = f32["wall"] * 1e3 / steps
-        glups = npts * steps / f32["wall"] / 1e9
-        kern_ms = f32["ev_ms"] / steps                  # average step-kernel duration
+        steps, reps = args.steps, f32["reps"]
+        wall = median([r["wall"] for r in reps])
+        kern_ms = median([r["ev_ms"] for r in reps]) / steps     # average step-kernel duration
+        glups = npts * steps / wall / 1e9
         achieved = ALG_BYTES_F32 * npts / (kern_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": traffic["bytes"] if traffic else None}
+        window = {"steps": [args.warmup, args.warmup + steps],
+                  "R_V": [median([r["R0"] for r in reps]), median([r["R1"] for r in reps])],
+                  "repeats": len(reps), "clock_warmup": f32["diag"]["warm"],
+                  "glups_each": [npts * steps / r["wall"] / 1e9 for r in reps],
+                  "kernel_us_each": [r["ev_ms"] * 1e3 / steps for r in reps]}
+        issue = None
         if args.coupling == "local":
-            alu = ALG_OPS_LOCAL26 * npts / (kern_ms * 1e-3) / 1e12
-            roofline = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-                        "frac": alu / VALU_PEAK_TOPS, "traffic": TRAFFIC_BYTES_LOCAL26}
-        else:
-            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+            mixes = [m for r in reps for m in r["mix"]]
+            mix = {k: sum(m[k] for m in mixes) / len(mixes) for k in ("bulk", "tail", "full")}
+            ops = ops_per_point(mix)
+            tops = ops * npts / (kern_ms * 1e-3) / 1e12
+            issue = {"achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                     "frac": tops / VALU_PEAK_TOPS, "ops_per_point": ops, "point_mix": mix}
         out.update({
             "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "grain256: 256^3 periodic grid, one grain R=60 dx at the "
                                    "centre (ideal radial profile), lambda=4 dx, mu=0, "
@@ -458,6 +715,9 @@ def main():
             "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
             "hbm_achieved_gbs": achieved,
             "roofline": roofline,
+            "issue_rate": issue,
+            "traffic_counters": traffic,
+            "window": window,
             "kernel_ms_per_step": kern_ms,
             "phi_range": [f32["diag"]["phi_min"], f32["diag"]["phi_max"]],
             "grain": grain_shape(f32["diag"], w.lam),
@@ -465,35 +725,45 @@ def main():
     if f64 is not None:
         s64 = args.fp64_steps
         g64 = npts * s64 / f64["wall"] / 1e9
+        k64 = f64["ev_ms"] / s64
         out["fp64_plain"] = {"value": g64, "unit": "GLUPS", "steps": s64,
-                             "ms_per_step": f64["wall"] * 1e3 / s64,
-                             "pct_hbm_peak": 100.0 * ALG_BYTES_F64 * npts /
-                             (f64["ev_ms"] / s64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                             "ms_per_step": f64["wall"] * 1e3 / s64, "kernel_ms_per_step": k64,
+                             "pct_hbm_peak": 100.0 * ALG_BYTES_F64 * npts / (k64 * 1e-3) / 1e9
+                             / HBM_PEAK_GBS}
         if f32 is not None:
             out["speedup_vs_fp64_plain"] = out["value"] / g64
     if args.only in ("", "batch"):
+        print("leg: batch64", file=sys.stderr, flush=True)
         out["batch64"] = batch_leg(spfm, torch, inputs, args.side_steps, 10)
     if args.only in ("", "grains"):
+        print("leg: grains512", file=sys.stderr, flush=True)
         out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
     if args.only in ("", "temporal"):
+        print("leg: temporal", file=sys.stderr, flush=True)
         out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
         # CF: the HBM-bound step, where fusing steps pays
         out["grains512_cf"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, coupling="cf")
         out["grains512_cf_temporal3"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=3,
                                                    coupling="cf")
     if args.only in ("", "musweep"):
+        print("leg: mu sweep", file=sys.stderr, flush=True)
         out["mu_sweep128"] = mu_sweep_leg(spfm, torch, inputs)
     if args.only in ("", "walls"):
+        print("leg: walls", file=sys.stderr, flush=True)
         out["orientation120_walls"] = walls_leg(spfm, torch)
         # the continuum-field control at the paper's mu0: friction makes it orientation dependent
         out["orientation120_walls_cf"] = walls_leg(spfm, torch, coupling="cf", mu0=0.1)
     if args.only in ("", "models"):
+        print("leg: models", file=sys.stderr, flush=True)
         out["fig7_models"] = models_leg(spfm, torch)
     if args.only in ("", "cube"):
+        print("leg: cube", file=sys.stderr, flush=True)
         out["fig9_cube60"] = cube_leg(spfm, torch)
     if args.only in ("", "friction"):
+        print("leg: friction", file=sys.stderr, flush=True)
         out["fig3_friction"] = friction_leg(spfm)
     if not args.no_cpu and f32 is not None:
+        print("leg: cpu oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -38,11 +38,58 @@ def test_grain_radius_inverts_the_ideal_phase_volume(radius, lam):
 
 
 def test_roofline_peaks():
-    """VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
+    """VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
     second (39.3 T, a quarter of the 157.3 TFLOP/s that counts an FMA as two
     flops and packed FP32 as two lanes); HBM: 8 TB/s; 8 algorithmic bytes per
     FP32 point and step."""
     assert bench.VALU_PEAK_TOPS == pytest.approx(39.3216)
     assert bench.VALU_PEAK_TOPS * 4 == pytest.approx(157.3, rel=1e-3)
     assert bench.HBM_PEAK_GBS == 8000.0 and bench.ALG_BYTES_F32 == 8
-    assert bench.ALG_OPS_LOCAL26 == pytest.approx(65.9, abs=0.05)
+    assert bench.ops_per_point({"bulk": 0.131, "tail": 0.798, "full": 0.071}) == pytest.approx(65.9, abs=0.05)
+
+
+def test_tail_threshold_and_point_mix():
+    """The tail threshold 2^-24 / (2 cosh(4 sqrt(3) / lambda) - 2) for 26 neighbours,
+    and the branch classes of an ideal planar profile: bulk where phi(1-phi)
+    rounds to 0 in FP32, full coupling within the band where it exceeds the
+    threshold, the tail elsewhere."""
+    import numpy as np
+    lam = 4.0
+    xt = bench.xtail_local(lam)
+    assert xt == pytest.approx(2.0 ** -24 / (2.0 * math.cosh(4.0 * math.sqrt(3.0) / lam) - 2.0), rel=1e-7)
+    s = np.arange(-200, 200) + 0.25
+    phi = (0.5 * (1.0 - np.tanh(2.0 * s / lam))).astype(np.float32)
+    mix = bench.point_mix(phi, xt)
+    assert sum(mix.values()) == pytest.approx(1.0)
+    x = phi.astype(np.float64) * (1.0 - phi.astype(np.float64))
+    # the full band: x >= xt, i.e. |s| below about (lambda/4) ln(1/xt)
+    half = lam / 4.0 * math.log(1.0 / xt)
+    assert mix["full"] * s.size == pytest.approx(2 * half, abs=3)
+    assert mix["bulk"] > 0 and mix["tail"] > 0
+    assert np.count_nonzero(x == 0) >= mix["bulk"] * s.size
+
+
+def test_traffic_from_counter_rows(tmp_path):
+    """Per-launch HBM bytes from the rocprofv3 counter CSV: the mean of the step
+    kernel's last dispatches, each counter scaled by the copy reference's reading
+    of a known size."""
+    csv_text = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for i in range(3):
+        csv_text.append(f"{i},\"void at::native::elementwise<MulFunctor<float>>\",FETCH_SIZE,131072.0")
+    for i in range(3, 8):
+        csv_text.append(f"{i},\"void spfm::k_step_tiled<float, 26, 0, false>\",FETCH_SIZE,{40000.0 + i}")
+    p = tmp_path / "run_counter_collection.csv"
+    p.write_text("\n".join(csv_text) + "\n")
+    fetch = bench.parse_counter_csv(str(p), "FETCH_SIZE")
+    assert len(fetch) == 8
+    write = [(i, n, 262144.0 if "Mul" in n else 65536.0) for i, n, _ in fetch]
+    t = bench.traffic_from_counters(fetch, write, steps=2, copy_bytes=4 * (1 << 26))
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    assert t["fetch_kib"] == pytest.approx(40006.5)
+    assert t["bytes"] == pytest.approx((40006.5 * 2.0 + 65536.0) * 1024.0)
+    assert bench.traffic_from_counters(fetch, [], 2, 4 * (1 << 26)) is None
+
+
+def test_median():
+    assert bench.median([3.0, 1.0, 2.0]) == 2.0
+    assert bench.median([4.0, 1.0, 2.0, 3.0]) == 2.5

@@ -135,3 +135,32 @@ def test_cubic_symmetry_on_the_device(S, dtype, tol, op):
             s.step(10)
             out.append(s.get_field().astype(np.float64))
     assert float(np.abs(T(out[0]) - out[1]).max()) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_set_mu_between_graph_replays(S, dtype, tol):
+    """Steps on a non-null stream replay captured graphs of 16 launches; set_mu
+    waits for them, drops the graphs and the next steps use the new driving
+    force.  The oracle runs the same switch (Eq. 2 with mu, then with mu')."""
+    import torch
+    phi0 = slab111(3.0)
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    start = phi0 if dtype == "f64" else as_f32_input(phi0)
+    ref = start
+    for mu in (0.04, -0.06):
+        p = oracle.params(phi0.shape, lam=3.0, mu=mu, dt=0.1, stencil=26, coupling="local", eps=eps)
+        ref = oracle.step(p, ref, 40)
+    stream = torch.cuda.Stream()
+    print(f"case set_mu between graph replays {dtype}", flush=True)
+    with S.Spfm(phi0.shape, lam=3.0, mu=0.04, stencil=26, dtype=dtype, coupling="local", dt=0.1,
+                kernel="tiled", stream=stream, eps=eps, C_Gamma=p.C_Gamma) as s:
+        s.set_field(phi0)
+        s.step(40)          # two graph replays and 8 single launches
+        s.set_mu(-0.06)
+        s.step(40)
+        d = s.diagnostics()
+        got = s.get_field().astype(np.float64)
+    assert d["step"] == 80 and d["mu"] == -0.06
+    err = float(np.abs(got - ref).max())
+    print(f"  max|dphi| = {err:.3e}", flush=True)
+    assert err <= tol
