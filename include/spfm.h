@@ -63,11 +63,22 @@ typedef enum { SPFM_F32 = 0, SPFM_F64 = 1 } spfm_dtype;
 typedef enum { SPFM_LOCAL = 0, SPFM_GLOBAL = 1, SPFM_CF = 2 } spfm_coupling;
 
 /* Kernel choice: PLAIN = one thread per point reading its 27 neighbours from
- * global memory; TILED = LDS-staged tiles marching along z; AUTO = TILED with
- * the z-chunk per block chosen by timing candidates on the current field at
- * the first spfm_step (that call synchronises the stream once).  Results do
- * not depend on the z-chunk. */
-typedef enum { SPFM_KERNEL_AUTO = 0, SPFM_KERNEL_PLAIN = 1, SPFM_KERNEL_TILED = 2 } spfm_kernel;
+ * global memory; TILED = LDS-staged tiles marching along z; RESIDENT = one
+ * workgroup per grid holding the whole stored grid in LDS (two copies: at most
+ * 20480 FP32 or 10240 FP64 stored points) and taking many steps per launch
+ * with workgroup barriers only (not with conserve_volume or tsteps > 1).
+ * AUTO = TILED with the z-chunk per block chosen by timing candidates on the
+ * current field at the first spfm_step (that call synchronises the stream
+ * once); for batches whose stored grids all have at most 4096 points (where
+ * one workgroup's step is quicker than a launch), AUTO = RESIDENT.  Results do not
+ * depend on the kernel choice among TILED and RESIDENT, nor on the z-chunk:
+ * they are equal bit for bit. */
+typedef enum {
+    SPFM_KERNEL_AUTO = 0,
+    SPFM_KERNEL_PLAIN = 1,
+    SPFM_KERNEL_TILED = 2,
+    SPFM_KERNEL_RESIDENT = 3
+} spfm_kernel;
 
 typedef struct {
     int32_t nx, ny, nz; /* grid points per axis: >= 3 on periodic axes, >= 1 on walled axes */
@@ -314,6 +325,8 @@ spfm_status spfm_batch_diagnostics(spfm_batch *b, spfm_diag *out /* n entries */
 int64_t spfm_batch_points(const spfm_batch *b);
 /* Leading z-chunk of the batch's work items (after tuning, if any); 0 for NULL. */
 int32_t spfm_batch_zchunk(const spfm_batch *b);
+/* The step kernel the batch uses: SPFM_KERNEL_TILED or SPFM_KERNEL_RESIDENT; -1 for NULL. */
+int32_t spfm_batch_kernel(const spfm_batch *b);
 
 /* Host-only helpers (no HIP call): the calibration C_Gamma(lambda/dx) used
  * when C_Gamma <= 0, and the explicit stability bound for a parameter set

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["step_kernels.hip", "temporal.hip", "walls.hip", "volume.hip", "reduce.hip", "init.hip",
+SOURCES = ["step_kernels.hip", "resident.hip", "temporal.hip", "walls.hip", "volume.hip", "reduce.hip", "init.hip",
            "host_math.cpp", "api.cpp"]
 LIB = os.path.join(HERE, "libspfm.so")
 OBJDIR = os.path.join(ROOT, "_build")
@@ -26,16 +26,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, one hipcc per source) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJDIR, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(OBJDIR, src + ".o")
+    objs = [os.path.join(OBJDIR, src + ".o") for src in SOURCES]
+
+    def compile_one(src_obj):
+        src, obj = src_obj
         cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(compile_one, zip(SOURCES, objs)))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

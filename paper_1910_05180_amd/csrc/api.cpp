@@ -96,8 +96,15 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
                     "grid too large (one stored z-plane < 2^31 bytes, ny <= 262140, nz <= 65535)");
     if (o.coupling != SPFM_LOCAL && o.coupling != SPFM_GLOBAL && o.coupling != SPFM_CF)
         return fail(SPFM_E_INVAL, "unknown coupling %d", o.coupling);
-    if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_TILED)
+    if (o.kernel < SPFM_KERNEL_AUTO || o.kernel > SPFM_KERNEL_RESIDENT)
         return fail(SPFM_E_INVAL, "unknown kernel %d", o.kernel);
+    if (o.kernel == SPFM_KERNEL_RESIDENT) {
+        if ((int64_t)sx * sy * sz > resident_max_cells((int)esize))
+            return fail(SPFM_E_INVAL, "the resident kernel holds at most %d stored points of this dtype",
+                        resident_max_cells((int)esize));
+        if (o.tsteps > 1 || o.conserve_volume)
+            return fail(SPFM_E_INVAL, "the resident kernel takes single steps at fixed mu");
+    }
     if (o.zchunk < 0 || o.zchunk > 4096) return fail(SPFM_E_INVAL, "zchunk must be in 0..4096");
     if (o.tsteps < 0 || o.tsteps > 4) return fail(SPFM_E_INVAL, "tsteps must be in 0..4");
     if (o.tsteps > 1 && (o.dtype != SPFM_F32 || o.kernel == SPFM_KERNEL_PLAIN))
@@ -358,6 +365,31 @@ struct spfm_ctx {
         return from_interior(buf[1 - cur], buf[cur]);
     }
 
+    // Resident kernel: the step coefficients of the stored dtype and the grid's
+    // offset (0) in device memory, uploaded before a launch when changed.
+    void* d_coef = nullptr;
+    int64_t* d_off = nullptr;
+    bool coef_dirty = true;
+    hipError_t launch_resident(int from, int to, int nsteps) {
+        const int S = r.p.stencil, C = kernel_coupling(r.p.coupling, r.p.interp);
+        const int cells = r.sx * r.sy * r.sz;
+        const bool f64 = r.dtype == SPFM_F64;
+        if (coef_dirty) {
+            const hipError_t e = hipMemcpyAsync(d_coef, f64 ? (const void*)&kd : (const void*)&kf,
+                                                f64 ? sizeof kd : sizeof kf, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return e;
+            coef_dirty = false;
+        }
+        return f64 ? launch_step_resident<double>((const double*)buf[from], (double*)buf[to],
+                                                  (const StepCoef<double>*)d_coef, d_off,
+                                                  (const WallCoef<double>*)d_wall, 1, cells, nsteps, S, C,
+                                                  stream)
+                   : launch_step_resident<float>((const float*)buf[from], (float*)buf[to],
+                                                 (const StepCoef<float>*)d_coef, d_off,
+                                                 (const WallCoef<float>*)d_wall, 1, cells, nsteps, S, C,
+                                                 stream);
+    }
+
     int zlen = kTileZ;        // planes per block of the tiled kernel (the leading chunks)
     bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
     bool tuned = false;
@@ -377,6 +409,7 @@ struct spfm_ctx {
                                     kernel_coupling(r.p.coupling, r.p.interp), r.tsteps, zlen, stream);
     }
     hipError_t launch_one(int from) {
+        if (r.kernel == SPFM_KERNEL_RESIDENT) return launch_resident(from, 1 - from, 1);
         const void* in = buf[from];
         void* out = buf[1 - from];
         const int S = r.p.stencil, C = kernel_coupling(r.p.coupling, r.p.interp);
@@ -427,6 +460,7 @@ struct spfm_ctx {
         wf = wall_coef<float>(r);
         wd = wall_coef<double>(r);
         nghost = wall_ghosts(r.sx, r.sy, r.sz, r.walls);
+        coef_dirty = true;
         graphs.clear();
     }
 };
@@ -464,9 +498,19 @@ struct spfm_batch {
     std::vector<Tracker> track;
     GraphCache graphs;
 
+    // Resident kernel (every stored grid fits the LDS of one workgroup): one
+    // launch takes many steps of all grids; max_cells is the largest stored grid.
+    bool resident = false;
+    int max_cells = 0;
+    hipError_t launch_resident(int from, int to, int nsteps) {
+        return launch_step_resident<float>(buf[from], buf[to], d_coef, d_offset, walls ? d_wall : nullptr,
+                                           n, max_cells, nsteps, stencil, coupling, stream);
+    }
+
     int unit() const { return 1; }
     hipError_t launch_unit(int from) { return launch_one(from); }
     hipError_t launch_one(int from) {
+        if (resident) return launch_resident(from, 1 - from, 1);
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
                                    walls ? d_wall : nullptr, stencil, coupling, stream);
     }
@@ -764,6 +808,25 @@ spfm_status run_steps(Obj* o, int64_t n) {
     return SPFM_OK;
 }
 
+// Resident kernel: n steps in launches of at most kResidentChunk steps each; a
+// launch of an odd count writes the other buffer, of an even count the same one.
+constexpr int kResidentChunk = 4096;
+constexpr int64_t kResidentAutoCells = 4096;   // largest stored grid AUTO steps resident
+template <typename Obj>
+spfm_status run_resident(Obj* o, int64_t n) {
+    if (n < 0) return fail(SPFM_E_INVAL, "negative step count");
+    while (n > 0) {
+        const int chunk = (int)std::min<int64_t>(n, kResidentChunk);
+        const int to = (chunk & 1) ? 1 - o->cur : o->cur;
+        const hipError_t e = o->launch_resident(o->cur, to, chunk);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "resident step launch: %s", hipGetErrorString(e));
+        o->cur = to;
+        o->nsteps += chunk;
+        n -= chunk;
+    }
+    return SPFM_OK;
+}
+
 spfm_status copy_in(void* dst, const void* src, size_t bytes, int src_on_device, hipStream_t s) {
     if (!src) return fail(SPFM_E_INVAL, "source is NULL");
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -775,6 +838,35 @@ spfm_status copy_out(void* dst, const void* src, size_t bytes, int dst_on_device
     if (!dst) return fail(SPFM_E_INVAL, "destination is NULL");
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return SPFM_OK;
+}
+
+spfm_status check_spheres(int32_t n, const double* centers, const double* radii) {
+    if (n < 0 || (n > 0 && (!centers || !radii))) return fail(SPFM_E_INVAL, "bad sphere list");
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 4; ++a)
+            if (!std::isfinite(a < 3 ? centers[3 * i + a] : radii[i]))
+                return fail(SPFM_E_INVAL, "non-finite sphere %d", i);
+    return SPFM_OK;
+}
+
+// The field of n spheres from the device table d_sph (4 doubles per sphere),
+// enqueued on the context stream; synchronises before returning, so the table
+// may be reused afterwards.
+spfm_status init_spheres_from(spfm_ctx* c, int32_t n, const double* d_sph) {
+    const Params& p = c->r.p;
+    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
+    hipError_t e = c->r.dtype == SPFM_F64
+                       ? launch_init_spheres<double>((double*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n,
+                                                     d_sph, c->stream)
+                       : launch_init_spheres<float>((float*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n,
+                                                    d_sph, c->stream);
+    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "sphere init: %s", hipGetErrorString(e));
+    if (se != hipSuccess) return fail(SPFM_E_HIP, "sphere init sync: %s", hipGetErrorString(se));
+    c->nsteps = 0;
+    c->track.reset(n == 1 ? 2 : 0, 0.0);
     return SPFM_OK;
 }
 
@@ -826,7 +918,20 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
         return fail(SPFM_E_NOMEM, "device allocation of the reduction scratch failed");
     }
     c->refresh_coef();
-    if (r.walls && r.kernel == SPFM_KERNEL_TILED) {
+    if (r.kernel == SPFM_KERNEL_RESIDENT) {
+        const size_t cb = r.dtype == SPFM_F64 ? sizeof(StepCoef<double>) : sizeof(StepCoef<float>);
+        const int64_t zero = 0;
+        if (hipMalloc(&c->d_coef, cb) != hipSuccess || hipMalloc(&c->d_off, sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            spfm_destroy(c);
+            return fail(SPFM_E_NOMEM, "device allocation of the resident step tables failed");
+        }
+        if (hipMemcpy(c->d_off, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) {
+            spfm_destroy(c);
+            return fail(SPFM_E_HIP, "upload of the resident step tables failed");
+        }
+    }
+    if (r.walls && (r.kernel == SPFM_KERNEL_TILED || r.kernel == SPFM_KERNEL_RESIDENT)) {
         const bool f64 = r.dtype == SPFM_F64;
         const size_t wb = f64 ? sizeof(WallCoef<double>) : sizeof(WallCoef<float>);
         if (hipMalloc(&c->d_wall, wb) != hipSuccess) {
@@ -857,6 +962,8 @@ void spfm_destroy(spfm_ctx* c) {
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_wall) (void)hipFree(c->d_wall);
+    if (c->d_coef) (void)hipFree(c->d_coef);
+    if (c->d_off) (void)hipFree(c->d_off);
     if (c->owns) {
         if (c->buf[0]) (void)hipFree(c->buf[0]);
         if (c->buf[1]) (void)hipFree(c->buf[1]);
@@ -910,32 +1017,24 @@ spfm_status spfm_init_planar(spfm_ctx* c, const int32_t hkl[3], double offset) {
 
 spfm_status spfm_init_spheres(spfm_ctx* c, int32_t n, const double* centers, const double* radii) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
-    if (n < 0 || (n > 0 && (!centers || !radii))) return fail(SPFM_E_INVAL, "bad sphere list");
+    spfm_status st = check_spheres(n, centers, radii);
+    if (st != SPFM_OK) return st;
     std::vector<double> h((size_t)std::max(n, 1) * 4, 0.0);
     for (int i = 0; i < n; ++i) {
         for (int a = 0; a < 3; ++a) h[4 * i + a] = centers[3 * i + a];
         h[4 * i + 3] = radii[i];
-        for (int a = 0; a < 4; ++a)
-            if (!std::isfinite(h[4 * i + a])) return fail(SPFM_E_INVAL, "non-finite sphere %d", i);
     }
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, sizeof(double) * h.size()));
     hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
-    const Params& p = c->r.p;
-    void* dst = c->r.walls ? c->buf[1 - c->cur] : c->buf[c->cur];
-    if (e == hipSuccess) {
-        e = c->r.dtype == SPFM_F64
-                ? launch_init_spheres<double>((double*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream)
-                : launch_init_spheres<float>((float*)dst, p.nx, p.ny, p.nz, p.dx, p.lambda, n, d, c->stream);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(d);
+        return fail(SPFM_E_HIP, "sphere upload: %s", hipGetErrorString(e));
     }
-    if (e == hipSuccess && c->r.walls) e = c->to_interior(c->buf[c->cur], dst);
-    hipError_t se = hipStreamSynchronize(c->stream);
+    st = init_spheres_from(c, n, d);
     (void)hipFree(d);
-    if (e != hipSuccess) return fail(SPFM_E_HIP, "sphere init: %s", hipGetErrorString(e));
-    if (se != hipSuccess) return fail(SPFM_E_HIP, "sphere init sync: %s", hipGetErrorString(se));
-    c->nsteps = 0;
-    c->track.reset(n == 1 ? 2 : 0, 0.0);
-    return SPFM_OK;
+    return st;
 }
 
 spfm_status spfm_init_front(spfm_ctx* c, const double n[3], double offset) {
@@ -1077,6 +1176,7 @@ spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
 
 spfm_status spfm_step(spfm_ctx* c, int64_t n) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    if (c->r.kernel == SPFM_KERNEL_RESIDENT) return run_resident(c, n);
     if (n > 0 && c->auto_kernel && !c->tuned) {
         spfm_status st = autotune(c);
         if (st != SPFM_OK) return st;
@@ -1149,7 +1249,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     if (o.dtype != SPFM_F32) return fail(SPFM_E_INVAL, "batches run in F32");
     if (o.d_phi[0] || o.d_phi[1]) return fail(SPFM_E_INVAL, "batches allocate their own buffers");
     if (o.C_Gamma > 0.0) return fail(SPFM_E_INVAL, "batches calibrate C_Gamma per grid");
-    if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled kernel");
+    if (o.kernel == SPFM_KERNEL_PLAIN) return fail(SPFM_E_INVAL, "batches use the tiled or resident kernel");
     if (o.tsteps > 1) return fail(SPFM_E_INVAL, "batches step one step per launch (tsteps <= 1)");
     if (o.conserve_volume) return fail(SPFM_E_INVAL, "batches keep mu fixed (conserve_volume = 0)");
     spfm_batch* b = new (std::nothrow) spfm_batch;
@@ -1192,6 +1292,24 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         if (o.walls) wall[i] = wall_coef<float>(ri);
     }
     b->dims = dims;
+    // The resident kernel when every stored grid fits one workgroup's LDS: asked
+    // for, or chosen by AUTO (unless a z-chunk for the tiled kernel was given)
+    // for grids of at most kResidentAutoCells stored points.  One workgroup runs
+    // on one CU, so a step of a larger grid takes longer there than the launch of
+    // one tiled step of the whole batch: 7 walled 120 x 10 x 10 TI_n grids (17568
+    // stored points each) took 28.5 us per step resident against 7.1 us tiled,
+    // 12 periodic 256 x 3 x 3 slabs 1.7 us against 3.2 us.
+    int64_t largest = 0;
+    for (const GridDims& d : dims) largest = std::max<int64_t>(largest, (int64_t)d.nx * d.ny * d.nz);
+    const bool fits = largest <= resident_max_cells((int)sizeof(float));
+    b->max_cells = fits ? (int)largest : 0;
+    if (o.kernel == SPFM_KERNEL_RESIDENT && !fits) {
+        spfm_batch_destroy(b);
+        return fail(SPFM_E_INVAL, "the resident kernel holds at most %d stored points per grid",
+                    resident_max_cells((int)sizeof(float)));
+    }
+    b->resident = o.kernel == SPFM_KERNEL_RESIDENT ||
+                  (o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0 && largest <= kResidentAutoCells);
     b->tx = tile_x(true, o.coupling);
     b->auto_zlen = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0;
     const int zb = o.zchunk > 0 ? o.zchunk : default_zlen(dims, b->tx, kTileY, true, (int64_t)1 << 19, 4);
@@ -1288,6 +1406,7 @@ spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on
 
 spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
     if (!b) return fail(SPFM_E_INVAL, "batch is NULL");
+    if (b->resident) return run_resident(b, n);
     if (n > 0 && b->auto_zlen && !b->tuned) {
         spfm_status st = autotune(b);
         if (st != SPFM_OK) return st;
@@ -1314,6 +1433,10 @@ spfm_status spfm_batch_diagnostics(spfm_batch* b, spfm_diag* out) {
 int64_t spfm_batch_points(const spfm_batch* b) { return b ? b->points : 0; }
 
 int32_t spfm_batch_zchunk(const spfm_batch* b) { return b ? b->zlen : 0; }
+
+int32_t spfm_batch_kernel(const spfm_batch* b) {
+    return b ? (b->resident ? SPFM_KERNEL_RESIDENT : SPFM_KERNEL_TILED) : -1;
+}
 
 double spfm_calibrate_cgamma(double lambda_over_dx, int coupling) {
     return calibrate_cgamma(lambda_over_dx, coupling);

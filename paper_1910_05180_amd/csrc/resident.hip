@@ -1,0 +1,189 @@
+// Resident step for small grids (forward Euler of Eq. 2, periodic or with the
+// contact-angle walls of Eq. 7): one block per grid holds the whole stored
+// grid in LDS, twice (phi^n and phi^{n+1}), and takes many steps in one launch
+// with block barriers only; HBM is touched once at the start and once at the
+// end.  Grids of the orientation study (120 x 10 x 10 between walls) and of the
+// 1D model comparison (256 x 3 x 3 slabs) are small enough, and their steps are
+// otherwise bound by the latency of one launch per step.
+//
+// Every point is computed by the same per-plane sums and point update as the
+// tiled sweep (point_from_planes), on the same neighbour values: the result of
+// n resident steps equals n tiled steps bit for bit.
+//  * The block's threads own columns of the grid's interior, each cut into
+//    z-segments so that the columns and segments spread evenly over the
+//    threads; a thread marches its segment along z keeping the per-plane sums
+//    of three planes in registers, as the tiled sweep does.
+//  * TI_n: psi' of a neighbour is evaluated where it is needed (four in-plane
+//    face neighbours and the column cell of each plane) instead of being
+//    staged: the two field copies use the LDS.
+//  * Walls: before each step the ghost cells of the current copy are set from
+//    their interior neighbours by Eq. 7 with the coefficient of their class.
+//  * The output may be the input buffer (an even number of steps): a block reads
+//    its whole grid before its first step and writes it after its last.
+#include "spfm_impl.h"
+
+namespace spfm {
+
+namespace {
+
+constexpr int kResThreads = 1024;
+
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Per-plane sums of the column (x, y) on plane z of the field F (row stride sx,
+// plane stride pl), with the same association as plane_sums on a staged tile:
+// xm, xp, ym, yp are the wrapped (or, next to a wall, ghost) neighbour indices.
+template <typename T, int S, int C>
+__device__ __forceinline__ void column_plane(const T* __restrict__ F, int pl, int sx, int z, int x,
+                                             int xm, int xp, int y, int ym, int yp, bool with_grad,
+                                             T eps, PlaneRegs<T>& R) {
+    const T* Q = F + (size_t)z * pl;
+    const T* r0 = Q + y * sx;
+    const T* rm = Q + ym * sx;
+    const T* rp = Q + yp * sx;
+    const T e = r0[xp], w = r0[xm], n = rp[x], s = rm[x];
+    R.c = r0[x];
+    R.fc = (e + w) + (n + s);
+    if (S >= 18) R.dc = (rp[xp] + rm[xm]) + (rp[xm] + rm[xp]);
+    if (C == kLocal) {
+        R.pc = psi2(R.c, eps);
+        if (with_grad) {
+            R.gx = psi2(e, eps) - psi2(w, eps);
+            R.gy = psi2(n, eps) - psi2(s, eps);
+        }
+    }
+}
+
+template <typename T, int S, int C, bool W>
+__global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
+    const T* buf_in, T* buf_out, const StepCoef<T>* __restrict__ coef,
+    const int64_t* __restrict__ offset, const WallCoef<T>* __restrict__ wall, int nsteps) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x;
+    const StepCoef<T> k = coef[g];
+    const int sx = k.nx, sy = k.ny, sz = k.nz;
+    const int pl = sx * sy, cells = pl * sz;
+    T* A = lds;
+    T* B = lds + cells;
+    const T* in = buf_in + offset[g];
+    T* out = buf_out + offset[g];
+    for (int i = tid; i < cells; i += kResThreads) A[i] = in[i];
+    __syncthreads();   // the ghost fill reads cells that other threads loaded
+
+    const int walls = W ? wall[g].walls : 0;
+    const int wx = walls & 1, wy = (walls >> 1) & 1, wz = (walls >> 2) & 1;
+    const int nxi = sx - 2 * wx, nyi = sy - 2 * wy, nzi = sz - 2 * wz;
+    const int ncol = nxi * nyi;
+    // z-segments per column: the count that minimises the planes a thread
+    // touches, (points + 2 planes of each segment's halo) x segments per thread.
+    int nseg = 1;
+    {
+        int best = 1 << 30;
+        for (int q = 1; q <= nzi; ++q) {
+            const int per = (ncol * q + kResThreads - 1) / kResThreads;
+            const int cost = per * ((nzi + q - 1) / q + 2);
+            if (cost < best) { best = cost; nseg = q; }
+        }
+    }
+    const int items = ncol * nseg;
+
+    for (int step = 0; step < nsteps; ++step) {
+        if (W) {   // ghosts of the current copy from their interior neighbours (Eq. 7)
+            const WallCoef<T>& wc = wall[g];
+            for (int i = tid; i < cells; i += kResThreads) {
+                const int x = i % sx, y = (i / sx) % sy, z = i / pl;
+                const int cx = wx ? (x == 0 ? -1 : (x == sx - 1 ? 1 : 0)) : 0;
+                const int cy = wy ? (y == 0 ? -1 : (y == sy - 1 ? 1 : 0)) : 0;
+                const int cz = wz ? (z == 0 ? -1 : (z == sz - 1 ? 1 : 0)) : 0;
+                if (cx | cy | cz)
+                    A[i] = wall_map(A[(z - cz) * pl + (y - cy) * sx + (x - cx)],
+                                    wc.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)]);
+            }
+        }
+        __syncthreads();
+        for (int it = tid; it < items; it += kResThreads) {
+            const int col = it % ncol, seg = it / ncol;
+            const int x = wx + col % nxi, y = wy + col / nxi;
+            const int xm = wrap1(x - 1, sx), xp = wrap1(x + 1, sx);
+            const int ym = wrap1(y - 1, sy), yp = wrap1(y + 1, sy);
+            const int za = wz + (seg * nzi) / nseg, zb = wz + ((seg + 1) * nzi) / nseg;
+            PlaneRegs<T> Rm{}, R0{}, Rp{};
+            column_plane<T, S, C>(A, pl, sx, wrap1(za - 1, sz), x, xm, xp, y, ym, yp, false, k.eps, Rm);
+            column_plane<T, S, C>(A, pl, sx, za, x, xm, xp, y, ym, yp, true, k.eps, R0);
+            for (int z = za; z < zb; ++z) {
+                column_plane<T, S, C>(A, pl, sx, wrap1(z + 1, sz), x, xm, xp, y, ym, yp, true, k.eps, Rp);
+                B[z * pl + y * sx + x] = point_from_planes<T, S, C>(Rm, R0, Rp, k);
+                Rm = R0;
+                R0 = Rp;
+            }
+        }
+        __syncthreads();
+        T* t = A;
+        A = B;
+        B = t;
+    }
+    for (int i = tid; i < cells; i += kResThreads) out[i] = A[i];
+}
+
+template <typename T, int S, int C>
+struct ResidentLaunch {
+    static hipError_t run(const T* in, T* out, const StepCoef<T>* coef, const int64_t* offset,
+                          const WallCoef<T>* wall, int ngrids, int max_cells, int nsteps,
+                          hipStream_t s) {
+        const size_t lds = 2 * (size_t)max_cells * sizeof(T);
+        if (wall) {
+            auto kfn = k_step_resident<T, S, C, true>;
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kfn, dim3(ngrids), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
+                               nsteps);
+        } else {
+            auto kfn = k_step_resident<T, S, C, false>;
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kfn, dim3(ngrids), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
+                               nsteps);
+        }
+        return hipGetLastError();
+    }
+};
+
+template <typename T, typename... Args>
+hipError_t resident_dispatch(int stencil, int coupling, Args... args) {
+#define SPFM_RCASE(S_, C_)                                                  \
+    if (stencil == S_ && coupling == C_) return ResidentLaunch<T, S_, C_>::run(args...);
+    SPFM_RCASE(6, kLocal) SPFM_RCASE(6, kGlobal) SPFM_RCASE(6, kCF)
+    SPFM_RCASE(18, kLocal) SPFM_RCASE(18, kGlobal) SPFM_RCASE(18, kCF)
+    SPFM_RCASE(26, kLocal) SPFM_RCASE(26, kGlobal) SPFM_RCASE(26, kCF)
+    SPFM_RCASE(6, kCF5) SPFM_RCASE(18, kCF5) SPFM_RCASE(26, kCF5)
+    SPFM_RCASE(6, kCFAbel) SPFM_RCASE(18, kCFAbel) SPFM_RCASE(26, kCFAbel)
+#undef SPFM_RCASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int resident_max_cells(int elem_bytes) { return kResidentLdsBytes / (2 * elem_bytes); }
+
+template <typename T>
+hipError_t launch_step_resident(const T* buf_in, T* buf_out, const StepCoef<T>* d_coef,
+                                const int64_t* d_offset, const WallCoef<T>* d_wall, int ngrids,
+                                int max_cells, int nsteps, int stencil, int coupling, hipStream_t s) {
+    if (ngrids <= 0 || nsteps <= 0) return hipSuccess;
+    if (max_cells <= 0 || max_cells > resident_max_cells((int)sizeof(T))) return hipErrorInvalidValue;
+    return resident_dispatch<T>(stencil, coupling, buf_in, buf_out, d_coef, d_offset, d_wall, ngrids,
+                                max_cells, nsteps, s);
+}
+
+template hipError_t launch_step_resident<float>(const float*, float*, const StepCoef<float>*,
+                                                const int64_t*, const WallCoef<float>*, int, int, int,
+                                                int, int, hipStream_t);
+template hipError_t launch_step_resident<double>(const double*, double*, const StepCoef<double>*,
+                                                 const int64_t*, const WallCoef<double>*, int, int,
+                                                 int, int, int, hipStream_t);
+
+}  // namespace spfm

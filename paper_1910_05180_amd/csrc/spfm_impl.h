@@ -437,6 +437,16 @@ hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCo
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
                                const WallCoef<float>* d_wall, int stencil, int coupling,
                                hipStream_t s);
+// Resident step (resident.hip): one block per grid keeps the stored grid in LDS
+// (two copies, 2 x cells x sizeof(T) <= kResidentLdsBytes) and takes nsteps steps
+// in one launch: reads buf_in + offset[g], writes buf_out + offset[g] (which may
+// be the same buffer).  Results equal nsteps tiled steps bit for bit.
+constexpr int kResidentLdsBytes = 163840;   // gfx950: LDS one workgroup may allocate
+int resident_max_cells(int elem_bytes);
+template <typename T>
+hipError_t launch_step_resident(const T* buf_in, T* buf_out, const StepCoef<T>* d_coef,
+                                const int64_t* d_offset, const WallCoef<T>* d_wall, int ngrids,
+                                int max_cells, int nsteps, int stencil, int coupling, hipStream_t s);
 // Tiles of the single-step tiled kernels: a block marches one tile column
 // kTileX x kTileY along z, each of its waves computing a 16 x 4 patch.  FP32
 // TI_n uses 16 x 8 columns (two waves): its full-coupling branch makes the

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(HERE, "libspfm.so")
 
 F32, F64 = 0, 1
 LOCAL, GLOBAL, CF = 0, 1, 2
-KERNEL_AUTO, KERNEL_PLAIN, KERNEL_TILED = 0, 1, 2
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_TILED, KERNEL_RESIDENT = 0, 1, 2, 3
 _DTYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
 _COUPLINGS = {"local": LOCAL, "global": GLOBAL, "cf": CF}
-_KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "tiled": KERNEL_TILED}
+_KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "tiled": KERNEL_TILED,
+            "resident": KERNEL_RESIDENT}
 _INTERPS = {"h3": 0, "h5": 1, "habel": 2}
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
@@ -124,6 +125,7 @@ def load():
         "spfm_batch_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
         "spfm_batch_points": ([vp], i64),
         "spfm_batch_zchunk": ([vp], i32),
+        "spfm_batch_kernel": ([vp], i32),
         "spfm_calibrate_cgamma": ([d, ctypes.c_int], d),
         "spfm_stable_dt": ([ctypes.c_int, ctypes.c_int, dp, dp, d, d, d, d, d, d], d),
         "spfm_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -399,6 +401,11 @@ class SpfmBatch:
     def zchunk(self) -> int:
         """Leading z-chunk of the work items (chosen at the first step with kernel="auto")."""
         return int(load().spfm_batch_zchunk(self._h))
+
+    @property
+    def kernel(self) -> str:
+        """The step kernel in use: "tiled" or "resident"."""
+        return {KERNEL_TILED: "tiled", KERNEL_RESIDENT: "resident"}[int(load().spfm_batch_kernel(self._h))]
 
     def init_planar(self, hkls, offsets):
         h = np.ascontiguousarray(np.asarray(hkls, dtype=np.int32).reshape(-1, 3))

@@ -163,3 +163,31 @@ def test_walled_batch_accepts_short_walled_axes(S):
     creation then stops only at the device."""
     st, msg = try_batch(S, [(1, 1, 50), (2, 3, 40)], walls="yz", wall_sin=[(0,) * 6, (0,) * 6])
     assert st != -1, msg
+
+
+@pytest.mark.parametrize("shape,kw", [
+    ((32, 32, 32), dict()),                           # 32768 stored FP32 points > 20480
+    ((16, 16, 48), dict(dtype="f64")),                # 12288 FP64 points > 10240
+    ((18, 30, 36), dict(walls=7)),                    # 20 x 32 x 38 = 24320 stored with ghosts
+    ((8, 8, 8), dict(conserve_volume=True)),
+    ((8, 8, 8), dict(tsteps=2)),
+])
+def test_resident_kernel_refuses_what_it_cannot_hold(S, shape, kw):
+    """The resident kernel keeps two copies of the stored grid in one
+    workgroup's 160 KiB of LDS and takes single steps at fixed mu."""
+    st, msg = S.try_create(shape, kernel="resident", **kw)
+    assert st == -1 and "resident" in msg, msg
+
+
+def test_resident_kernel_accepts_the_largest_grid_it_holds(S):
+    """20480 FP32 / 10240 FP64 stored points pass validation (creation then
+    stops only at the device on a machine without one)."""
+    st, msg = S.try_create((16, 32, 40), kernel="resident")
+    assert st != -1, msg
+    st, msg = S.try_create((16, 16, 40), kernel="resident", dtype="f64")
+    assert st != -1, msg
+
+
+def test_resident_batch_refuses_a_grid_it_cannot_hold(S):
+    st, msg = try_batch(S, [(8, 8, 8), (32, 32, 32)], kernel="resident")
+    assert st == -1 and "resident" in msg, msg
