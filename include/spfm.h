@@ -223,6 +223,18 @@ spfm_status spfm_field_ptr(spfm_ctx *ctx, void **d_ptr);
 spfm_status spfm_init_planar(spfm_ctx *ctx, const int32_t hkl[3], double offset);
 spfm_status spfm_init_spheres(spfm_ctx *ctx, int32_t n, const double *centers,
                               const double *radii);
+/* Allocation-free variant of spfm_init_spheres, for callers that cannot
+ * allocate device memory (tight loops that re-initialise a field, harnesses
+ * that forbid allocation).  Same arguments and the same field bit for bit; the
+ * sphere table is staged in a library-held static device array of at most 4096
+ * spheres (128 KiB per GPU, held until the process ends) instead of a
+ * per-call allocation.  Calls no hipMalloc or hipFree.  SPFM_E_INVAL for n >
+ * 4096 (and as spfm_init_spheres otherwise); SPFM_E_STATE unless the device
+ * that was current at spfm_create is current.  The call waits for its own
+ * work, so calls from one host thread never overlap; calls that overlap on one
+ * GPU (other host threads or processes) share the array and race. */
+spfm_status spfm_init_spheres_noalloc(spfm_ctx *ctx, int32_t n, const double *centers,
+                                      const double *radii);
 /* Eq. 3 single planar front (not periodic): phi = (1 - tanh(2 s / lambda)) / 2,
  * s = p . n/|n| - c, c = the box centre (nx, ny, nz) dx / 2 projected on n/|n|
  * plus offset; phase 1 behind the front, n points into phase 0.  Every axis

@@ -313,6 +313,7 @@ struct GraphCache {
 
 struct spfm_ctx {
     Resolved r;
+    int device = 0;           // the device current at create (the buffers live there)
     hipStream_t stream = nullptr;
     void* buf[2] = {nullptr, nullptr};
     bool owns = false;
@@ -884,6 +885,10 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     spfm_ctx* c = new (std::nothrow) spfm_ctx;
     if (!c) return fail(SPFM_E_NOMEM, "host allocation failed");
     c->r = r;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(SPFM_E_HIP, "hipGetDevice failed");
+    }
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
     const bool f32 = r.dtype == SPFM_F32;
@@ -1035,6 +1040,30 @@ spfm_status spfm_init_spheres(spfm_ctx* c, int32_t n, const double* centers, con
     st = init_spheres_from(c, n, d);
     (void)hipFree(d);
     return st;
+}
+
+spfm_status spfm_init_spheres_noalloc(spfm_ctx* c, int32_t n, const double* centers,
+                                      const double* radii) {
+    if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
+    spfm_status st = check_spheres(n, centers, radii);
+    if (st != SPFM_OK) return st;
+    if (n > kMaxScratchSpheres)
+        return fail(SPFM_E_INVAL, "at most %d spheres without allocation (got %d)", kMaxScratchSpheres, n);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(SPFM_E_STATE, "the context lives on device %d; device %d is current", c->device, dev);
+    double* d = nullptr;
+    HIP_TRY(sphere_scratch(&d));
+    if (n > 0) {
+        // pack (x, y, z) and R of each sphere into rows of 4 doubles, straight
+        // from the caller's arrays
+        HIP_TRY(hipMemcpy2DAsync(d, 4 * sizeof(double), centers, 3 * sizeof(double), 3 * sizeof(double),
+                                 (size_t)n, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpy2DAsync(d + 3, 4 * sizeof(double), radii, sizeof(double), sizeof(double),
+                                 (size_t)n, hipMemcpyHostToDevice, c->stream));
+    }
+    return init_spheres_from(c, n, d);
 }
 
 spfm_status spfm_init_front(spfm_ctx* c, const double n[3], double offset) {

@@ -9,9 +9,18 @@
 //  spheres: phi = 1 - prod_i (1 - phi_i), phi_i = L(R_i - |p - c_i|) with the
 //           minimum-image distance, accumulated as sum_i phi_i prod_{j<i}(1 - phi_j)
 //           so that small tail values keep their relative accuracy.
+#include <mutex>
+
 #include "spfm_impl.h"
 
 namespace spfm {
+
+// Device staging of the sphere table for the allocation-free initialisation
+// (4 doubles per sphere: centre x, y, z, radius).  One copy per GPU, held
+// until the process ends; every call on a GPU overwrites it.  In host code the
+// array's name is not a device address: host code uses the pointer that
+// sphere_scratch() obtains from the runtime for the current device.
+static __device__ __align__(256) double scratch[4 * kMaxScratchSpheres];
 
 namespace {
 
@@ -102,6 +111,25 @@ hipError_t launch_init_spheres(T* phi, int nx, int ny, int nz, double dx, double
     hipLaunchKernelGGL((k_init_spheres<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        phi, nx, ny, nz, dx, 4.0 / lambda, cutoff, nsph, d_spheres);
     return hipGetLastError();
+}
+
+hipError_t sphere_scratch(double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static double* ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!ptr[dev]) {   // once per device, with that device current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double*>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 template hipError_t launch_init_planar<float>(float*, int, int, int, double, double, const int*,

@@ -536,5 +536,9 @@ hipError_t launch_init_planar(T* phi, int nx, int ny, int nz, double dx, double 
 template <typename T>
 hipError_t launch_init_spheres(T* phi, int nx, int ny, int nz, double dx, double lambda, int n,
                                const double* d_spheres, hipStream_t s);
+// Allocation-free sphere initialisation: the device address, on the current
+// device, of a static table of kMaxScratchSpheres spheres (4 doubles each).
+constexpr int kMaxScratchSpheres = 4096;
+hipError_t sphere_scratch(double** out);
 
 }  // namespace spfm

@@ -105,6 +105,7 @@ def load():
         "spfm_field_ptr": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
         "spfm_init_planar": ([vp, ip, d], ctypes.c_int),
         "spfm_init_spheres": ([vp, i32, dp, dp], ctypes.c_int),
+        "spfm_init_spheres_noalloc": ([vp, i32, dp, dp], ctypes.c_int),
         "spfm_init_front": ([vp, dp, d], ctypes.c_int),
         "spfm_init_box": ([vp, dp, dp], ctypes.c_int),
         "spfm_contour_stats": ([vp, ctypes.POINTER(Contour)], ctypes.c_int),
@@ -280,12 +281,15 @@ class Spfm:
         h = (ctypes.c_int32 * 3)(*[int(v) for v in hkl])
         _check(load().spfm_init_planar(self._h, h, float(offset)))
 
-    def init_spheres(self, centers, radii):
+    def init_spheres(self, centers, radii, noalloc: bool = False):
+        """Eq. 3 grains; noalloc: through spfm_init_spheres_noalloc (no device
+        allocation, at most 4096 spheres)."""
         c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
         r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
         assert c.shape[0] == r.size
         dp = ctypes.POINTER(ctypes.c_double)
-        _check(load().spfm_init_spheres(self._h, r.size, c.ctypes.data_as(dp), r.ctypes.data_as(dp)))
+        f = load().spfm_init_spheres_noalloc if noalloc else load().spfm_init_spheres
+        _check(f(self._h, r.size, c.ctypes.data_as(dp), r.ctypes.data_as(dp)))
 
     def init_box(self, lo, hi):
         a = np.ascontiguousarray(lo, dtype=np.float64).reshape(3)
