@@ -37,7 +37,6 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # running fractions 39, their sum 3, select 1).  The mix is measured on the
 # field at the start and the end of the timed window.
 OPS_BULK, OPS_TAIL, OPS_FULL = 28, 64, 157
-ZCHUNK = 32                    # leading planes per block (the fastest in sweeps of 16..64)
 REPEATS = 5                    # timed windows of the headline; the median is reported
 
 
@@ -66,6 +65,10 @@ def parse():
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain copy of 2^26 floats (256 MiB read + 256 MiB written), "
                          "the reference that scales hardware byte counters")
+    ap.add_argument("--tile", type=int, nargs=2, default=None, metavar=("TX", "TY"),
+                    help="tile column of the headline's tiled kernel (default: tuned at the first step)")
+    ap.add_argument("--zchunk", type=int, default=0,
+                    help="leading z-chunk of the headline's tiled kernel (default: tuned at the first step)")
     ap.add_argument("--traffic-child", action="store_true",
                     help="internal: the headline kernel alone, once, for a counter pass")
     return ap.parse_args()
@@ -192,7 +195,16 @@ def warm_clocks(torch, stream, step, chunk=200, min_s=1.0, max_s=4.0, tol=0.01):
         last = ms
 
 
-def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", zchunk=ZCHUNK,
+def headline_kernel(tile=None, zchunk=0):
+    """Options of the headline step: the tiled kernel with the given tile column
+    and z-chunk, or (None, 0) the autotuner's choice among the compiled shapes
+    and chunk lengths, timed at the first step."""
+    if tile is None and not zchunk:
+        return dict(kernel="auto")
+    return dict(kernel="auto" if tile is None or not zchunk else "tiled", tile=tile, zchunk=zchunk)
+
+
+def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", tile=None, zchunk=0,
                  rewarm_steps=300):
     """The FP32 tiled step on the grain workload.  The clocks are first brought
     to their steady state on a scratch context of the same workload (its steps
@@ -208,7 +220,7 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", zc
     reps = []
     with torch.cuda.stream(stream):
         kw = dict(lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil, dtype="f32",
-                  coupling=coupling, kernel="tiled", dt=w.dt, zchunk=zchunk, stream=stream)
+                  coupling=coupling, dt=w.dt, stream=stream, **headline_kernel(tile, zchunk))
         scratch = spfm.Spfm(w.shape, **kw)
         scratch.init_spheres(w.centers, w.radii)
         warm = warm_clocks(torch, stream, scratch.step)
@@ -234,7 +246,9 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", zc
             reps.append({"wall": wall, "ev_ms": e0.elapsed_time(e1), "R0": d0["interface_position"],
                          "R1": d1["interface_position"], "mix": (m0, m1)})
         d = s.diagnostics()
-        d["zchunk"] = s.info()["zchunk"]
+        inf = s.info()
+        d["zchunk"] = inf["zchunk"]
+        d["tile"] = [inf["tile_x"], inf["tile_y"]]
         d["warm"] = {"seconds": warm[0], "steps": warm[1], "us_per_step_last": warm[2]}
         d["contour"] = s.contour_stats()
         if w.rays is not None:
@@ -274,8 +288,9 @@ def traffic_from_counters(fetch_rows, write_rows, steps, copy_bytes, kernel_tag=
         return None
     kib = copy_bytes / 1024.0
     fs, ws = kib / f_copy, kib / w_copy
+    name = [n for _, n, _ in fetch_rows if kernel_tag in n][-1]
     return {"bytes": (f_step * fs + w_step * ws) * 1024.0, "fetch_kib": f_step, "write_kib": w_step,
-            "fetch_scale": fs, "write_scale": ws}
+            "fetch_scale": fs, "write_scale": ws, "kernel": name}
 
 
 def measure_traffic(args):
@@ -293,6 +308,7 @@ def measure_traffic(args):
         return None
     env = dict(os.environ, TMPDIR="/tmp")
     rows = {}
+    chosen = {"tile": args.tile, "zchunk": args.zchunk}
     tmp = tempfile.mkdtemp(prefix="spfm_traffic_", dir="/tmp")
     try:
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -300,8 +316,18 @@ def measure_traffic(args):
             cmd = [prof, "--pmc", counter, "--output-format", "csv", "-d", out, "-o", "run", "--",
                    sys.executable, os.path.abspath(__file__), "--traffic-child", "--steps", str(args.steps),
                    "--warmup", str(args.warmup), "--coupling", args.coupling]
+            if chosen["tile"] is not None:
+                cmd += ["--tile", str(chosen["tile"][0]), str(chosen["tile"][1])]
+            if chosen["zchunk"]:
+                cmd += ["--zchunk", str(chosen["zchunk"])]
             print(f"traffic: {counter} pass", file=sys.stderr, flush=True)
             r = subprocess.run(cmd, cwd="/tmp", env=env, capture_output=True, text=True, timeout=240)
+            # the first pass tunes the kernel; later passes and the timed run reuse its choice
+            for line in reversed(r.stdout.splitlines()):
+                if line.startswith("{") and "zchunk" in line:
+                    c = json.loads(line)
+                    chosen = {"tile": c["tile"], "zchunk": c["zchunk"]}
+                    break
             files = glob.glob(os.path.join(out, "**", "*counter_collection.csv"), recursive=True)
             if r.returncode != 0 and not files:
                 print(f"traffic: {counter} pass failed (rc {r.returncode}): {r.stderr[-400:]}",
@@ -316,7 +342,10 @@ def measure_traffic(args):
         return None
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return traffic_from_counters(rows["FETCH_SIZE"], rows["WRITE_SIZE"], args.steps, 4 * (1 << 26))
+    t = traffic_from_counters(rows["FETCH_SIZE"], rows["WRITE_SIZE"], args.steps, 4 * (1 << 26))
+    if t is not None:
+        t.update(chosen)
+    return t
 
 
 def traffic_child(args):
@@ -330,13 +359,15 @@ def traffic_child(args):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = spfm.Spfm(w.shape, lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil,
-                      dtype="f32", coupling=args.coupling, kernel="tiled", dt=w.dt, zchunk=ZCHUNK,
-                      stream=stream)
+                      dtype="f32", coupling=args.coupling, dt=w.dt, stream=stream,
+                      **headline_kernel(args.tile, args.zchunk))
         s.init_spheres(w.centers, w.radii)
         s.step(args.warmup)
         s.step(args.steps)
         torch.cuda.synchronize()
+        inf = s.info()
         s.close()
+    print(json.dumps({"tile": [inf["tile_x"], inf["tile_y"]], "zchunk": inf["zchunk"]}), flush=True)
 
 
 def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="local", zchunk=0,
@@ -362,7 +393,9 @@ def timed_run(spfm, torch, shape, w, *, dtype, kernel, steps, warmup, coupling="
         wall = time.perf_counter() - t0
         ev_ms = e0.elapsed_time(e1)
         d = s.diagnostics()
-        d["zchunk"] = s.info()["zchunk"]
+        inf = s.info()
+        d["zchunk"] = inf["zchunk"]
+        d["tile"] = [inf["tile_x"], inf["tile_y"]]
         if contour:
             d["contour"] = s.contour_stats()
             if rays is not None:
@@ -392,10 +425,11 @@ def batch_leg(spfm, torch, inputs, steps, warmup):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         n = b.points
-        zc = b.zchunk
+        inf = b.info()
         b.close()
     return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "grids": len(ws), "points": n,
-            "steps": steps, "zchunk": zc, "ms_per_step": wall * 1e3 / steps,
+            "steps": steps, "kernel": "tiled", "tile": [inf["tile_x"], inf["tile_y"]],
+            "zchunk": inf["zchunk"], "ms_per_step": wall * 1e3 / steps,
             "kernel_ms_per_step": e0.elapsed_time(e1) / steps,
             "pct_hbm_peak": 100.0 * ALG_BYTES_F32 * n / (e0.elapsed_time(e1) / steps * 1e-3) / 1e9
             / HBM_PEAK_GBS}
@@ -407,14 +441,16 @@ def grains_leg(spfm, torch, inputs, steps, warmup, tsteps=0, coupling="local"):
     tsteps > 1 the temporally blocked kernel fuses that many steps per pass over
     the field (z-chunk 64, the library's size rule for fused steps)."""
     w = inputs.grains512()
-    zc = 64 if tsteps > 1 else ZCHUNK
     steps -= steps % max(tsteps, 1)
-    wall, ev_ms, _ = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel="tiled", steps=steps,
+    # one step per pass: tile and z-chunk tuned at the first (warm-up) step
+    kernel, zc = ("tiled", 64) if tsteps > 1 else ("auto", 0)
+    wall, ev_ms, d = timed_run(spfm, torch, w.shape, w, dtype="f32", kernel=kernel, steps=steps,
                                warmup=warmup, zchunk=zc, tsteps=tsteps, coupling=coupling)
     n = w.shape[0] * w.shape[1] * w.shape[2]
     bytes_per_point = ALG_BYTES_F32 / max(tsteps, 1)
     return {"value": n * steps / wall / 1e9, "unit": "GLUPS", "points": n, "grains": len(w.radii),
-            "coupling": coupling, "steps": steps, "tsteps": max(tsteps, 1), "zchunk": zc,
+            "coupling": coupling, "steps": steps, "tsteps": max(tsteps, 1), "zchunk": d["zchunk"],
+            "tile": d["tile"],
             "ms_per_step": wall * 1e3 / steps, "kernel_ms_per_step": ev_ms / steps,
             "pct_hbm_peak": 100.0 * bytes_per_point * n / (ev_ms / steps * 1e-3) / 1e9
             / HBM_PEAK_GBS}
@@ -670,8 +706,11 @@ def main():
     f32 = f64 = None
     if args.only in ("", "f32"):
         print("leg: f32 headline", file=sys.stderr, flush=True)
+        # the kernel configuration the counter passes ran (tuned there), else tuned here
+        tile = traffic["tile"] if traffic else args.tile
+        zc = traffic["zchunk"] if traffic else args.zchunk
         reps, d = headline_leg(spfm, torch, w, steps=args.steps, warmup=args.warmup,
-                               repeats=max(1, args.repeats), coupling=args.coupling)
+                               repeats=max(1, args.repeats), coupling=args.coupling, tile=tile, zchunk=zc)
         f32 = {"reps": reps, "diag": d}
     if args.only in ("", "f64"):
         print("leg: f64 plain", file=sys.stderr, flush=True)
@@ -711,7 +750,7 @@ def main():
                                    "Gamma=M=dx=1, dt=0.1, 26 neighbours, TI_n local normal, "
                                    "FP32 tiled kernel",
                        "points": npts, "stencil": 26, "coupling": args.coupling,
-                       "kernel": "tiled", "zchunk": f32["diag"]["zchunk"]},
+                       "kernel": "tiled", "tile": f32["diag"]["tile"], "zchunk": f32["diag"]["zchunk"]},
             "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
             "hbm_achieved_gbs": achieved,
             "roofline": roofline,

@@ -137,6 +137,13 @@ typedef struct {
     const double *batch_wall_sin; /* batches with walls: 6 values per grid, wall_sin of grid i at
                            6 i (read at spfm_batch_create only); NULL = wall_sin for every grid.
                            Ignored by single contexts */
+    int32_t tile[2];    /* tiled kernel: tile column (x, y) of one block, {0, 0} = chosen by the
+                           library: 16 x 8 (F32 TI_n) or 64 x 8 untuned, and with kernel AUTO the
+                           fastest compiled shape timed at the first step together with the
+                           z-chunk.  Compiled shapes: 16x8, 32x8, 64x8, 16x16, 32x16, 64x16 for
+                           F32 without walls and h3; 64x8, 32x8, 16x8 for F64 TI_n; 16x8 (F32
+                           TI_n) or 64x8 otherwise.  Another shape is SPFM_E_INVAL.  Results do
+                           not depend on the shape */
 } spfm_options;
 
 typedef struct {
@@ -168,6 +175,7 @@ typedef struct {
     int32_t walls;             /* walled axes (bit mask) */
     int32_t interp;            /* interpolation function (spfm_options.interp) */
     int32_t conserve_volume;
+    int32_t tile_x, tile_y;    /* tile column of the tiled kernel (after tuning); 0 for other kernels */
 } spfm_info;
 
 /* Shape of a particle from its phi = 1/2 contour (Sec. 3.3, Eq. 8-10 at
@@ -275,6 +283,16 @@ spfm_status spfm_energy(spfm_ctx *ctx, int with_mu, double *out);
 spfm_status spfm_ray_radii(spfm_ctx *ctx, const double centre[3], int32_t n, const double *dirs,
                            double *radii);
 
+/* Total force on the interfaces of the current field (FP64 compensated sum;
+ * synchronises): F = sum_p sum_k gamma_j nu_j (lambda^2 / |r_k|^2 D_k -
+ * g_k'(phi_p)), the system sum of the bracket of Eq. 4 (the interface part of
+ * the functional derivative of Eq. 1, Sec. 2.1), in units of 1/dx^2 with the
+ * context's model and stencil; walled grids take their Eq. 7 ghost values.  It
+ * vanishes for an ideal front wherever the model is translationally
+ * invariant, and oscillates with the front's position on the grid otherwise
+ * (the grid-friction force of Fig. 3).  Evaluated from the field alone: no
+ * step is taken and the field is unchanged. */
+spfm_status spfm_force(spfm_ctx *ctx, double *out);
 /* Change the homogeneous driving force mu of the mu h(phi) term of Eq. 1
  * (Sec. 2.1; it enters the step of Eq. 2 as -2 M mu h'(phi) / (3 lambda Gamma)).
  * Re-checks the explicit stability bound (SPFM_E_UNSTABLE, mu unchanged) and
@@ -339,6 +357,13 @@ int64_t spfm_batch_points(const spfm_batch *b);
 int32_t spfm_batch_zchunk(const spfm_batch *b);
 /* The step kernel the batch uses: SPFM_KERNEL_TILED or SPFM_KERNEL_RESIDENT; -1 for NULL. */
 int32_t spfm_batch_kernel(const spfm_batch *b);
+/* What the batch runs (after tuning, if any): kernel, tile column and leading
+ * z-chunk of the tiled kernel (0 for the resident one), grid and point counts. */
+typedef struct {
+    int32_t kernel, tile_x, tile_y, zchunk, grids;
+    int64_t points;
+} spfm_batch_info;
+spfm_status spfm_batch_get_info(const spfm_batch *b, spfm_batch_info *out);
 
 /* Host-only helpers (no HIP call): the calibration C_Gamma(lambda/dx) used
  * when C_Gamma <= 0, and the explicit stability bound for a parameter set

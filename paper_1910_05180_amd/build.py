@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["step_kernels.hip", "resident.hip", "temporal.hip", "walls.hip", "volume.hip", "reduce.hip", "init.hip",
+SOURCES = ["step_kernels.hip", "step_local_tiled.hip", "step_local_batched.hip", "step_global.hip",
+           "step_cf.hip", "resident.hip", "force.hip", "temporal.hip", "walls.hip", "volume.hip", "reduce.hip", "init.hip",
            "host_math.cpp", "api.cpp"]
 LIB = os.path.join(HERE, "libspfm.so")
 OBJDIR = os.path.join(ROOT, "_build")

@@ -50,6 +50,7 @@ struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
     int tsteps;   // steps per launch (temporal blocking), 1 = one step
+    int tile;     // tile shape of the tiled kernel asked for (TileShape), -1 = library choice
     int conserve_volume;   // mu chosen at every step so that sum phi is constant
     int walls;    // bit d: contact-angle walls on axis d
     double wall_sin[6];
@@ -106,6 +107,20 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
             return fail(SPFM_E_INVAL, "the resident kernel takes single steps at fixed mu");
     }
     if (o.zchunk < 0 || o.zchunk > 4096) return fail(SPFM_E_INVAL, "zchunk must be in 0..4096");
+    r->tile = -1;
+    if (o.tile[0] != 0 || o.tile[1] != 0) {
+        int t = -1;
+        for (int k = 0; k < kNumTileShapes; ++k)
+            if (tile_tx(k) == o.tile[0] && tile_ty(k) == o.tile[1]) t = k;
+        const int kc = kernel_coupling(o.coupling, o.interp);
+        if (t < 0 || !tile_compiled(o.dtype == SPFM_F32, kc, o.walls != 0, t) ||
+            o.kernel == SPFM_KERNEL_PLAIN || o.kernel == SPFM_KERNEL_RESIDENT)
+            return fail(SPFM_E_INVAL,
+                        "tile %d x %d is not compiled for this dtype, coupling and walls (or kernel), "
+                        "see spfm_options.tile",
+                        o.tile[0], o.tile[1]);
+        r->tile = t;
+    }
     if (o.tsteps < 0 || o.tsteps > 4) return fail(SPFM_E_INVAL, "tsteps must be in 0..4");
     if (o.tsteps > 1 && (o.dtype != SPFM_F32 || o.kernel == SPFM_KERNEL_PLAIN))
         return fail(SPFM_E_INVAL, "tsteps > 1 needs dtype F32 and the tiled kernel");
@@ -392,7 +407,9 @@ struct spfm_ctx {
     }
 
     int zlen = kTileZ;        // planes per block of the tiled kernel (the leading chunks)
-    bool auto_kernel = false; // SPFM_KERNEL_AUTO: choose zlen by timing at the first step
+    int tile = kTile64x8;     // tile shape of the tiled kernel (TileShape)
+    bool tune_z = false;      // SPFM_KERNEL_AUTO without zchunk: time z-chunks at the first step
+    bool tune_tile = false;   // SPFM_KERNEL_AUTO without tile: time tile shapes at the first step
     bool tuned = false;
     // Work items of the tiled kernel (tile_schedule of the stored grid for zlen).
     TileItem* d_items = nullptr;
@@ -426,12 +443,12 @@ struct spfm_ctx {
         if (r.dtype == SPFM_F64) {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
-                    : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, d_items,
-                                                nitems, (const WallCoef<double>*)d_wall, stream);
+                    : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, tile,
+                                                d_items, nitems, (const WallCoef<double>*)d_wall, stream);
         } else {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
-                    : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, d_items,
+                    : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, tile, d_items,
                                                nitems, (const WallCoef<float>*)d_wall, stream);
         }
         if (e != hipSuccess || !r.conserve_volume) return e;
@@ -485,8 +502,9 @@ struct spfm_batch {
     int nitems = 0;
     size_t items_cap = 0;
     std::vector<GridDims> dims;
-    int tx = 16, zlen = kTileZ;
-    bool auto_zlen = false, tuned = false;
+    int tile = kTile16x8, zlen = kTileZ;
+    bool tune_z = false, tune_tile = false, tuned = false;
+    bool walled_f32 = false;
     // Many grids, often larger than the last-level cache together: tile rows
     // are dealt to the XCDs in contiguous groups.
     static constexpr bool kSpreadRows = false;
@@ -513,7 +531,7 @@ struct spfm_batch {
     hipError_t launch_one(int from) {
         if (resident) return launch_resident(from, 1 - from, 1);
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
-                                   walls ? d_wall : nullptr, stencil, coupling, stream);
+                                   walls ? d_wall : nullptr, stencil, coupling, tile, stream);
     }
     // Grid i as a dense array: its region of the current buffer, or (with walls)
     // its interior packed into its region of the other buffer, which the next
@@ -666,9 +684,9 @@ std::vector<TileItem> tile_schedule(const std::vector<GridDims>& grids, int tx, 
 // z-chunks of zb planes (after the stream has drained: no launch may still read
 // the old table); captured graphs hold the old table and are dropped.
 template <typename Obj>
-spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tx, int zb) {
+spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tile, int zb) {
     HIP_TRY(hipStreamSynchronize(o->stream));
-    const std::vector<TileItem> items = tile_schedule(dims, tx, kTileY, zb, Obj::kSpreadRows);
+    const std::vector<TileItem> items = tile_schedule(dims, tile_tx(tile), tile_ty(tile), zb, Obj::kSpreadRows);
     if (items.size() > 0x7fffffff) return fail(SPFM_E_INVAL, "too many tiles");
     if (items.size() > o->items_cap) {
         if (o->d_items) (void)hipFree(o->d_items);
@@ -686,46 +704,45 @@ spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tx, int 
     HIP_TRY(hipStreamSynchronize(o->stream));
     o->nitems = (int)items.size();
     o->zlen = zb;
+    o->tile = tile;
     o->graphs.clear();
     return SPFM_OK;
 }
-spfm_status set_schedule(spfm_ctx* c, int zb) {
-    return set_schedule(c, {GridDims{c->r.sx, c->r.sy, c->r.sz}},
-                        tile_x(c->r.dtype == SPFM_F32, c->r.p.coupling), zb);
+spfm_status set_schedule(spfm_ctx* c, int tile, int zb) {
+    return set_schedule(c, {GridDims{c->r.sx, c->r.sy, c->r.sz}}, tile, zb);
 }
-spfm_status set_schedule(spfm_batch* b, int zb) { return set_schedule(b, b->dims, b->tx, zb); }
+spfm_status set_schedule(spfm_batch* b, int tile, int zb) { return set_schedule(b, b->dims, tile, zb); }
 
-// SPFM_KERNEL_AUTO: time the step for the candidate z-chunk lengths (those up
-// to twice the deepest grid) on the current field, reading the current buffer
-// and writing the other one, which the next step overwrites anyway.  The length
-// of the size rule (the current one) is kept unless another is at least 2%
-// faster: the first steps of a process run while the clocks still ramp up, and
-// differences below that are within the noise of these short timings.  When
-// the size rule has already shortened the chunks below full (zlen < zfull),
-// the work cannot fill the GPU, a launch takes about as long as the host needs
-// to issue it, and timing single launches would measure the host: the rule's
-// length is kept untimed.  The result of a step does not depend on the chunk
-// length.
+// SPFM_KERNEL_AUTO: time the step for the candidate (tile shape, z-chunk)
+// pairs on the current field, reading the current buffer and writing the other
+// one, which the next step overwrites anyway.  The untuned pair (the current
+// one: the default shape and the size rule's length) is kept unless another is
+// at least 2% faster: the first steps of a process run while the clocks still
+// ramp up, and differences below that are within the noise of these short
+// timings.  When the size rule has already shortened the chunks below full
+// (zlen < zfull), the work cannot fill the GPU, a launch takes about as long
+// as the host needs to issue it, and timing single launches would measure the
+// host: the untuned pair is kept.  The result of a step does not depend on the
+// tile shape or the chunk length.
+struct TuneCand {
+    int tile, z;
+};
 template <typename Obj>
-spfm_status tune_zchunk(Obj* o, const int* cand, int ncand, int nz, int zfull) {
+spfm_status tune_schedule(Obj* o, const std::vector<TuneCand>& cand, int zfull) {
     o->tuned = true;
-    const int rule = o->zlen;
-    if (rule < zfull) return SPFM_OK;
+    const TuneCand rule{o->tile, o->zlen};
+    if (rule.z < zfull || cand.size() < 2) return SPFM_OK;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
-    float best[8];
-    for (float& v : best) v = 1e30f;
-    ncand = std::min(ncand, 8);
+    std::vector<float> best(cand.size(), 1e30f);
     spfm_status st = SPFM_OK;
     // Three sweeps over the candidates (the first also warms clocks and caches);
     // each candidate: two untimed launches, then five timed ones; the best of
     // the sweeps counts.
     for (int sweep = 0; sweep < 3 && st == SPFM_OK; ++sweep) {
-        for (int ci = 0; ci < ncand; ++ci) {
-            const int z = cand[ci];
-            if (ci > 0 && z > 2 * nz) break;
-            st = set_schedule(o, z);   // also sets zlen, which the temporal kernel takes
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+            st = set_schedule(o, cand[ci].tile, cand[ci].z);   // zlen also steers the temporal kernel
             if (st != SPFM_OK) break;
             hipError_t e = hipSuccess;
             for (int i = 0; i < 7 && e == hipSuccess; ++i) {
@@ -737,33 +754,62 @@ spfm_status tune_zchunk(Obj* o, const int* cand, int ncand, int nz, int zfull) {
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
-            if (ms < best[ci]) best[ci] = ms;
+            best[ci] = std::min(best[ci], ms);
         }
     }
-    int bi = 0;
-    for (int ci = 1; ci < ncand; ++ci)
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
         if (best[ci] < best[bi]) bi = ci;
-    for (int ci = 0; ci < ncand; ++ci)
-        if (cand[ci] == rule && best[ci] <= 1.02f * best[bi]) bi = ci;
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+        if (cand[ci].tile == rule.tile && cand[ci].z == rule.z && best[ci] <= 1.02f * best[bi]) bi = ci;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != SPFM_OK) return st;
-    return set_schedule(o, cand[bi]);
+    if (st != SPFM_OK) {
+        (void)set_schedule(o, rule.tile, rule.z);
+        return st;
+    }
+    return set_schedule(o, cand[bi].tile, cand[bi].z);
+}
+
+// Candidate pairs: every compiled tile shape (when the shape is tuned) with
+// every chunk length up to twice the deepest grid (when the length is tuned);
+// the untuned pair first.
+std::vector<TuneCand> tune_candidates(int tile, int zlen, bool tune_tile, bool tune_z, bool f32, int C,
+                                      bool walled, const int* zs, int nzs, int depth) {
+    std::vector<TuneCand> out{TuneCand{tile, zlen}};
+    for (int t = 0; t < kNumTileShapes; ++t) {
+        if (!(t == tile || (tune_tile && tile_compiled(f32, C, walled, t)))) continue;
+        for (int i = 0; i < nzs; ++i) {
+            const int z = zs[i];
+            if (!(z == zlen || tune_z) || (i > 0 && z > 2 * depth)) continue;
+            if (t == tile && z == zlen) continue;
+            out.push_back(TuneCand{t, z});
+        }
+    }
+    return out;
 }
 
 spfm_status autotune(spfm_ctx* c) {
     c->tuned = true;
     if (c->r.kernel != SPFM_KERNEL_TILED) return SPFM_OK;
-    static const int cand[4] = {8, 16, 32, 64};
-    return tune_zchunk(c, cand, 4, c->r.p.nz, c->r.tsteps > 1 ? 2 * kTileZ : kTileZ);
+    static const int zs[4] = {8, 16, 32, 64};
+    const bool f32 = c->r.dtype == SPFM_F32;
+    const int C = kernel_coupling(c->r.p.coupling, c->r.p.interp);
+    // fused steps (tsteps > 1) run the temporal kernel's own tile; only its chunk is timed
+    const bool tt = c->tune_tile && c->r.tsteps == 1;
+    return tune_schedule(c, tune_candidates(c->tile, c->zlen, tt, c->tune_z, f32, C, c->r.walls != 0, zs, 4,
+                                            c->r.p.nz),
+                         c->r.tsteps > 1 ? 2 * kTileZ : kTileZ);
 }
 
 // Batches: small grids gain from chunks down to 4 planes.
 spfm_status autotune(spfm_batch* b) {
-    static const int cand[5] = {4, 8, 16, 32, 64};
+    static const int zs[5] = {4, 8, 16, 32, 64};
     int nz = 1;
     for (const GridDims& d : b->dims) nz = std::max(nz, d.nz);
-    return tune_zchunk(b, cand, 5, nz, kTileZ);
+    return tune_schedule(b, tune_candidates(b->tile, b->zlen, b->tune_tile, b->tune_z, true, b->coupling,
+                                            b->walls != 0, zs, 5, nz),
+                         kTileZ);
 }
 
 template <typename Obj>
@@ -890,13 +936,16 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
         return fail(SPFM_E_HIP, "hipGetDevice failed");
     }
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
-    c->auto_kernel = (!opt || opt->kernel == SPFM_KERNEL_AUTO) && !(opt && opt->zchunk > 0);
+    const bool autok = !opt || opt->kernel == SPFM_KERNEL_AUTO;
+    c->tune_z = autok && !(opt && opt->zchunk > 0);
+    c->tune_tile = autok && r.tile < 0;
     const bool f32 = r.dtype == SPFM_F32;
     const bool temporal = r.tsteps > 1;
-    const int tx = temporal ? 64 : tile_x(f32, r.p.coupling);      // temporal: 64 x 8
+    c->tile = r.tile >= 0 ? r.tile : default_tile(f32, kernel_coupling(r.p.coupling, r.p.interp));
+    const int tx = temporal ? 64 : tile_tx(c->tile), ty = temporal ? 8 : tile_ty(c->tile);   // temporal: 64 x 8
     c->zlen = (opt && opt->zchunk > 0)
                   ? opt->zchunk
-                  : default_zlen({GridDims{r.sx, r.sy, r.sz}}, tx, kTileY, !temporal,
+                  : default_zlen({GridDims{r.sx, r.sy, r.sz}}, tx, ty, !temporal,
                                  temporal ? (int64_t)1 << 20 : (int64_t)1 << 19, 8);
     const size_t bytes = c->stored_bytes();
     if (opt && opt->d_phi[0]) {
@@ -952,7 +1001,7 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
         }
     }
     if (r.kernel == SPFM_KERNEL_TILED) {   // single tiled steps (also the remainder of fused ones)
-        st = set_schedule(c, c->zlen);
+        st = set_schedule(c, c->tile, c->zlen);
         if (st != SPFM_OK) { spfm_destroy(c); return st; }
     }
     *out = c;
@@ -1185,6 +1234,31 @@ spfm_status spfm_energy(spfm_ctx* c, int with_mu, double* out) {
     return SPFM_OK;
 }
 
+spfm_status spfm_force(spfm_ctx* c, double* out) {
+    if (!c || !out) return fail(SPFM_E_INVAL, "NULL argument");
+    const Params& p = c->r.p;
+    const int S = p.stencil, C = kernel_coupling(p.coupling, p.interp);
+    const bool f64 = c->r.dtype == SPFM_F64;
+    void* field = c->buf[c->cur];
+    void* dens = c->buf[1 - c->cur];   // dead between steps
+    hipError_t e = hipSuccess;
+    if (c->r.walls)   // the ghost layers of the current field from Eq. 7
+        e = f64 ? launch_fill_walls<double>((double*)field, c->wd, c->nghost, c->stream)
+                : launch_fill_walls<float>((float*)field, c->wf, c->nghost, c->stream);
+    if (e == hipSuccess)
+        e = f64 ? launch_force_density<double>((const double*)field, (double*)dens, c->kd0, c->r.walls, S, C,
+                                               c->stream)
+                : launch_force_density<float>((const float*)field, (float*)dens, c->kf0, c->r.walls, S, C,
+                                              c->stream);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "force: %s", hipGetErrorString(e));
+    spfm_status st = c->red.run(dens, c->r.dtype, c->points(), c->stream);
+    if (st != SPFM_OK) return st;
+    // the density is dt A times the bracket of Eq. 4 summed over directions
+    const double A = 2.0 * p.M / (3.0 * p.C_Gamma * p.lambda * p.lambda);
+    *out = c->red.h_out->sum_phi / (p.dt * A);
+    return SPFM_OK;
+}
+
 spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
@@ -1206,7 +1280,7 @@ spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
 spfm_status spfm_step(spfm_ctx* c, int64_t n) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (c->r.kernel == SPFM_KERNEL_RESIDENT) return run_resident(c, n);
-    if (n > 0 && c->auto_kernel && !c->tuned) {
+    if (n > 0 && (c->tune_z || c->tune_tile) && !c->tuned) {
         spfm_status st = autotune(c);
         if (st != SPFM_OK) return st;
         c->graphs.clear();
@@ -1244,6 +1318,8 @@ spfm_status spfm_get_info(const spfm_ctx* c, spfm_info* o) {
     o->dt_max = c->r.dt_max;
     o->stencil = p.stencil; o->coupling = p.coupling; o->dtype = c->r.dtype; o->kernel = c->r.kernel;
     o->zchunk = c->zlen;
+    o->tile_x = c->r.kernel == SPFM_KERNEL_TILED ? tile_tx(c->tile) : 0;
+    o->tile_y = c->r.kernel == SPFM_KERNEL_TILED ? tile_ty(c->tile) : 0;
     o->tsteps = c->r.tsteps;
     o->walls = c->r.walls;
     o->interp = c->r.p.interp;
@@ -1337,11 +1413,14 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         return fail(SPFM_E_INVAL, "the resident kernel holds at most %d stored points per grid",
                     resident_max_cells((int)sizeof(float)));
     }
+    const int asked_tile = b->r[0].tile;   // the same options resolve every grid alike
     b->resident = o.kernel == SPFM_KERNEL_RESIDENT ||
-                  (o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0 && largest <= kResidentAutoCells);
-    b->tx = tile_x(true, o.coupling);
-    b->auto_zlen = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0;
-    const int zb = o.zchunk > 0 ? o.zchunk : default_zlen(dims, b->tx, kTileY, true, (int64_t)1 << 19, 4);
+                  (o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0 && asked_tile < 0 && largest <= kResidentAutoCells);
+    b->tile = asked_tile >= 0 ? asked_tile : default_tile(true, b->coupling);
+    b->tune_z = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0;
+    b->tune_tile = o.kernel == SPFM_KERNEL_AUTO && asked_tile < 0;
+    const int zb = o.zchunk > 0 ? o.zchunk
+                                : default_zlen(dims, tile_tx(b->tile), tile_ty(b->tile), true, (int64_t)1 << 19, 4);
     b->total = off;
     const size_t bytes = (size_t)off * sizeof(float);
     if (hipMalloc(&b->buf[0], bytes) != hipSuccess || hipMalloc(&b->buf[1], bytes) != hipSuccess ||
@@ -1362,7 +1441,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         spfm_batch_destroy(b);
         return fail(SPFM_E_HIP, "batch upload failed");
     }
-    st = set_schedule(b, zb);
+    st = set_schedule(b, b->tile, zb);
     if (st != SPFM_OK) { spfm_batch_destroy(b); return st; }
     *out = b;
     return SPFM_OK;
@@ -1436,7 +1515,7 @@ spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on
 spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
     if (!b) return fail(SPFM_E_INVAL, "batch is NULL");
     if (b->resident) return run_resident(b, n);
-    if (n > 0 && b->auto_zlen && !b->tuned) {
+    if (n > 0 && (b->tune_z || b->tune_tile) && !b->tuned) {
         spfm_status st = autotune(b);
         if (st != SPFM_OK) return st;
     }
@@ -1465,6 +1544,17 @@ int32_t spfm_batch_zchunk(const spfm_batch* b) { return b ? b->zlen : 0; }
 
 int32_t spfm_batch_kernel(const spfm_batch* b) {
     return b ? (b->resident ? SPFM_KERNEL_RESIDENT : SPFM_KERNEL_TILED) : -1;
+}
+
+spfm_status spfm_batch_get_info(const spfm_batch* b, spfm_batch_info* o) {
+    if (!b || !o) return fail(SPFM_E_INVAL, "NULL argument");
+    o->kernel = b->resident ? SPFM_KERNEL_RESIDENT : SPFM_KERNEL_TILED;
+    o->tile_x = b->resident ? 0 : tile_tx(b->tile);
+    o->tile_y = b->resident ? 0 : tile_ty(b->tile);
+    o->zchunk = b->resident ? 0 : b->zlen;
+    o->grids = b->n;
+    o->points = b->points;
+    return SPFM_OK;
 }
 
 double spfm_calibrate_cgamma(double lambda_over_dx, int coupling) {

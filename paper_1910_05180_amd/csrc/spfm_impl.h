@@ -179,7 +179,15 @@ __device__ __forceinline__ void shell_laplacian(At at, T p, T& s1, T& s2, T& s3)
 // second differences and grad(gx,gy,gz), which sets the central differences of
 // psi' across the point (LOCAL only; called only where phi(1-phi) != 0).
 template <typename T, int S, int C, typename Grad>
+__device__ __forceinline__ T point_incr(T p, T s1, T s2, T s3, Grad grad, const StepCoef<T>& k);
+template <typename T, int S, int C, typename Grad>
 __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const StepCoef<T>& k) {
+    return p + point_incr<T, S, C>(p, s1, s2, s3, grad, k);
+}
+// The increment of one forward-Euler step at the point, dt d_t phi (point_core
+// adds it to p).
+template <typename T, int S, int C, typename Grad>
+__device__ __forceinline__ T point_incr(T p, T s1, T s2, T s3, Grad grad, const StepCoef<T>& k) {
     const T x = p * (T(1) - p);
     const T u = fma(T(-2), p, T(1));
     T upd = k.K[0] * s1;
@@ -327,7 +335,7 @@ __device__ __forceinline__ T point_core(T p, T s1, T s2, T s3, Grad grad, const 
     } else {
         upd = fma(-k.b, x, upd);
     }
-    return p + upd;
+    return upd;
 }
 
 // Per-column values a thread of a z-marching sweep keeps for one plane: the
@@ -391,6 +399,15 @@ __device__ __forceinline__ T point_update(At at, Grad grad, const StepCoef<T>& k
     return point_core<T, S, C>(p, s1, s2, s3, grad, k);
 }
 
+// dt d_t phi at one point (the increment of point_update).
+template <typename T, int S, int C, typename At, typename Grad>
+__device__ __forceinline__ T point_rate_dt(At at, Grad grad, const StepCoef<T>& k) {
+    const T p = at(0, 0, 0);
+    T s1, s2, s3;
+    shell_laplacian<T, S>(at, p, s1, s2, s3);
+    return point_incr<T, S, C>(p, s1, s2, s3, grad, k);
+}
+
 // Contact-angle walls (walls.hip): stored dims, the walled axes (bit d = axis d)
 // and the composed Eq. 7 coefficient for every ghost class (cx, cy, cz in
 // {-1, 0, 1}: below the low wall, inside, above the high wall), at index
@@ -426,8 +443,18 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 // (Eq. 7), so no fill launch is needed.
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
-                             const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
+                             int tile, const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
                              hipStream_t s);
+// The tiled and batched steps of one kernel coupling (sweep.h; instantiated in
+// the per-coupling translation units).
+template <typename T, int C>
+hipError_t launch_tiled_coupling(const T* in, T* out, const StepCoef<T>& k, int stencil, int tile,
+                                 const TileItem* items, int nitems, const WallCoef<T>* wall,
+                                 hipStream_t s);
+template <int C>
+hipError_t launch_batched_coupling(const float* in, float* out, const StepCoef<float>* coef,
+                                   const int64_t* offset, int stencil, int tile, const TileItem* items,
+                                   int nitems, const WallCoef<float>* wall, hipStream_t s);
 // TB = tsteps (2..4) steps per launch, FP32 (temporal.hip).
 hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<float>& k, int stencil,
                                 int coupling, int tsteps, int zlen, hipStream_t s);
@@ -435,7 +462,7 @@ hipError_t launch_step_temporal(const float* in, float* out, const StepCoef<floa
 // with d_wall (one entry per instance) the grids have walls, as for the tiled step.
 hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCoef<float>* d_coef,
                                const int64_t* d_offset, const TileItem* d_items, int nitems,
-                               const WallCoef<float>* d_wall, int stencil, int coupling,
+                               const WallCoef<float>* d_wall, int stencil, int coupling, int tile,
                                hipStream_t s);
 // Resident step (resident.hip): one block per grid keeps the stored grid in LDS
 // (two copies, 2 x cells x sizeof(T) <= kResidentLdsBytes) and takes nsteps steps
@@ -447,18 +474,35 @@ template <typename T>
 hipError_t launch_step_resident(const T* buf_in, T* buf_out, const StepCoef<T>* d_coef,
                                 const int64_t* d_offset, const WallCoef<T>* d_wall, int ngrids,
                                 int max_cells, int nsteps, int stencil, int coupling, hipStream_t s);
-// Tiles of the single-step tiled kernels: a block marches one tile column
-// kTileX x kTileY along z, each of its waves computing a 16 x 4 patch.  FP32
-// TI_n uses 16 x 8 columns (two waves): its full-coupling branch makes the
-// work of a wave uneven from plane to plane, and a block of few waves loses
-// little at its barriers while the SIMD runs waves of other blocks.  The other
-// kernels use 64 x 8 columns (eight waves), whose halo is relatively smaller.
-constexpr int tile_x(bool f32, int coupling) { return f32 && coupling == kLocal ? 16 : 64; }
-constexpr int kTileY = 8;
+// Tile shapes of the single-step tiled kernels: a block marches one tile
+// column TX x TY along z, each of its waves computing a 16 x 4 patch.  The
+// untuned shapes: FP32 TI_n uses 16 x 8 columns (two waves): its full-coupling
+// branch makes the work of a wave uneven from plane to plane, and a block of
+// few waves loses little at its barriers while the SIMD runs waves of other
+// blocks; the other kernels use 64 x 8 columns (eight waves), whose halo is
+// relatively smaller.  The autotuner times the other compiled shapes.
+enum TileShape : int {
+    kTile16x8 = 0, kTile32x8 = 1, kTile64x8 = 2, kTile16x16 = 3, kTile32x16 = 4, kTile64x16 = 5,
+    kNumTileShapes = 6
+};
+constexpr int tile_tx(int t) {
+    return (t == kTile16x8 || t == kTile16x16) ? 16 : ((t == kTile32x8 || t == kTile32x16) ? 32 : 64);
+}
+constexpr int tile_ty(int t) { return t >= kTile16x16 ? 16 : 8; }
+constexpr int default_tile(bool f32, int coupling) { return f32 && coupling == kLocal ? kTile16x8 : kTile64x8; }
+// Shapes compiled for a kernel variant (kernel coupling C, walled or not): every
+// shape for the FP32 steps with h3 (TI_n, TI_<hkl>, CF); 64 x 8, 32 x 8 and
+// 16 x 8 for FP64 TI_n; the untuned shape alone for walled grids (small, launch
+// bound) and for CF with h5 or h_Abel.
+constexpr bool tile_compiled(bool f32, int C, bool W, int t) {
+    return t == default_tile(f32, C) ||
+           (!W && (f32 ? C <= kCF : (C == kLocal && (t == kTile32x8 || t == kTile16x8))));
+}
 constexpr int kWaveX = 16;
-// LDS row stride of a staged halo plane: 80 for 64-wide tiles puts the four
-// rows of a 16 x 4 wave patch in distinct LDS banks.
-constexpr int lds_row(int tx) { return tx == 64 ? 80 : tx + 2; }
+// LDS row stride of a staged halo plane.  48 and 80 put the rows of a 16 x 4
+// wave patch in distinct LDS banks; the 16-wide tiles keep 18, the smallest,
+// since their blocks are many per CU and larger rows would cap them by LDS.
+constexpr int lds_row(int tx) { return tx == 16 ? 18 : (tx == 32 ? 48 : 80); }
 constexpr int kTileZ = 32;   // default planes per block (the z-chunk is a launch argument)
 constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
 
@@ -482,6 +526,14 @@ hipError_t launch_box_copy(T* dst, int dnx, int dny, int dx0, int dy0, int dz0, 
 template <typename T>
 hipError_t launch_init_front(T* phi, int nx, int ny, int nz, double dx, double lambda,
                              const double n[3], double offset, hipStream_t s);
+
+// Force density of the field (force.hip): dt d_t phi without the driving force
+// (coefficients k with mu = 0) at every interior point of the stored grid
+// (walled axes wx, wy, wz skip one ghost layer per end), packed densely into
+// dens (nx*ny*nz interior values).  Ghost layers must hold their Eq. 7 values.
+template <typename T>
+hipError_t launch_force_density(const T* phi, T* dens, const StepCoef<T>& k, int walls, int stencil,
+                                int coupling, hipStream_t s);
 
 // Constant volume and contour statistics (volume.hip).  d_part holds
 // kReduceBlocks x 8 doubles; d_state 2 doubles (g, mu); d_out 7 doubles

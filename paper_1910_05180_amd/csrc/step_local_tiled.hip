@@ -1,0 +1,14 @@
+// TI_n tiled step (sweep.h) for every compiled tile shape, FP32 and FP64.
+#include "sweep.h"
+
+namespace spfm {
+
+template hipError_t launch_tiled_coupling<float, kLocal>(const float*, float*, const StepCoef<float>&,
+                                                         int, int, const TileItem*, int,
+                                                         const WallCoef<float>*, hipStream_t);
+template hipError_t launch_tiled_coupling<double, kLocal>(const double*, double*,
+                                                          const StepCoef<double>&, int, int,
+                                                          const TileItem*, int,
+                                                          const WallCoef<double>*, hipStream_t);
+
+}  // namespace spfm

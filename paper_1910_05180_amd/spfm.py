@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
                 ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6),
                 ("interp", ctypes.c_int32), ("conserve_volume", ctypes.c_int32),
-                ("batch_wall_sin", ctypes.c_void_p)]
+                ("batch_wall_sin", ctypes.c_void_p), ("tile", ctypes.c_int32 * 2)]
 
 
 class Diag(ctypes.Structure):
@@ -66,7 +66,13 @@ class Info(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
                 ("walls", ctypes.c_int32), ("interp", ctypes.c_int32),
-                ("conserve_volume", ctypes.c_int32)]
+                ("conserve_volume", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32), ("grids", ctypes.c_int32), ("points", ctypes.c_int64)]
 
 
 class Contour(ctypes.Structure):
@@ -112,6 +118,7 @@ def load():
         "spfm_ray_radii": ([vp, dp, i32, dp, dp], ctypes.c_int),
         "spfm_energy": ([vp, ctypes.c_int, dp], ctypes.c_int),
         "spfm_set_mu": ([vp, d], ctypes.c_int),
+        "spfm_force": ([vp, dp], ctypes.c_int),
         "spfm_step": ([vp, i64], ctypes.c_int),
         "spfm_diagnostics": ([vp, ctypes.POINTER(Diag)], ctypes.c_int),
         "spfm_get_info": ([vp, ctypes.POINTER(Info)], ctypes.c_int),
@@ -127,6 +134,7 @@ def load():
         "spfm_batch_points": ([vp], i64),
         "spfm_batch_zchunk": ([vp], i32),
         "spfm_batch_kernel": ([vp], i32),
+        "spfm_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
         "spfm_calibrate_cgamma": ([d, ctypes.c_int], d),
         "spfm_stable_dt": ([ctypes.c_int, ctypes.c_int, dp, dp, d, d, d, d, d, d], d),
         "spfm_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -168,7 +176,7 @@ def _stream_handle(stream):
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
              allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None,
-             interp="h3", conserve_volume=False) -> Options:
+             interp="h3", conserve_volume=False, tile=None) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -187,6 +195,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.wall_sin[:] = [float(v) for v in wall_sin] if wall_sin is not None else [0.0] * 6
     o.interp = _INTERPS[interp] if isinstance(interp, str) else int(interp)
     o.conserve_volume = 1 if conserve_volume else 0
+    o.tile[:] = [int(v) for v in tile] if tile is not None else [0, 0]
     return o
 
 
@@ -328,6 +337,12 @@ class Spfm:
                                       float(offset)))
 
     # -- stepping --
+    def force(self) -> float:
+        """Total force of the current field: the system sum of the Eq. 4 bracket."""
+        v = ctypes.c_double()
+        _check(load().spfm_force(self._h, ctypes.byref(v)))
+        return float(v.value)
+
     def set_mu(self, mu: float):
         _check(load().spfm_set_mu(self._h, float(mu)))
 
@@ -410,6 +425,12 @@ class SpfmBatch:
     def kernel(self) -> str:
         """The step kernel in use: "tiled" or "resident"."""
         return {KERNEL_TILED: "tiled", KERNEL_RESIDENT: "resident"}[int(load().spfm_batch_kernel(self._h))]
+
+    def info(self) -> dict:
+        """Kernel, tile column and z-chunk in use (after tuning), grid and point counts."""
+        i = BatchInfo()
+        _check(load().spfm_batch_get_info(self._h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in BatchInfo._fields_}
 
     def init_planar(self, hkls, offsets):
         h = np.ascontiguousarray(np.asarray(hkls, dtype=np.int32).reshape(-1, 3))

@@ -191,3 +191,24 @@ def test_resident_kernel_accepts_the_largest_grid_it_holds(S):
 def test_resident_batch_refuses_a_grid_it_cannot_hold(S):
     st, msg = try_batch(S, [(8, 8, 8), (32, 32, 32)], kernel="resident")
     assert st == -1 and "resident" in msg, msg
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tile=(8, 8)), dict(tile=(16, 4)), dict(tile=(128, 8)),
+    dict(tile=(32, 8), walls=1),                     # walled grids: the default shape only
+    dict(tile=(32, 16), dtype="f64"),                # FP64 TI_n: 64x8, 32x8, 16x8
+    dict(tile=(32, 8), dtype="f64", coupling="cf"),  # FP64 CF: 64x8 only
+    dict(tile=(16, 8), coupling="cf", interp="h5"),  # CF with h5: 64x8 only
+    dict(tile=(16, 8), kernel="plain"), dict(tile=(16, 8), kernel="resident"),
+])
+def test_create_rejects_tiles_not_compiled(S, kw):
+    st, msg = S.try_create((16, 16, 16), **kw)
+    assert st == -1 and "tile" in msg, msg
+
+
+@pytest.mark.parametrize("kw", [dict(tile=(64, 16)), dict(tile=(16, 16), coupling="global"),
+                                dict(tile=(16, 8), dtype="f64"), dict(tile=(64, 8), coupling="cf", interp="habel"),
+                                dict(tile=(16, 8), walls=1)])
+def test_create_accepts_compiled_tiles(S, kw):
+    st, msg = S.try_create((16, 16, 16), **kw)
+    assert st != -1, msg
