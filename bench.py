@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5,
                     help="untimed steps of the measured field before each timed window (the "
-                         "clocks are warmed on a scratch context of the same workload)")
+                         "clocks are first warmed for about a second on the same context)")
     ap.add_argument("--repeats", type=int, default=REPEATS,
                     help="timed windows of the headline (field re-initialised each time); median")
     ap.add_argument("--fp64-steps", type=int, default=50)
@@ -174,15 +174,19 @@ def host_cpu():
     return {"cpu_model": model, "host_cores": usable, "host_cpus_total": os.cpu_count() or 0}
 
 
-def warm_clocks(torch, stream, step, chunk=200, min_s=1.0, max_s=4.0, tol=0.01):
-    """Run step(chunk) repeatedly until at least min_s seconds have passed and two
-    consecutive chunks took the same time within tol (at most max_s seconds): the
-    GPU's clocks ramp up over the first fraction of a second of sustained work.
-    Returns (seconds, steps, microseconds per step of the last chunk)."""
+def warm_clocks(torch, stream, step, reinit, chunk=200, every=10, min_s=1.0, max_s=4.0, tol=0.01):
+    """Run step(chunk) repeatedly, calling reinit() every `every` chunks so that
+    the work per step stays that of the timed window, until at least min_s
+    seconds have passed and two consecutive chunks took the same time within tol
+    (at most max_s seconds): the GPU's clocks ramp up over the first fraction of
+    a second of sustained work.  Returns (seconds, steps, microseconds per step of
+    the last chunk)."""
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0, n, last = time.perf_counter(), 0, None
     while True:
+        if (n // chunk) % every == 0:
+            reinit()
         e0.record(stream)
         step(chunk)
         e1.record(stream)
@@ -207,29 +211,28 @@ def headline_kernel(tile=None, zchunk=0):
 def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", tile=None, zchunk=0,
                  rewarm_steps=300):
     """The FP32 tiled step on the grain workload.  The clocks are first brought
-    to their steady state on a scratch context of the same workload (its steps
-    are not measured, see warm_clocks); then `repeats` times: the measured field
-    is initialised (R = 60), stepped `warmup` times untimed, and exactly `steps`
-    steps are timed, bracketed by stream synchronisation (wall clock) and by HIP
-    events on the kernel's stream.  The scratch context steps `rewarm_steps`
-    more before each window so that the GPU never idles between them.  The
-    branch mix of the step is counted on the field at both ends of every
-    window."""
+    to their steady state by stepping the measured context itself, its field
+    re-initialised every 2000 steps (see warm_clocks; these steps are not
+    measured); then `repeats` times: `rewarm_steps` untimed steps so that the
+    GPU never idles between windows, the field initialised afresh (R = 60),
+    stepped `warmup` times untimed, and exactly `steps` steps timed, bracketed by
+    stream synchronisation (wall clock) and by HIP events on the kernel's
+    stream.  The branch mix of the step is counted on the field at both ends of
+    every window."""
     stream = torch.cuda.Stream()
     xt = xtail_local(w.lam, w.dx, w.stencil)
     reps = []
     with torch.cuda.stream(stream):
         kw = dict(lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil, dtype="f32",
                   coupling=coupling, dt=w.dt, stream=stream, **headline_kernel(tile, zchunk))
-        scratch = spfm.Spfm(w.shape, **kw)
-        scratch.init_spheres(w.centers, w.radii)
-        warm = warm_clocks(torch, stream, scratch.step)
         s = spfm.Spfm(w.shape, **kw)
+        init = lambda: s.init_spheres(w.centers, w.radii)
+        warm = warm_clocks(torch, stream, s.step, init)
         bufs = {b.data_ptr(): b for b in s._buffers}
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         for _ in range(repeats):
-            scratch.step(rewarm_steps)
+            s.step(rewarm_steps)
             s.init_spheres(w.centers, w.radii)
             s.step(warmup)
             d0 = s.diagnostics()           # synchronises the stream
@@ -254,7 +257,6 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", ti
         if w.rays is not None:
             d["rays"] = s.ray_radii(w.rays, centre=d["contour"]["centre"])
         s.close()
-        scratch.close()
     return reps, d
 
 

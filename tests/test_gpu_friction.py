@@ -33,6 +33,23 @@ def oracle_force(coupling, lam, n, c, u):
     return math.fsum(rate.ravel()) / (2 * p.M / (3 * p.C_Gamma * lam * lam))
 
 
+def bracket_scale(lam, n, c):
+    """Sum over the line of the magnitudes of the Laplacian terms of the Eq. 4
+    bracket, lambda^2 sum_k w_k |D_k| / |r_k|^2: the size of what cancels in the
+    force, which sets the FP64 rounding of both sums."""
+    shape = (1, 1, 300)
+    p = oracle.params(shape, lam=lam, stencil=26, coupling="local", mu=0.0)
+    f = oracle.fill_walls(p, oracle.pad(oracle.front(shape, n, c, lam=lam), 7), 7, oracle.front_sin_alpha(n))
+    total = 0.0
+    for k in range(13):
+        r, shell = oracle.direction(k)
+        w = p.gamma[shell - 1] * oracle.nu(shell) / shell
+        d = (f[1 + r[2], 1 + r[1], 1 + r[0]:301 + r[0]] + f[1 - r[2], 1 - r[1], 1 - r[0]:301 - r[0]]
+             - 2.0 * f[1, 1, 1:301])
+        total += lam * lam * w * float(np.abs(d).sum())
+    return total
+
+
 def rot(axis, deg):
     t = math.radians(deg)
     if axis == "001":
@@ -50,7 +67,15 @@ def test_front_force_matches_oracle(S, coupling, u, lam, axis, deg):
     got = friction.front_forces(S, coupling=coupling, lam=lam, n=n, shifts=shifts, u=u)
     for c, f in zip(shifts, got):
         ref = oracle_force(coupling, lam, n, c, u)
-        assert abs(f - ref) <= 1e-12 * max(1.0, abs(ref)), (c, f, ref)
+        scale = bracket_scale(lam, n, c)
+        print(f"F {coupling} lam={lam} {axis}:{deg} c={c}: {f:.6e} oracle {ref:.6e} scale {scale:.2f}",
+              flush=True)
+        # Both sides sum FP64 terms of the size `scale` that cancel.  The
+        # oracle evaluates the derivative of Eq. 6 literally (tanh, 1 - a^2 u^2),
+        # which at lambda~ = 1 (a up to 0.997) rounds to a few 1e-12 of the scale:
+        # on the TI_n front, which feels no force, it gives -5.4e-12 and -9.9e-12
+        # where the device's hyperbolic form gives below 1e-13.
+        assert abs(f - ref) <= 2e-11 * max(1.0, scale), (c, f, ref, scale)
 
 
 def test_fig3_on_the_device(S):
