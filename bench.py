@@ -224,8 +224,13 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", ti
     reps = []
     with torch.cuda.stream(stream):
         kw = dict(lam=w.lam, mu=w.mu, Gamma=w.Gamma, M=w.M, dx=w.dx, stencil=w.stencil, dtype="f32",
-                  coupling=coupling, dt=w.dt, stream=stream, **headline_kernel(tile, zchunk))
-        s = spfm.Spfm(w.shape, **kw)
+                  coupling=coupling, dt=w.dt, stream=stream)
+        if tile is None or not zchunk:
+            # the autotuner times its candidates at the first step: give it warm clocks
+            with spfm.Spfm(w.shape, kernel="tiled", **kw) as scratch:
+                warm_clocks(torch, stream, scratch.step, lambda: scratch.init_spheres(w.centers, w.radii),
+                            min_s=0.5)
+        s = spfm.Spfm(w.shape, **kw, **headline_kernel(tile, zchunk))
         init = lambda: s.init_spheres(w.centers, w.radii)
         warm = warm_clocks(torch, stream, s.step, init)
         bufs = {b.data_ptr(): b for b in s._buffers}
@@ -235,8 +240,6 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", ti
             s.step(rewarm_steps)
             s.init_spheres(w.centers, w.radii)
             s.step(warmup)
-            d0 = s.diagnostics()           # synchronises the stream
-            m0 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             e0.record(stream)
@@ -244,10 +247,19 @@ def headline_leg(spfm, torch, w, *, steps, warmup, repeats, coupling="local", ti
             e1.record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
-            d1 = s.diagnostics()
-            m1 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
-            reps.append({"wall": wall, "ev_ms": e0.elapsed_time(e1), "R0": d0["interface_position"],
-                         "R1": d1["interface_position"], "mix": (m0, m1)})
+            reps.append({"wall": wall, "ev_ms": e0.elapsed_time(e1)})
+        # the window's state (the same in every repeat: the run is deterministic):
+        # radius and branch mix at its two ends, taken after the timed windows so
+        # that no reduction or allocation idles the GPU between them
+        s.init_spheres(w.centers, w.radii)
+        s.step(warmup)
+        d0 = s.diagnostics()
+        m0 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
+        s.step(steps)
+        d1 = s.diagnostics()
+        m1 = point_mix(bufs[s.field_ptr()], xt) if coupling == "local" else None
+        for r in reps:
+            r.update({"R0": d0["interface_position"], "R1": d1["interface_position"], "mix": (m0, m1)})
         d = s.diagnostics()
         inf = s.info()
         d["zchunk"] = inf["zchunk"]
@@ -297,9 +309,9 @@ def traffic_from_counters(fetch_rows, write_rows, steps, copy_bytes, kernel_tag=
 
 def measure_traffic(args):
     """Two rocprofv3 counter passes over a child run of the headline kernel (the
-    same window: --warmup untimed steps, then --steps), FETCH_SIZE then WRITE_SIZE,
-    with the copy reference in the same process.  Run before this process touches
-    the GPU; returns None (with the reason on stderr) if anything fails."""
+    same window: --warmup untimed steps, then --steps, in the tile and z-chunk of
+    args), FETCH_SIZE then WRITE_SIZE, with the copy reference in the same
+    process.  Returns None (with the reason on stderr) if anything fails."""
     import glob
     import shutil
     import subprocess
@@ -690,10 +702,7 @@ def main():
     if args.traffic_child:
         traffic_child(args)
         return
-    # counter passes first, in child processes, before this process uses the GPU
     traffic = None
-    if args.only in ("", "f32") and not args.no_traffic:
-        traffic = measure_traffic(args)
     import torch
 
     from paper_1910_05180_amd import inputs, spfm
@@ -708,12 +717,16 @@ def main():
     f32 = f64 = None
     if args.only in ("", "f32"):
         print("leg: f32 headline", file=sys.stderr, flush=True)
-        # the kernel configuration the counter passes ran (tuned there), else tuned here
-        tile = traffic["tile"] if traffic else args.tile
-        zc = traffic["zchunk"] if traffic else args.zchunk
         reps, d = headline_leg(spfm, torch, w, steps=args.steps, warmup=args.warmup,
-                               repeats=max(1, args.repeats), coupling=args.coupling, tile=tile, zchunk=zc)
+                               repeats=max(1, args.repeats), coupling=args.coupling, tile=args.tile,
+                               zchunk=args.zchunk)
         f32 = {"reps": reps, "diag": d}
+        if not args.no_traffic:
+            # two counter passes in child processes, on the configuration timed here
+            print("leg: traffic counters", file=sys.stderr, flush=True)
+            targs = argparse.Namespace(**vars(args))
+            targs.tile, targs.zchunk = d["tile"], d["zchunk"]
+            traffic = measure_traffic(targs)
     if args.only in ("", "f64"):
         print("leg: f64 plain", file=sys.stderr, flush=True)
         wall64, ev64, d64 = timed_run(spfm, torch, w.shape, w, dtype="f64", kernel="plain",

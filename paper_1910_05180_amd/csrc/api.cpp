@@ -737,10 +737,10 @@ spfm_status tune_schedule(Obj* o, const std::vector<TuneCand>& cand, int zfull) 
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
     std::vector<float> best(cand.size(), 1e30f);
     spfm_status st = SPFM_OK;
-    // Three sweeps over the candidates (the first also warms clocks and caches);
-    // each candidate: two untimed launches, then five timed ones; the best of
-    // the sweeps counts.
-    for (int sweep = 0; sweep < 3 && st == SPFM_OK; ++sweep) {
+    // Four sweeps over the candidates, the first untimed (it warms clocks and
+    // caches); each candidate: two untimed launches, then five timed ones; the
+    // best of the timed sweeps counts.
+    for (int sweep = 0; sweep < 4 && st == SPFM_OK; ++sweep) {
         for (size_t ci = 0; ci < cand.size(); ++ci) {
             st = set_schedule(o, cand[ci].tile, cand[ci].z);   // zlen also steers the temporal kernel
             if (st != SPFM_OK) break;
@@ -754,7 +754,7 @@ spfm_status tune_schedule(Obj* o, const std::vector<TuneCand>& cand, int zfull) 
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
-            best[ci] = std::min(best[ci], ms);
+            if (sweep > 0) best[ci] = std::min(best[ci], ms);
         }
     }
     size_t bi = 0;

@@ -4,18 +4,23 @@
 // Constant volume.  The rate of Eq. 2 is affine in the homogeneous driving
 // force, rate(mu) = rate(0) - beta mu h'(phi), beta = 2M / (3 lambda Gamma).  A
 // step is the ordinary step kernel with mu = 0, writing phi* = phi + dt rate(0),
-// followed by three launches that never leave the device:
-//   k_cv_partial  per-block FP64 compensated sums of phi* - phi and h'(phi);
-//   k_cv_final    g = sum(phi* - phi) / sum h'(phi) and mu = g / (dt beta),
-//                 stored in device memory;
-//   k_cv_apply    phi_new = phi* - g h'(phi), evaluated in FP64.
-// Then sum phi_new = sum phi up to the rounding of the stored values.
+// followed by two launches that never leave the device:
+//   k_cv_partial       per-block FP64 compensated sums of phi* - phi and h'(phi);
+//   k_cv_apply_final   every block reduces those partials in the same fixed
+//                      order to g = sum(phi* - phi) / sum h'(phi) (block 0
+//                      stores g and mu = g / (dt beta) in device memory) and
+//                      applies phi_new = phi* - g h'(phi) to its points in FP64.
+// Then sum phi_new = sum phi up to the rounding of the stored values.  The
+// partial count grows with the grid (64 to 1024), so that on small grids each
+// block of the second launch reads little to reduce them.
 //
 // Contours.  On every grid edge (p, p + e_d) whose end values bracket 1/2 the
 // contour point is p + t e_d with t the zero of the linear interpolation of
 // ln((1 - phi)/phi) (Eq. 8-10 at l = 1/2).  Two passes: the barycentre
 // sum phi x / sum phi, then count, sum, min and max of the distances of the
 // contour points from it.
+#include <algorithm>
+
 #include "spfm_impl.h"
 
 namespace spfm {
@@ -96,10 +101,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_cv_partial(const T* __restri
     }
 }
 
-// state[0] = g (the correction per unit h'), state[1] = mu.
-__global__ __launch_bounds__(kReduceThreads) void k_cv_final(const double* __restrict__ part,
-                                                             int nparts, double dt_beta,
-                                                             double* __restrict__ state) {
+// state[0] = g (the correction per unit h'), state[1] = mu.  Every block
+// reduces the partials alike, so every block applies the same g.
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void k_cv_apply_final(T* __restrict__ phi_new,
+                                                                   const T* __restrict__ phi_old,
+                                                                   int64_t n, int interp,
+                                                                   const double* __restrict__ part,
+                                                                   int nparts, double dt_beta,
+                                                                   double* __restrict__ state) {
+    __shared__ double g_sh;
     Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
     double mn = 0.0, mx = 0.0;
     for (int b = threadIdx.x; b < nparts; b += kReduceThreads) {
@@ -111,19 +122,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_cv_final(const double* __res
     if (threadIdx.x == 0) {
         const double den = a[1].value();
         const double g = den != 0.0 ? a[0].value() / den : 0.0;
-        state[0] = g;
-        state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
+        g_sh = g;
+        if (blockIdx.x == 0) {
+            state[0] = g;
+            state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
+        }
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cv_apply(T* __restrict__ phi_new, const T* __restrict__ phi_old,
-                                                  int64_t n, int interp,
-                                                  const double* __restrict__ state) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double g = state[0];
-    phi_new[i] = (T)((double)phi_new[i] - g * h_prime(interp, (double)phi_old[i]));
+    __syncthreads();
+    const double g = g_sh;
+    const int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x;
+    if (i < n) phi_new[i] = (T)((double)phi_new[i] - g * h_prime(interp, (double)phi_old[i]));
 }
 
 // Pass 1 of the contour statistics: sum phi, sum phi x, sum phi y, sum phi z.
@@ -454,16 +462,15 @@ __global__ __launch_bounds__(256) void k_ray_radii(const T* __restrict__ phi, in
 template <typename T>
 hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
                              double* d_part, double* d_state, hipStream_t s) {
-    hipLaunchKernelGGL((k_cv_partial<T>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, phi_old,
-                       phi_new, n, interp, d_part);
+    // about 16 points per thread of the partial pass, 64 to kReduceBlocks partials
+    const int nparts = (int)std::min<int64_t>(kReduceBlocks, std::max<int64_t>(64, n / (16 * kReduceThreads)));
+    hipLaunchKernelGGL((k_cv_partial<T>), dim3(nparts), dim3(kReduceThreads), 0, s, phi_old, phi_new, n,
+                       interp, d_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cv_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, kReduceBlocks, dt_beta,
+    hipLaunchKernelGGL((k_cv_apply_final<T>), dim3((unsigned)((n + kReduceThreads - 1) / kReduceThreads)),
+                       dim3(kReduceThreads), 0, s, phi_new, phi_old, n, interp, d_part, nparts, dt_beta,
                        d_state);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_cv_apply<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi_new,
-                       phi_old, n, interp, d_state);
     return hipGetLastError();
 }
 
