@@ -133,7 +133,11 @@ typedef struct {
                            coupling CF (the comparisons of Sec. 3.1), else SPFM_E_INVAL */
     int32_t conserve_volume; /* nonzero: the homogeneous driving force is chosen at every step so
                            that sum phi stays constant (Sec. 3.3; mu at create only sets the
-                           stability check); periodic grids, tsteps <= 1, not in batches */
+                           stability check); periodic grids, tsteps <= 1, not in batches.  The
+                           sums that fix it are exact (terms rounded to 2^-54, added as
+                           integers), so the result does not depend on the kernel's schedule;
+                           the tiled kernel forms them in the step itself (the untuned tile
+                           shape only) and applies the correction in one more launch */
     const double *batch_wall_sin; /* batches with walls: 6 values per grid, wall_sin of grid i at
                            6 i (read at spfm_batch_create only); NULL = wall_sin for every grid.
                            Ignored by single contexts */
@@ -142,8 +146,9 @@ typedef struct {
                            fastest compiled shape timed at the first step together with the
                            z-chunk.  Compiled shapes: 16x8, 32x8, 64x8, 16x16, 32x16, 64x16 for
                            F32 without walls and h3; 64x8, 32x8, 16x8 for F64 TI_n; 16x8 (F32
-                           TI_n) or 64x8 otherwise.  Another shape is SPFM_E_INVAL.  Results do
-                           not depend on the shape */
+                           TI_n) or 64x8 otherwise; with conserve_volume the untuned shape
+                           alone.  Another shape is SPFM_E_INVAL.  Results do not depend on the
+                           shape */
 } spfm_options;
 
 typedef struct {

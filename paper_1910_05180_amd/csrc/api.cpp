@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -114,10 +115,11 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
             if (tile_tx(k) == o.tile[0] && tile_ty(k) == o.tile[1]) t = k;
         const int kc = kernel_coupling(o.coupling, o.interp);
         if (t < 0 || !tile_compiled(o.dtype == SPFM_F32, kc, o.walls != 0, t) ||
-            o.kernel == SPFM_KERNEL_PLAIN || o.kernel == SPFM_KERNEL_RESIDENT)
+            o.kernel == SPFM_KERNEL_PLAIN || o.kernel == SPFM_KERNEL_RESIDENT ||
+            (o.conserve_volume && t != default_tile(o.dtype == SPFM_F32, kc)))
             return fail(SPFM_E_INVAL,
-                        "tile %d x %d is not compiled for this dtype, coupling and walls (or kernel), "
-                        "see spfm_options.tile",
+                        "tile %d x %d is not compiled for this dtype, coupling and walls (or kernel; "
+                        "constant volume: the default shape only), see spfm_options.tile",
                         o.tile[0], o.tile[1]);
         r->tile = t;
     }
@@ -415,6 +417,9 @@ struct spfm_ctx {
     TileItem* d_items = nullptr;
     int nitems = 0;
     size_t items_cap = 0;
+    // Constant volume with the tiled kernel: the step's exact sums, 4 words per
+    // work item, then 4 words for their total (items_cap + 1 entries).
+    unsigned long long* d_cvpart = nullptr;
     // One grid: tile rows are dealt to the XCDs round robin.
     static constexpr bool kSpreadRows = true;
 
@@ -439,26 +444,37 @@ struct spfm_ctx {
         }
         const StepCoef<double>& cd = r.conserve_volume ? kd0 : kd;
         const StepCoef<float>& cf = r.conserve_volume ? kf0 : kf;
+        // constant volume, tiled: the step also forms the sums of its work items
+        unsigned long long* cvp = r.conserve_volume ? d_cvpart : nullptr;
         hipError_t e;
         if (r.dtype == SPFM_F64) {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
                     : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, tile,
-                                                d_items, nitems, (const WallCoef<double>*)d_wall, stream);
+                                                d_items, nitems, (const WallCoef<double>*)d_wall, cvp,
+                                                stream);
         } else {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
                     : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, tile, d_items,
-                                               nitems, (const WallCoef<float>*)d_wall, stream);
+                                               nitems, (const WallCoef<float>*)d_wall, cvp, stream);
         }
         if (e != hipSuccess || !r.conserve_volume) return e;
         // the step ran without the driving force; add the one that keeps sum phi
         const double dt_beta = r.p.dt * 2.0 * r.p.M / (3.0 * r.p.lambda * r.p.Gamma);
-        return r.dtype == SPFM_F64
-                   ? launch_cv_correct<double>((const double*)in, (double*)out, points(), r.p.interp,
-                                               dt_beta, d_part(), d_state(), stream)
-                   : launch_cv_correct<float>((const float*)in, (float*)out, points(), r.p.interp,
-                                              dt_beta, d_part(), d_state(), stream);
+        const bool f64 = r.dtype == SPFM_F64;
+        if (r.kernel == SPFM_KERNEL_PLAIN) {
+            unsigned long long* part = reinterpret_cast<unsigned long long*>(d_part());
+            return f64 ? launch_cv_correct<double>((const double*)in, (double*)out, points(), r.p.interp,
+                                                   dt_beta, part, d_state(), stream)
+                       : launch_cv_correct<float>((const float*)in, (float*)out, points(), r.p.interp,
+                                                  dt_beta, part, d_state(), stream);
+        }
+        unsigned long long* total = d_cvpart + 4 * items_cap;
+        return f64 ? launch_cv_apply<double>((const double*)in, (double*)out, points(), r.p.interp, dt_beta,
+                                             d_cvpart, nitems, total, d_state(), stream)
+                   : launch_cv_apply<float>((const float*)in, (float*)out, points(), r.p.interp, dt_beta,
+                                            d_cvpart, nitems, total, d_state(), stream);
     }
     // New step coefficients from r; drops the cached graphs, so no replay may
     // still be queued (callers synchronise the stream first).
@@ -696,6 +712,20 @@ spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tile, in
             (void)hipGetLastError();
             o->d_items = nullptr;
             return fail(SPFM_E_NOMEM, "device allocation of the tile schedule failed");
+        }
+        if constexpr (std::is_same<Obj, spfm_ctx>::value) {
+            if (o->r.conserve_volume) {   // the step's constant-volume sums, then their total
+                if (o->d_cvpart) (void)hipFree(o->d_cvpart);
+                o->d_cvpart = nullptr;
+                if (hipMalloc(&o->d_cvpart, (items.size() + 1) * 4 * sizeof(unsigned long long)) !=
+                    hipSuccess) {
+                    (void)hipGetLastError();
+                    o->d_cvpart = nullptr;
+                    (void)hipFree(o->d_items);
+                    o->d_items = nullptr;
+                    return fail(SPFM_E_NOMEM, "device allocation of the constant-volume sums failed");
+                }
+            }
         }
         o->items_cap = items.size();
     }
@@ -938,7 +968,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     const bool autok = !opt || opt->kernel == SPFM_KERNEL_AUTO;
     c->tune_z = autok && !(opt && opt->zchunk > 0);
-    c->tune_tile = autok && r.tile < 0;
+    // constant volume: the untuned tile shape (the step's sums are compiled for it alone)
+    c->tune_tile = autok && r.tile < 0 && !r.conserve_volume;
     const bool f32 = r.dtype == SPFM_F32;
     const bool temporal = r.tsteps > 1;
     c->tile = r.tile >= 0 ? r.tile : default_tile(f32, kernel_coupling(r.p.coupling, r.p.interp));
@@ -1015,6 +1046,7 @@ void spfm_destroy(spfm_ctx* c) {
     c->red.release();
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_cvpart) (void)hipFree(c->d_cvpart);
     if (c->d_wall) (void)hipFree(c->d_wall);
     if (c->d_coef) (void)hipFree(c->d_coef);
     if (c->d_off) (void)hipFree(c->d_off);

@@ -38,6 +38,84 @@ inline int kernel_coupling(int coupling, int interp) {
     return coupling == kCF && interp == kH5 ? kCF5 : (coupling == kCF && interp == kHAbel ? kCFAbel : coupling);
 }
 
+// Slope h'(phi) of the interpolation function, in FP64.
+__host__ __device__ __forceinline__ double h_slope(int interp, double phi) {
+    const double x = phi * (1.0 - phi);
+    if (interp == kH5) return 30.0 * x * x;
+    if (interp == kHAbel) {
+        const double d = 1.0 - 2.0 * x;
+        return 2.0 * x / (d * d);
+    }
+    return 6.0 * x;
+}
+// The interpolation of a kernel coupling.
+constexpr int kernel_interp(int C) { return C == kCF5 ? kH5 : (C == kCFAbel ? kHAbel : kH3); }
+
+// Exact sums for the constant-volume correction.  Each term v is rounded once
+// to a multiple of 2^-54 (|v| clamped to 64: the integer part of v 2^24, then
+// the remainder in units of 2^-54), and the rounded terms are added as 128-bit
+// integers.  Integer addition is exact and associative, so a total does not
+// depend on how the points are split among threads, work items or launches:
+// the correction is the same for every tile shape, z-chunk and kernel.
+// s[0] sums phi* - phi, s[1] sums h'(phi); a partial is stored as 4 words
+// (low and high word of s[0], then of s[1]).
+struct CvAcc {
+    __int128 s[2];
+    __device__ __forceinline__ static __int128 fix(double v) {
+        v = fmin(fmax(v, -64.0), 64.0);
+        const double a = v * 0x1p24;
+        const double h = rint(a);                        // |h| <= 2^30
+        const int r = (int)rint((a - h) * 0x1p30);       // a - h is exact, |r| <= 2^29
+        return (__int128)(int)h * ((__int128)1 << 30) + r;
+    }
+    __device__ __forceinline__ void add(double dphi, double hp) {
+        s[0] += fix(dphi);
+        s[1] += fix(hp);
+    }
+    __device__ __forceinline__ void add_words(const unsigned long long* w) {
+        s[0] += (__int128)(((unsigned __int128)w[1] << 64) | w[0]);
+        s[1] += (__int128)(((unsigned __int128)w[3] << 64) | w[2]);
+    }
+    __device__ __forceinline__ void store(unsigned long long* w) const {
+        w[0] = (unsigned long long)s[0];
+        w[1] = (unsigned long long)((unsigned __int128)s[0] >> 64);
+        w[2] = (unsigned long long)s[1];
+        w[3] = (unsigned long long)((unsigned __int128)s[1] >> 64);
+    }
+    // The value of a sum (one rounding of q 2^-54, q = a 2^30 + b, 0 <= b < 2^30).
+    __device__ __forceinline__ static double value(__int128 q) {
+        const long long a = (long long)(q >> 30);
+        const int b = (int)(q & (((__int128)1 << 30) - 1));
+        return (double)a * 0x1p-24 + (double)b * 0x1p-54;
+    }
+};
+__device__ __forceinline__ __int128 shfl_xor_i128(__int128 v, int m) {
+    const unsigned __int128 u = (unsigned __int128)v;
+    unsigned w[4] = {(unsigned)u, (unsigned)(u >> 32), (unsigned)(u >> 64), (unsigned)(u >> 96)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = __shfl_xor(w[i], m);
+    return (__int128)(((unsigned __int128)w[3] << 96) | ((unsigned __int128)w[2] << 64) |
+                      ((unsigned __int128)w[1] << 32) | w[0]);
+}
+// Sum of a over the block (NT threads, a multiple of 64), stored to dst by
+// thread 0.  Every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void cv_block_store(CvAcc a, unsigned long long* dst) {
+    for (int m = 32; m > 0; m >>= 1) {
+        a.s[0] += shfl_xor_i128(a.s[0], m);
+        a.s[1] += shfl_xor_i128(a.s[1], m);
+    }
+    __shared__ unsigned long long red[NT / 64][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) a.store(red[wave]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CvAcc t{{0, 0}};
+        for (int w = 0; w < NT / 64; ++w) t.add_words(red[w]);
+        t.store(dst);
+    }
+}
+
 template <typename T>
 struct StepCoef {
     int nx, ny, nz;
@@ -441,16 +519,19 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 // d_wall (device memory) non-null: the stored grid has contact-angle walls, and
 // ghost cells are computed from their interior neighbours as they are staged
 // (Eq. 7), so no fill launch is needed.
+// cv_part non-null (periodic grids, the untuned tile shape only): the step also
+// writes, for work item i, the exact sums of phi* - phi and h'(phi) over its
+// points into cv_part[4i .. 4i+3] (CvAcc; the constant-volume correction).
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              int tile, const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
-                             hipStream_t s);
+                             unsigned long long* cv_part, hipStream_t s);
 // The tiled and batched steps of one kernel coupling (sweep.h; instantiated in
 // the per-coupling translation units).
 template <typename T, int C>
 hipError_t launch_tiled_coupling(const T* in, T* out, const StepCoef<T>& k, int stencil, int tile,
                                  const TileItem* items, int nitems, const WallCoef<T>* wall,
-                                 hipStream_t s);
+                                 unsigned long long* cv_part, hipStream_t s);
 template <int C>
 hipError_t launch_batched_coupling(const float* in, float* out, const StepCoef<float>* coef,
                                    const int64_t* offset, int stencil, int tile, const TileItem* items,
@@ -535,12 +616,23 @@ template <typename T>
 hipError_t launch_force_density(const T* phi, T* dens, const StepCoef<T>& k, int walls, int stencil,
                                 int coupling, hipStream_t s);
 
-// Constant volume and contour statistics (volume.hip).  d_part holds
-// kReduceBlocks x 8 doubles; d_state 2 doubles (g, mu); d_out 7 doubles
-// (barycentre x, y, z, then count, sum R, min R, max R in grid units).
+// Constant volume and contour statistics (volume.hip).  launch_cv_correct: the
+// partial sums of phi_new - phi_old and h'(phi_old) (at most kReduceBlocks CvAcc
+// partials, 4 words each, in d_part), then the correction.  launch_cv_apply: the
+// correction from nparts partials already written by the step (cv_part of
+// launch_step_tiled); beyond kCvDirectParts they are first reduced into d_total
+// (4 words).  Both apply phi_new -= g h'(phi_old) with g = sum(phi_new -
+// phi_old) / sum h'(phi_old) and store g, mu = g / dt_beta in d_state (2
+// doubles).  launch_contour_stats: d_part holds kReduceBlocks x 8 doubles, d_out
+// 7 doubles (barycentre x, y, z, then count, sum R, min R, max R in grid units).
+constexpr int kCvDirectParts = 1024;
 template <typename T>
 hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
-                             double* d_part, double* d_state, hipStream_t s);
+                             unsigned long long* d_part, double* d_state, hipStream_t s);
+template <typename T>
+hipError_t launch_cv_apply(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
+                           const unsigned long long* d_part, int nparts, unsigned long long* d_total,
+                           double* d_state, hipStream_t s);
 template <typename T>
 hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
                                 hipStream_t s);

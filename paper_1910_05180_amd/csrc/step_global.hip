@@ -5,11 +5,13 @@ namespace spfm {
 
 template hipError_t launch_tiled_coupling<float, kGlobal>(const float*, float*, const StepCoef<float>&,
                                                           int, int, const TileItem*, int,
-                                                          const WallCoef<float>*, hipStream_t);
+                                                          const WallCoef<float>*, unsigned long long*,
+                                                         hipStream_t);
 template hipError_t launch_tiled_coupling<double, kGlobal>(const double*, double*,
                                                            const StepCoef<double>&, int, int,
                                                            const TileItem*, int,
-                                                           const WallCoef<double>*, hipStream_t);
+                                                           const WallCoef<double>*, unsigned long long*,
+                                                          hipStream_t);
 template hipError_t launch_batched_coupling<kGlobal>(const float*, float*, const StepCoef<float>*,
                                                      const int64_t*, int, int, const TileItem*, int,
                                                      const WallCoef<float>*, hipStream_t);

@@ -46,11 +46,17 @@ __device__ __forceinline__ int wrap_once(int i, int n) {
 // with the composed coefficient of its ghost class as it is staged; ghost planes
 // of a walled z axis are read from their interior neighbour planes.  Points on
 // ghost layers are computed too, and their values are never read.
-template <typename T, int S, int C, bool W, int TX, int TY>
+//
+// V (periodic grids): the block also sums phi* - phi and h'(phi) over its output
+// points exactly (CvAcc) and stores the sums to cvp, for the constant-volume
+// correction that follows the step.
+template <typename T, int S, int C, bool W, bool V, int TX, int TY>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi,
-                                           const WallCoef<T>* __restrict__ w) {
+                                           const WallCoef<T>* __restrict__ w,
+                                           unsigned long long* __restrict__ cvp) {
+    static_assert(!(V && W), "constant volume needs a periodic grid");
     // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
     // wave computes a kWaveX x (64 / kWaveX) patch of the tile.
     constexpr int HX = TX + 2, HY = TY + 2, NC = HX * HY;
@@ -141,10 +147,15 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     };
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const int dst_off = ((y0 + ty) * nx + (x0 + tx)) * (int)sizeof(T);
+    CvAcc cv{{0, 0}};
     auto point = [&](__amdgpu_buffer_rsrc_t dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
                      const PlaneRegs<T>& Rp) {
         const T v = point_from_planes<T, S, C>(Rm, R0, Rp, k);
         if (active) buf_store<(C == kLocal && sizeof(T) == 4) ? kStoreThrough : 0>(v, dst, dst_off);
+        if (V && active) {
+            const double c = (double)R0.c;
+            cv.add((double)v - c, h_slope(kernel_interp(C), c));
+        }
     };
     // Descriptors of the input planes, fetched strictly in order r = 0, 1, ...
     // (plane z0 - 1 + r with periodic wrap), and of the output planes, written
@@ -237,6 +248,7 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         if (r + 2 > nout) break;
         iter(P1t{}, Guarded{}, r + 2, D, E, A, B, qb0, qb1);
     }
+    if constexpr (V) cv_block_store<NT>(cv, cvp);
 }
 
 template <int TX, int TY>
@@ -255,24 +267,35 @@ struct Smem {
 // which keeps them free of spills.
 // FP32 TI_n on tiles wider than 16 needs a few more registers (it spills at 72)
 // and is compiled for 6 waves.
+// The constant-volume variants carry two 128-bit sums per thread (4 waves FP32).
 template <typename T, int C = kLocal, int TX = 16>
 struct WavesPerSimd {
     static constexpr int value = sizeof(T) == 4 ? (C == kLocal && TX != 16 ? 6 : SPFM_WAVES_F32) : 2;
     static constexpr int walled = sizeof(T) == 4 ? 4 : 2;
 };
+template <typename T, int C, bool W, bool V, int TX>
+constexpr int waves_per_simd() {
+    return W || V ? WavesPerSimd<T>::walled : WavesPerSimd<T, C, TX>::value;
+}
 
 // One block per work item of a tile schedule (see the host-side schedule
 // builder): the item gives the tile column origin and its z-chunk; items with
-// zlen = 0 pad the table and exit at once.  W: walled grid, coefficients at w.
-template <typename T, int S, int C, bool W, int TX, int TY>
-__global__ __launch_bounds__((Smem<TX, TY>::NT), (W ? WavesPerSimd<T>::walled : WavesPerSimd<T, C, TX>::value)) void k_step_tiled(
+// zlen = 0 pad the table and exit at once (with V, after storing zero sums).
+// W: walled grid, coefficients at w.  V: constant-volume sums of item i to
+// cvp + 4i.
+template <typename T, int S, int C, bool W, bool V, int TX, int TY>
+__global__ __launch_bounds__((Smem<TX, TY>::NT), (waves_per_simd<T, C, W, V, TX>())) void k_step_tiled(
     const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items,
-    const WallCoef<T>* __restrict__ w) {
+    const WallCoef<T>* __restrict__ w, unsigned long long* __restrict__ cvp) {
     __shared__ T sphi[4 * Smem<TX, TY>::HP];
     __shared__ T spsi[C == kLocal ? 4 * Smem<TX, TY>::HP : 1];
     const TileItem it = items[blockIdx.x];
-    if (it.zlen <= 0) return;
-    tile_sweep<T, S, C, W, TX, TY>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi, w);
+    unsigned long long* const cvi = V ? cvp + 4 * (size_t)blockIdx.x : nullptr;
+    if (it.zlen <= 0) {
+        if (V && threadIdx.x < 4) cvi[threadIdx.x] = 0;
+        return;
+    }
+    tile_sweep<T, S, C, W, V, TX, TY>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi, w, cvi);
 }
 
 template <int S, int C, bool W, int TX, int TY>
@@ -286,8 +309,8 @@ __global__ __launch_bounds__((Smem<TX, TY>::NT), (W ? WavesPerSimd<float>::walle
     if (it.zlen <= 0) return;   // padding of the schedule
     const StepCoef<float> k = coef[it.inst];
     const int64_t off = offset[it.inst];
-    tile_sweep<float, S, C, W, TX, TY>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0, it.zlen,
-                                       sphi, spsi, W ? wall + it.inst : nullptr);
+    tile_sweep<float, S, C, W, false, TX, TY>(buf_in + off, buf_out + off, k, it.x0, it.y0, it.z0,
+                                              it.zlen, sphi, spsi, W ? wall + it.inst : nullptr, nullptr);
 }
 
 
@@ -315,11 +338,11 @@ void for_each_variant(int stencil, bool walled, int tile, F&& f) {
     else if (stencil == 26) by_walls(std::integral_constant<int, 26>{});
 }
 
-template <typename T, int S, int C, bool W, int TX, int TY>
+template <typename T, int S, int C, bool W, bool V, int TX, int TY>
 hipError_t run_tiled(const T* in, T* out, const StepCoef<T>& k, const TileItem* items, int nitems,
-                     const WallCoef<T>* wall, hipStream_t s) {
-    hipLaunchKernelGGL((k_step_tiled<T, S, C, W, TX, TY>), dim3((unsigned)nitems), dim3(TX * TY), 0, s,
-                       in, out, k, items, wall);
+                     const WallCoef<T>* wall, unsigned long long* cvp, hipStream_t s) {
+    hipLaunchKernelGGL((k_step_tiled<T, S, C, W, V, TX, TY>), dim3((unsigned)nitems), dim3(TX * TY), 0,
+                       s, in, out, k, items, wall, cvp);
     return hipGetLastError();
 }
 
@@ -332,19 +355,29 @@ hipError_t run_batched(const float* in, float* out, const StepCoef<float>* coef,
 }
 
 // The tiled step of one kernel coupling C for the compiled tile shape `tile`
-// (hipErrorInvalidValue for a shape not compiled for this variant).
+// (hipErrorInvalidValue for a shape not compiled for this variant).  With cvp
+// (periodic grids, the untuned shape only) the constant-volume variant.
 template <typename T, int C>
 hipError_t launch_tiled_coupling(const T* in, T* out, const StepCoef<T>& k, int stencil, int tile,
                                  const TileItem* items, int nitems, const WallCoef<T>* wall,
-                                 hipStream_t s) {
+                                 unsigned long long* cvp, hipStream_t s) {
     if (nitems <= 0) return hipErrorInvalidValue;
     constexpr bool f32 = sizeof(T) == 4;
     hipError_t e = hipErrorInvalidValue;
     auto one = [&](auto S_, auto W_, auto T_) {
         constexpr int S = decltype(S_)::value, t = decltype(T_)::value;
         constexpr bool W = decltype(W_)::value;
+        if constexpr (!W && t == default_tile(f32, C)) {
+            if (cvp) {
+                e = run_tiled<T, S, C, false, true, tile_tx(t), tile_ty(t)>(in, out, k, items, nitems,
+                                                                             nullptr, cvp, s);
+                return;
+            }
+        }
         if constexpr (tile_compiled(f32, C, W, t))
-            e = run_tiled<T, S, C, W, tile_tx(t), tile_ty(t)>(in, out, k, items, nitems, wall, s);
+            if (!cvp)
+                e = run_tiled<T, S, C, W, false, tile_tx(t), tile_ty(t)>(in, out, k, items, nitems, wall,
+                                                                          nullptr, s);
     };
     for_each_variant(stencil, wall != nullptr, tile, one);
     return e;

@@ -4,15 +4,18 @@
 // Constant volume.  The rate of Eq. 2 is affine in the homogeneous driving
 // force, rate(mu) = rate(0) - beta mu h'(phi), beta = 2M / (3 lambda Gamma).  A
 // step is the ordinary step kernel with mu = 0, writing phi* = phi + dt rate(0),
-// followed by two launches that never leave the device:
-//   k_cv_partial       per-block FP64 compensated sums of phi* - phi and h'(phi);
-//   k_cv_apply_final   every block reduces those partials in the same fixed
-//                      order to g = sum(phi* - phi) / sum h'(phi) (block 0
-//                      stores g and mu = g / (dt beta) in device memory) and
-//                      applies phi_new = phi* - g h'(phi) to its points in FP64.
-// Then sum phi_new = sum phi up to the rounding of the stored values.  The
-// partial count grows with the grid (64 to 1024), so that on small grids each
-// block of the second launch reads little to reduce them.
+// and a correction that never leaves the device: the sums of phi* - phi and
+// h'(phi), g = sum(phi* - phi) / sum h'(phi), mu = g / (dt beta), and
+// phi_new = phi* - g h'(phi) at every point in FP64.  Then sum phi_new = sum phi
+// up to the rounding of the stored values.  The sums are exact integer sums of
+// terms rounded to 2^-54 (CvAcc), so g does not depend on which pass formed
+// them or how it split the points:
+//   k_cv_partial  per-block partial sums (the plain kernel's path; the tiled
+//                 step forms one partial per work item itself);
+//   k_cv_total    one block adds many partials into one;
+//   k_cv_apply    every block adds the partials (few: at most kCvDirectParts),
+//                 block 0 stores g and mu in device memory, and every block
+//                 applies the correction to its points.
 //
 // Contours.  On every grid edge (p, p + e_d) whose end values bracket 1/2 the
 // contour point is p + t e_d with t the zero of the linear interpolation of
@@ -41,16 +44,6 @@ struct Acc {   // TwoSum accumulator
     }
     __device__ __forceinline__ double value() const { return s + c; }
 };
-
-__device__ __forceinline__ double h_prime(int interp, double phi) {
-    const double x = phi * (1.0 - phi);
-    if (interp == kH5) return 30.0 * x * x;
-    if (interp == kHAbel) {
-        const double d = 1.0 - 2.0 * x;
-        return 2.0 * x / (d * d);
-    }
-    return 6.0 * x;
-}
 
 // Block sums of NQ (s, c) pairs plus NM min and max values, in a fixed order:
 // wave butterflies, then thread 0 over the waves.  Returns on thread 0.
@@ -85,53 +78,51 @@ template <typename T>
 __global__ __launch_bounds__(kReduceThreads) void k_cv_partial(const T* __restrict__ phi_old,
                                                                const T* __restrict__ phi_new,
                                                                int64_t n, int interp,
-                                                               double* __restrict__ part) {
-    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
-    double mn = 0.0, mx = 0.0;
+                                                               unsigned long long* __restrict__ part) {
+    CvAcc a{{0, 0}};
     const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
     for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride) {
         const double o = (double)phi_old[i];
-        a[0].add((double)phi_new[i] - o);
-        a[1].add(h_prime(interp, o));
+        a.add((double)phi_new[i] - o, h_slope(interp, o));
     }
-    block_sums<2>(a, mn, mx);
-    if (threadIdx.x == 0) {
-        double* q = part + (size_t)blockIdx.x * 4;
-        q[0] = a[0].s; q[1] = a[0].c; q[2] = a[1].s; q[3] = a[1].c;
-    }
+    cv_block_store<kReduceThreads>(a, part + 4 * (size_t)blockIdx.x);
 }
 
-// state[0] = g (the correction per unit h'), state[1] = mu.  Every block
-// reduces the partials alike, so every block applies the same g.
+__global__ __launch_bounds__(kReduceThreads) void k_cv_total(const unsigned long long* __restrict__ part,
+                                                             int nparts,
+                                                             unsigned long long* __restrict__ total) {
+    CvAcc a{{0, 0}};
+    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) a.add_words(part + 4 * (size_t)b);
+    cv_block_store<kReduceThreads>(a, total);
+}
+
+// state[0] = g (the correction per unit h'), state[1] = mu.  Every block adds
+// the same integers, so every block applies the same g.
 template <typename T>
-__global__ __launch_bounds__(kReduceThreads) void k_cv_apply_final(T* __restrict__ phi_new,
-                                                                   const T* __restrict__ phi_old,
-                                                                   int64_t n, int interp,
-                                                                   const double* __restrict__ part,
-                                                                   int nparts, double dt_beta,
-                                                                   double* __restrict__ state) {
-    __shared__ double g_sh;
-    Acc a[2] = {{0.0, 0.0}, {0.0, 0.0}};
-    double mn = 0.0, mx = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) {
-        const double* q = part + (size_t)b * 4;
-        a[0].merge(q[0], q[1]);
-        a[1].merge(q[2], q[3]);
-    }
-    block_sums<2>(a, mn, mx);
-    if (threadIdx.x == 0) {
-        const double den = a[1].value();
-        const double g = den != 0.0 ? a[0].value() / den : 0.0;
-        g_sh = g;
-        if (blockIdx.x == 0) {
-            state[0] = g;
-            state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
-        }
-    }
-    __syncthreads();
-    const double g = g_sh;
+__global__ __launch_bounds__(kReduceThreads) void k_cv_apply(T* __restrict__ phi_new,
+                                                             const T* __restrict__ phi_old, int64_t n,
+                                                             int interp,
+                                                             const unsigned long long* __restrict__ part,
+                                                             int nparts, double dt_beta,
+                                                             double* __restrict__ state) {
+    __shared__ unsigned long long tot[4];
+    // this thread's point, loaded first so that its latency overlaps the sums
     const int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x;
-    if (i < n) phi_new[i] = (T)((double)phi_new[i] - g * h_prime(interp, (double)phi_old[i]));
+    const bool in = i < n;
+    const T pn = in ? phi_new[i] : T(0), po = in ? phi_old[i] : T(0);
+    CvAcc a{{0, 0}};
+    for (int b = threadIdx.x; b < nparts; b += kReduceThreads) a.add_words(part + 4 * (size_t)b);
+    cv_block_store<kReduceThreads>(a, tot);
+    __syncthreads();
+    CvAcc t{{0, 0}};
+    t.add_words(tot);
+    const double den = CvAcc::value(t.s[1]);
+    const double g = den != 0.0 ? CvAcc::value(t.s[0]) / den : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state[0] = g;
+        state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
+    }
+    if (in) phi_new[i] = (T)((double)pn - g * h_slope(interp, (double)po));
 }
 
 // Pass 1 of the contour statistics: sum phi, sum phi x, sum phi y, sum phi z.
@@ -460,18 +451,33 @@ __global__ __launch_bounds__(256) void k_ray_radii(const T* __restrict__ phi, in
 }  // namespace
 
 template <typename T>
+hipError_t launch_cv_apply(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
+                           const unsigned long long* d_part, int nparts, unsigned long long* d_total,
+                           double* d_state, hipStream_t s) {
+    if (nparts <= 0 || n <= 0) return hipErrorInvalidValue;
+    if (nparts > kCvDirectParts) {   // one block adds them first: each apply block then reads one
+        hipLaunchKernelGGL(k_cv_total, dim3(1), dim3(kReduceThreads), 0, s, d_part, nparts, d_total);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        d_part = d_total;
+        nparts = 1;
+    }
+    hipLaunchKernelGGL((k_cv_apply<T>), dim3((unsigned)((n + kReduceThreads - 1) / kReduceThreads)),
+                       dim3(kReduceThreads), 0, s, phi_new, phi_old, n, interp, d_part, nparts, dt_beta,
+                       d_state);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
-                             double* d_part, double* d_state, hipStream_t s) {
+                             unsigned long long* d_part, double* d_state, hipStream_t s) {
     // about 16 points per thread of the partial pass, 64 to kReduceBlocks partials
     const int nparts = (int)std::min<int64_t>(kReduceBlocks, std::max<int64_t>(64, n / (16 * kReduceThreads)));
     hipLaunchKernelGGL((k_cv_partial<T>), dim3(nparts), dim3(kReduceThreads), 0, s, phi_old, phi_new, n,
                        interp, d_part);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_cv_apply_final<T>), dim3((unsigned)((n + kReduceThreads - 1) / kReduceThreads)),
-                       dim3(kReduceThreads), 0, s, phi_new, phi_old, n, interp, d_part, nparts, dt_beta,
-                       d_state);
-    return hipGetLastError();
+    return launch_cv_apply<T>(phi_old, phi_new, n, interp, dt_beta, d_part, nparts, nullptr, d_state, s);
 }
 
 template <typename T>
@@ -523,10 +529,16 @@ hipError_t launch_init_box(T* phi, int nx, int ny, int nz, double dx, double lam
     return hipGetLastError();
 }
 
-template hipError_t launch_cv_correct<float>(const float*, float*, int64_t, int, double, double*,
-                                             double*, hipStream_t);
-template hipError_t launch_cv_correct<double>(const double*, double*, int64_t, int, double, double*,
-                                              double*, hipStream_t);
+template hipError_t launch_cv_correct<float>(const float*, float*, int64_t, int, double,
+                                             unsigned long long*, double*, hipStream_t);
+template hipError_t launch_cv_correct<double>(const double*, double*, int64_t, int, double,
+                                              unsigned long long*, double*, hipStream_t);
+template hipError_t launch_cv_apply<float>(const float*, float*, int64_t, int, double,
+                                           const unsigned long long*, int, unsigned long long*, double*,
+                                           hipStream_t);
+template hipError_t launch_cv_apply<double>(const double*, double*, int64_t, int, double,
+                                            const unsigned long long*, int, unsigned long long*, double*,
+                                            hipStream_t);
 template hipError_t launch_contour_stats<float>(const float*, int, int, int, double*, double*,
                                                 hipStream_t);
 template hipError_t launch_contour_stats<double>(const double*, int, int, int, double*, double*,

@@ -63,10 +63,42 @@ def test_constant_volume_conserves_the_sum(S, dtype, tol):
                     stream=st) as s:
             s.set_field(phi0)
             v0 = s.diagnostics()["sum_phi"]
-            s.step(500)                     # graph replays of the four launches per step
+            s.step(500)                     # graph replays of the step and its correction
             d = s.diagnostics()
     assert abs(d["sum_phi"] / v0 - 1.0) <= tol
     assert d["mu"] < 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("coupling,interp", [("local", "h3"), ("cf", "h5")])
+def test_constant_volume_does_not_depend_on_the_schedule(S, dtype, coupling, interp):
+    """The tiled step forms exact sums per work item: one-plane chunks on 96^3
+    give more than 1024 items (added in a pass of their own before the
+    correction), 64-plane chunks a few hundred, the autotuner its own choice; the
+    plain kernel's path sums 1024 block partials.  The fields after 40 steps
+    and mu agree bit for bit among the tiled runs, and with the plain kernel's
+    mu to the rounding of the step itself."""
+    n, lam = 96, 3.0
+    phi0 = oracle.init_spheres((n, n, n), [(47.3, 50.2, 45.1)], [20.0], lam=lam)
+    if dtype == "f32":
+        phi0 = as_f32_input(phi0)
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    out = {}
+    for name, kw in (("z1", dict(kernel="tiled", zchunk=1)), ("z64", dict(kernel="tiled", zchunk=64)),
+                     ("auto", dict(kernel="auto")), ("plain", dict(kernel="plain"))):
+        print(f"case cv schedule {dtype} {coupling}+{interp} {name}", flush=True)
+        with S.Spfm(phi0.shape, lam=lam, mu=-0.2, stencil=26, dtype=dtype, coupling=coupling,
+                    interp=interp, eps=eps, conserve_volume=True, **kw) as s:
+            s.set_field(phi0)
+            s.step(40)
+            inf = s.info()
+            out[name] = (s.get_field(), s.diagnostics()["mu"], inf["zchunk"], inf["tile_x"], inf["tile_y"])
+    assert out["z1"][2] == 1 and out["z64"][2] == 64
+    for name in ("z64", "auto"):
+        assert np.array_equal(out[name][0], out["z1"][0]), name
+        assert out[name][1] == out["z1"][1], name
+        assert out[name][3:] == out["z1"][3:], name   # the untuned tile shape
+    assert abs(out["plain"][1] / out["z1"][1] - 1.0) <= (1e-12 if dtype == "f64" else 1e-5)
 
 
 def test_contour_stats_match_oracle(S):

@@ -200,6 +200,7 @@ def test_resident_batch_refuses_a_grid_it_cannot_hold(S):
     dict(tile=(32, 8), dtype="f64", coupling="cf"),  # FP64 CF: 64x8 only
     dict(tile=(16, 8), coupling="cf", interp="h5"),  # CF with h5: 64x8 only
     dict(tile=(16, 8), kernel="plain"), dict(tile=(16, 8), kernel="resident"),
+    dict(tile=(32, 8), conserve_volume=True),        # constant volume: the default shape only
 ])
 def test_create_rejects_tiles_not_compiled(S, kw):
     st, msg = S.try_create((16, 16, 16), **kw)
@@ -208,7 +209,8 @@ def test_create_rejects_tiles_not_compiled(S, kw):
 
 @pytest.mark.parametrize("kw", [dict(tile=(64, 16)), dict(tile=(16, 16), coupling="global"),
                                 dict(tile=(16, 8), dtype="f64"), dict(tile=(64, 8), coupling="cf", interp="habel"),
-                                dict(tile=(16, 8), walls=1)])
+                                dict(tile=(16, 8), walls=1), dict(tile=(16, 8), conserve_volume=True),
+                                dict(tile=(64, 8), coupling="cf", conserve_volume=True)])
 def test_create_accepts_compiled_tiles(S, kw):
     st, msg = S.try_create((16, 16, 16), **kw)
     assert st != -1, msg
