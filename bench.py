@@ -533,8 +533,9 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
     planar fronts rotated about [001] (0, 15, 30, 45 degrees) and [011] (15, 30,
     45 degrees) between contact-angle walls (Eq. 7) that hold their
     orientation, 26 neighbours, lambda = 4 dx, mu = mu0 cos(theta), dt = 0.05,
-    FP32, all seven in one walled batch (one step launch per step; the kernel
-    computes the wall ghosts as it reads them), TI_n unless coupling says
+    FP32, all seven in one walled batch (kernel AUTO: the tiled kernel, whole
+    grids or x segments of the resident kernel, timed at the first step; the
+    kernels compute the wall ghosts themselves), TI_n unless coupling says
     otherwise.  Reports the aggregate step rate, the relative error of each
     front's x-velocity against -M mu0 / Gamma, and the kinetic anisotropy (the
     spread of those errors over the orientations)."""
@@ -562,6 +563,7 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
         e1.record(stream)
         d1 = b.diagnostics()
         ms = e0.elapsed_time(e1)
+        info = b.info()
         b.close()
     worst, errs = 0.0, {}
     for (axis, deg), n, a, z in zip(runs, ns, d0, d1):
@@ -573,21 +575,32 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
     return {"value": pts * steps * len(runs) / (ms * 1e-3) / 1e9, "unit": "GLUPS",
             "grid": "120x10x10 + ghost layers", "orientations": len(runs), "grids_per_launch": len(runs),
             "coupling": coupling, "mu0": mu0, "steps": steps, "us_per_step": ms * 1e3 / steps,
+            "kernel": kernel_choice(spfm, info),
             "max_rel_velocity_error": worst,
             "kinetic_anisotropy": max(errs.values()) - min(errs.values()),
             "rel_velocity_error": errs}
 
 
+def kernel_choice(spfm, info):
+    """What a batch runs, from its info: "tiled 16x8 z4", "resident whole" or
+    "resident segments 8 halo 4"."""
+    if info["kernel"] == spfm.KERNEL_TILED:
+        return f"tiled {info['tile_x']}x{info['tile_y']} z{info['zchunk']}"
+    if info["segment"]:
+        return f"resident segments {info['segment']} halo {info['halo']}"
+    return "resident whole"
+
+
 def models_leg(spfm, torch, warm=2000, steps=4000):
     """The 1D model comparison of the paper's Fig. 7 as batched [100] slabs
     (3 x 3 x 256 periodic, two interfaces 128 dx apart, 6 neighbours, dt = 0.05,
-    FP32): for each model one launch per step steps the slabs of every
-    lambda~ in {4, 3, 2.5} and mu~ in {0.005, 0.01, 0.02, 0.05}.  Reports the
+    FP32): for each model one batch steps the slabs of every lambda~ in
+    {4, 3, 2.5} and mu~ in {0.005, 0.01, 0.02, 0.05} (kernel AUTO, as above).  Reports the
     relative error of the mean interface velocity against -M mu / Gamma."""
     models = [("CF+h3", "cf", "h3"), ("CF+h5", "cf", "h5"), ("CF+h_Abel", "cf", "habel"),
               ("TI_100+h3", "global", "h3"), ("TI_n+h3", "local", "h3")]
     cases = [(lam, mu) for lam in (4.0, 3.0, 2.5) for mu in (0.005, 0.01, 0.02, 0.05)]
-    shape, out, total_ms = (3, 3, 256), {}, 0.0
+    shape, out, total_ms, kernels = (3, 3, 256), {}, 0.0, {}
     for name, coupling, interp in models:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
@@ -604,6 +617,7 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
             e1.record(stream)
             d1 = b.diagnostics()
             total_ms += e0.elapsed_time(e1)
+            kernels[name] = kernel_choice(spfm, b.info())
             b.close()
         errs = {}
         for (lam, mu), a, e in zip(cases, d0, d1):
@@ -613,7 +627,8 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
     pts = shape[0] * shape[1] * shape[2] * len(cases)
     return {"value": pts * steps * len(models) / (total_ms * 1e-3) / 1e9, "unit": "GLUPS",
             "grids_per_launch": len(cases), "steps": steps,
-            "us_per_step": total_ms * 1e3 / (steps * len(models)), "rel_velocity_error": out}
+            "us_per_step": total_ms * 1e3 / (steps * len(models)), "kernel": kernels,
+            "rel_velocity_error": out}
 
 
 def cube_leg(spfm, torch, steps=3000):

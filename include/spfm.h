@@ -65,14 +65,16 @@ typedef enum { SPFM_LOCAL = 0, SPFM_GLOBAL = 1, SPFM_CF = 2 } spfm_coupling;
 /* Kernel choice: PLAIN = one thread per point reading its 27 neighbours from
  * global memory; TILED = LDS-staged tiles marching along z; RESIDENT = one
  * workgroup per grid holding the whole stored grid in LDS (two copies: at most
- * 20480 FP32 or 10240 FP64 stored points) and taking many steps per launch
- * with workgroup barriers only (not with conserve_volume or tsteps > 1).
- * AUTO = TILED with the z-chunk per block chosen by timing candidates on the
- * current field at the first spfm_step (that call synchronises the stream
- * once); for batches whose stored grids all have at most 4096 points (where
- * one workgroup's step is quicker than a launch), AUTO = RESIDENT.  Results do not
- * depend on the kernel choice among TILED and RESIDENT, nor on the z-chunk:
- * they are equal bit for bit. */
+ * 20480 FP32 or 10240 FP64 stored points), or for batches per x segment of a
+ * grid with halos (spfm_options.segment), taking many steps per launch with
+ * workgroup barriers only (not with conserve_volume or tsteps > 1).
+ * AUTO = TILED with the tile shape and z-chunk per block chosen by timing
+ * candidates on the current field at the first spfm_step (that call
+ * synchronises the stream once); for batches whose stored grids all fit the
+ * resident kernel, the first spfm_batch_step also times RESIDENT, whole and in
+ * segments, and keeps the fastest.  Results do not depend on the kernel choice
+ * among TILED and RESIDENT, nor on the tile, z-chunk or segments: they are
+ * equal bit for bit. */
 typedef enum {
     SPFM_KERNEL_AUTO = 0,
     SPFM_KERNEL_PLAIN = 1,
@@ -106,8 +108,9 @@ typedef struct {
     int32_t kernel;     /* spfm_kernel */
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
-                           library: a size rule (32 planes, 64 for fused steps, shorter for
-                           grids too small to fill the GPU); for AUTO on a grid that fills
+                           library: a size rule (32 planes, 64 for fused steps, shorter, down
+                           to 2 (8 fused), for grids too small to fill the GPU); for AUTO on a
+                           grid that fills
                            it, timed among 8..64 at the first step.
                            Single steps cut each tile column into blocks of at most zchunk
                            planes, except a tail (about 1.4 rounds of the work the GPU keeps
@@ -149,6 +152,15 @@ typedef struct {
                            TI_n) or 64x8 otherwise; with conserve_volume the untuned shape
                            alone.  Another shape is SPFM_E_INVAL.  Results do not depend on the
                            shape */
+    int32_t segment[2]; /* batches, resident kernel: {length, halo} cuts every grid along x into
+                           pieces of `length` stored columns, one workgroup each, that hold
+                           `halo` more columns on each open side and take at most `halo` steps
+                           per launch (the halos are stepped redundantly, so no workgroup waits
+                           for another); grids not longer than a piece stay whole.  {0, 0} =
+                           whole grids, or with kernel AUTO the fastest of the tiled kernel, whole
+                           grids and a set of {length, halo} pairs, timed at the first step.
+                           length >= 1 and 1 <= halo <= 4096 when given; SPFM_E_INVAL for
+                           single contexts and with kernel TILED.  Results do not depend on it */
 } spfm_options;
 
 typedef struct {
@@ -323,7 +335,7 @@ spfm_status spfm_get_info(const spfm_ctx *ctx, spfm_info *out);
  * grid.  Arrays have n entries.
  * The shared options (dtype must be F32, kernel, stream, C_Gamma <= 0, gamma,
  * eps, tau, allow_unstable, walls, zchunk) apply to every grid.  zchunk 0
- * with kernel TILED: 32 planes, halved down to 4 while the batch gives fewer
+ * with kernel TILED: 32 planes, halved down to 2 while the batch gives fewer
  * than 2^19 threads; with kernel AUTO and a batch that fills the GPU (32
  * planes kept) the first spfm_batch_step also times chunks of 4, 8, 16, 32 and
  * 64 planes and keeps the fastest (that call synchronises the stream, so it
@@ -363,10 +375,12 @@ int32_t spfm_batch_zchunk(const spfm_batch *b);
 /* The step kernel the batch uses: SPFM_KERNEL_TILED or SPFM_KERNEL_RESIDENT; -1 for NULL. */
 int32_t spfm_batch_kernel(const spfm_batch *b);
 /* What the batch runs (after tuning, if any): kernel, tile column and leading
- * z-chunk of the tiled kernel (0 for the resident one), grid and point counts. */
+ * z-chunk of the tiled kernel (0 for the resident one), grid and point counts,
+ * and the resident kernel's x-segment length and halo ({0, 0}: whole grids). */
 typedef struct {
     int32_t kernel, tile_x, tile_y, zchunk, grids;
     int64_t points;
+    int32_t segment, halo;
 } spfm_batch_info;
 spfm_status spfm_batch_get_info(const spfm_batch *b, spfm_batch_info *out);
 

@@ -47,6 +47,8 @@ struct GridDims {
     int nx, ny, nz;
 };
 
+constexpr int kResidentChunk = 4096;   // most steps of one whole-grid resident launch
+
 struct Resolved {
     Params p;
     int dtype, kernel, allow_unstable;
@@ -57,6 +59,7 @@ struct Resolved {
     double wall_sin[6];
     int sx, sy, sz;   // stored dims: the grid plus one ghost layer per end of a walled axis
     double dt_max;
+    int seg_len, seg_halo;   // resident x segments asked for (batches), 0 = none
 };
 
 // Validate and resolve everything that does not touch the GPU.
@@ -108,6 +111,15 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
             return fail(SPFM_E_INVAL, "the resident kernel takes single steps at fixed mu");
     }
     if (o.zchunk < 0 || o.zchunk > 4096) return fail(SPFM_E_INVAL, "zchunk must be in 0..4096");
+    r->seg_len = r->seg_halo = 0;
+    if (o.segment[0] != 0 || o.segment[1] != 0) {
+        if (o.segment[0] < 1 || o.segment[1] < 1 || o.segment[1] > 4096 ||
+            o.kernel == SPFM_KERNEL_TILED || o.kernel == SPFM_KERNEL_PLAIN)
+            return fail(SPFM_E_INVAL, "segment needs length >= 1, halo in 1..4096 and the resident "
+                                      "kernel (or AUTO)");
+        r->seg_len = o.segment[0];
+        r->seg_halo = o.segment[1];
+    }
     r->tile = -1;
     if (o.tile[0] != 0 || o.tile[1] != 0) {
         int t = -1;
@@ -400,13 +412,16 @@ struct spfm_ctx {
         }
         return f64 ? launch_step_resident<double>((const double*)buf[from], (double*)buf[to],
                                                   (const StepCoef<double>*)d_coef, d_off,
-                                                  (const WallCoef<double>*)d_wall, 1, cells, nsteps, S, C,
-                                                  stream)
+                                                  (const WallCoef<double>*)d_wall, nullptr, 1, cells,
+                                                  nsteps, S, C, stream)
                    : launch_step_resident<float>((const float*)buf[from], (float*)buf[to],
                                                  (const StepCoef<float>*)d_coef, d_off,
-                                                 (const WallCoef<float>*)d_wall, 1, cells, nsteps, S, C,
-                                                 stream);
+                                                 (const WallCoef<float>*)d_wall, nullptr, 1, cells,
+                                                 nsteps, S, C, stream);
     }
+    // Resident launches: up to kResidentChunk steps, in place for even counts.
+    int resident_chunk() const { return kResidentChunk; }
+    bool resident_in_place() const { return true; }
 
     int zlen = kTileZ;        // planes per block of the tiled kernel (the leading chunks)
     int tile = kTile64x8;     // tile shape of the tiled kernel (TileShape)
@@ -535,12 +550,24 @@ struct spfm_batch {
 
     // Resident kernel (every stored grid fits the LDS of one workgroup): one
     // launch takes many steps of all grids; max_cells is the largest stored grid.
+    // With x segments (seg_len > 0): the nres blocks of d_res, each region at
+    // most res_cells points, at most seg_halo steps per launch, out of place.
     bool resident = false;
     int max_cells = 0;
+    bool tune_res = false, res_tuned = false;   // AUTO: time tiled, whole and segmented at the first step
+    int seg_len = 0, seg_halo = 0;
+    ResItem* d_res = nullptr;
+    size_t res_cap = 0;
+    int nres = 0, res_cells = 0;
     hipError_t launch_resident(int from, int to, int nsteps) {
+        if (seg_len > 0)
+            return launch_step_resident<float>(buf[from], buf[to], d_coef, d_offset, walls ? d_wall : nullptr,
+                                               d_res, nres, res_cells, nsteps, stencil, coupling, stream);
         return launch_step_resident<float>(buf[from], buf[to], d_coef, d_offset, walls ? d_wall : nullptr,
-                                           n, max_cells, nsteps, stencil, coupling, stream);
+                                           nullptr, n, max_cells, nsteps, stencil, coupling, stream);
     }
+    int resident_chunk() const { return seg_len > 0 ? seg_halo : kResidentChunk; }
+    bool resident_in_place() const { return seg_len == 0; }
 
     int unit() const { return 1; }
     hipError_t launch_unit(int from) { return launch_one(from); }
@@ -607,7 +634,10 @@ int tail_planes(int nz, int64_t total_points) {
 // Planes per block: the longest z-chunk (kTileZ for single steps, 2 kTileZ for
 // fused ones, halved down to zmin) that still gives at least min_threads
 // threads for tiles tx x ty over all grids, counting the guided chunks of the
-// single-step schedule (guided) or uniform chunks (the temporal kernel).  A
+// single-step schedule (guided) or uniform chunks (the temporal kernel); then
+// halved on, down to 2 planes, while there are fewer than min_threads / 4
+// (grids far too small to fill the GPU: a 60^3 step takes 12.8 us with chunks
+// of 2 or 4 planes against 14.2 with 8).  A
 // fused chunk also computes 2 T - 2 extra planes of its intermediate levels
 // and reads 2 T extra input planes, which longer chunks amortise (CF, 3 fused
 // steps on the 512^3 grains: 752 GLUPS with 64 planes, 710 with 32).  Grids too
@@ -629,6 +659,7 @@ int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided
     };
     int z = guided ? kTileZ : 2 * kTileZ;
     while (z > zmin && threads(z) < min_threads) z /= 2;
+    while (guided && z > 2 && threads(z) < min_threads / 4) z /= 2;
     return z;
 }
 
@@ -832,7 +863,8 @@ spfm_status autotune(spfm_ctx* c) {
                          c->r.tsteps > 1 ? 2 * kTileZ : kTileZ);
 }
 
-// Batches: small grids gain from chunks down to 4 planes.
+// Batches: chunks from 4 planes are timed (the size rule goes down to 2 for
+// batches far too small to fill the GPU, where the tuner keeps the rule's length).
 spfm_status autotune(spfm_batch* b) {
     static const int zs[5] = {4, 8, 16, 32, 64};
     int nz = 1;
@@ -885,16 +917,17 @@ spfm_status run_steps(Obj* o, int64_t n) {
     return SPFM_OK;
 }
 
-// Resident kernel: n steps in launches of at most kResidentChunk steps each; a
-// launch of an odd count writes the other buffer, of an even count the same one.
-constexpr int kResidentChunk = 4096;
-constexpr int64_t kResidentAutoCells = 4096;   // largest stored grid AUTO steps resident
+// Resident kernel: n steps in launches of at most resident_chunk() steps each
+// (kResidentChunk for whole grids, the halo for segments); a whole-grid launch
+// of an odd count writes the other buffer, of an even count the same one, and a
+// segmented launch always the other one.
+constexpr int64_t kResidentAutoCells = 4096;   // largest stored grid AUTO steps resident untuned
 template <typename Obj>
 spfm_status run_resident(Obj* o, int64_t n) {
     if (n < 0) return fail(SPFM_E_INVAL, "negative step count");
     while (n > 0) {
-        const int chunk = (int)std::min<int64_t>(n, kResidentChunk);
-        const int to = (chunk & 1) ? 1 - o->cur : o->cur;
+        const int chunk = (int)std::min<int64_t>(n, o->resident_chunk());
+        const int to = ((chunk & 1) || !o->resident_in_place()) ? 1 - o->cur : o->cur;
         const hipError_t e = o->launch_resident(o->cur, to, chunk);
         if (e != hipSuccess) return fail(SPFM_E_HIP, "resident step launch: %s", hipGetErrorString(e));
         o->cur = to;
@@ -902,6 +935,137 @@ spfm_status run_resident(Obj* o, int64_t n) {
         n -= chunk;
     }
     return SPFM_OK;
+}
+
+// Resident segments: every grid's x axis cut into pieces of seg_len stored
+// columns (on a walled axis its interior, the ghost columns joining the end
+// pieces), each held with `halo` more columns on its open sides.  A grid whose
+// middle piece with its halos would span the grid stays whole.  Returns the
+// largest region in points.
+int64_t resident_items(const std::vector<GridDims>& dims, int walls, int seg_len, int halo,
+                       std::vector<ResItem>& out) {
+    out.clear();
+    int64_t cells = 0;
+    const int wx = walls & 1;
+    for (int g = 0; g < (int)dims.size(); ++g) {
+        const GridDims& d = dims[g];
+        const int xa = wx, xb = d.nx - wx;
+        const int64_t col = (int64_t)d.ny * d.nz;
+        if (seg_len <= 0 || (int64_t)seg_len + 2 * (int64_t)halo >= xb - xa) {
+            out.push_back(ResItem{g, 0, d.nx, 0, d.nx});
+            cells = std::max(cells, d.nx * col);
+            continue;
+        }
+        for (int s0 = xa; s0 < xb; s0 += seg_len) {
+            int ox = s0, oe = std::min(s0 + seg_len, xb);
+            if (wx && s0 == xa) ox = 0;
+            if (wx && oe == xb) oe = d.nx;
+            int rx0 = ox - halo, re = oe + halo;
+            if (wx) {
+                rx0 = std::max(rx0, 0);
+                re = std::min(re, d.nx);
+            }
+            out.push_back(ResItem{g, rx0, re - rx0, ox, oe - ox});
+            cells = std::max(cells, (int64_t)(re - rx0) * col);
+        }
+    }
+    return cells;
+}
+
+// Uploads the segments of (seg_len, halo) for the resident kernel of a batch
+// (seg_len 0: whole grids), after the stream has drained.
+spfm_status set_resident_segments(spfm_batch* b, int seg_len, int halo) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (seg_len <= 0) {
+        b->seg_len = b->seg_halo = b->nres = b->res_cells = 0;
+        return SPFM_OK;
+    }
+    std::vector<ResItem> items;
+    const int64_t cells = resident_items(b->dims, b->walls, seg_len, halo, items);
+    if (cells > resident_max_cells((int)sizeof(float)))
+        return fail(SPFM_E_INVAL, "a segment holds more than %d points", resident_max_cells((int)sizeof(float)));
+    if (items.size() > b->res_cap) {
+        if (b->d_res) (void)hipFree(b->d_res);
+        b->d_res = nullptr;
+        b->res_cap = 0;
+        if (hipMalloc(&b->d_res, items.size() * sizeof(ResItem)) != hipSuccess) {
+            (void)hipGetLastError();
+            b->d_res = nullptr;
+            return fail(SPFM_E_NOMEM, "device allocation of the resident segments failed");
+        }
+        b->res_cap = items.size();
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_res, items.data(), items.size() * sizeof(ResItem), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->seg_len = seg_len;
+    b->seg_halo = halo;
+    b->nres = (int)items.size();
+    b->res_cells = (int)cells;
+    return SPFM_OK;
+}
+
+// SPFM_KERNEL_AUTO on a batch whose grids fit the resident kernel: at the
+// first step, time the tiled kernel (its untuned schedule), whole grids, and x
+// segments of 4 to 64 columns with halos of 4 to 32 (those that cut some grid),
+// each over about 64 steps read from the current buffer and written to the
+// other one (the field does not change); keep the fastest, or the size rule's
+// choice (whole grids up to kResidentAutoCells stored points, else tiled)
+// unless another is at least 2% faster.  Two sweeps, the first untimed.
+spfm_status autotune_resident(spfm_batch* b) {
+    b->res_tuned = true;
+    struct Cand {
+        bool res;
+        int seg, halo;
+    };
+    std::vector<Cand> cand{Cand{b->resident, 0, 0}, Cand{!b->resident, 0, 0}};
+    static const int segs[5] = {4, 8, 16, 32, 64}, halos[4] = {4, 8, 16, 32};
+    std::vector<ResItem> tmp;
+    for (const int sl : segs)
+        for (const int h : halos) {
+            const int64_t cells = resident_items(b->dims, b->walls, sl, h, tmp);
+            if (tmp.size() > (size_t)b->n && cells <= resident_max_cells((int)sizeof(float)))
+                cand.push_back(Cand{true, sl, h});
+        }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(SPFM_E_HIP, "hipEventCreate"); }
+    std::vector<float> best(cand.size(), 1e30f);
+    spfm_status st = SPFM_OK;
+    for (int sweep = 0; sweep < 2 && st == SPFM_OK; ++sweep) {
+        for (size_t ci = 0; ci < cand.size() && st == SPFM_OK; ++ci) {
+            const Cand& c = cand[ci];
+            b->resident = c.res;
+            st = set_resident_segments(b, c.seg, c.halo);
+            if (st != SPFM_OK) break;
+            // steps per launch and launches: about 64 steps
+            const int spl = !c.res ? 1 : (c.seg > 0 ? c.halo : 16);
+            const int nl = std::max(1, 64 / spl);
+            hipError_t e = hipSuccess;
+            auto launch = [&]() {
+                return c.res ? b->launch_resident(b->cur, 1 - b->cur, spl) : b->launch_one(b->cur);
+            };
+            e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int i = 0; i < nl && e == hipSuccess; ++i) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = fail(SPFM_E_HIP, "resident autotune: %s", hipGetErrorString(e)); break; }
+            if (sweep > 0) best[ci] = std::min(best[ci], ms / (float)(nl * spl));
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+        if (best[ci] < best[bi]) bi = ci;
+    if (best[0] <= 1.02f * best[bi]) bi = 0;
+    if (st != SPFM_OK) bi = 0;
+    b->resident = cand[bi].res;
+    const spfm_status st2 = set_resident_segments(b, cand[bi].seg, cand[bi].halo);
+    return st != SPFM_OK ? st : st2;
 }
 
 spfm_status copy_in(void* dst, const void* src, size_t bytes, int src_on_device, hipStream_t s) {
@@ -961,6 +1125,10 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     spfm_ctx* c = new (std::nothrow) spfm_ctx;
     if (!c) return fail(SPFM_E_NOMEM, "host allocation failed");
     c->r = r;
+    if (r.seg_len > 0) {
+        delete c;
+        return fail(SPFM_E_INVAL, "segment is an option of batches");
+    }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(SPFM_E_HIP, "hipGetDevice failed");
@@ -1371,6 +1539,7 @@ void spfm_batch_destroy(spfm_batch* b) {
     if (b->d_coef) (void)hipFree(b->d_coef);
     if (b->d_offset) (void)hipFree(b->d_offset);
     if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_res) (void)hipFree(b->d_res);
     if (b->d_wall) (void)hipFree(b->d_wall);
     delete b;
 }
@@ -1440,14 +1609,16 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
     for (const GridDims& d : dims) largest = std::max<int64_t>(largest, (int64_t)d.nx * d.ny * d.nz);
     const bool fits = largest <= resident_max_cells((int)sizeof(float));
     b->max_cells = fits ? (int)largest : 0;
-    if (o.kernel == SPFM_KERNEL_RESIDENT && !fits) {
+    const int seg_asked = b->r[0].seg_len;   // the same options resolve every grid alike
+    if ((o.kernel == SPFM_KERNEL_RESIDENT || seg_asked > 0) && !fits) {
         spfm_batch_destroy(b);
         return fail(SPFM_E_INVAL, "the resident kernel holds at most %d stored points per grid",
                     resident_max_cells((int)sizeof(float)));
     }
     const int asked_tile = b->r[0].tile;   // the same options resolve every grid alike
-    b->resident = o.kernel == SPFM_KERNEL_RESIDENT ||
-                  (o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0 && asked_tile < 0 && largest <= kResidentAutoCells);
+    const bool autok = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0 && asked_tile < 0;
+    b->resident = o.kernel == SPFM_KERNEL_RESIDENT || seg_asked > 0 || (autok && largest <= kResidentAutoCells);
+    b->tune_res = autok && seg_asked == 0 && fits;
     b->tile = asked_tile >= 0 ? asked_tile : default_tile(true, b->coupling);
     b->tune_z = o.kernel == SPFM_KERNEL_AUTO && o.zchunk <= 0;
     b->tune_tile = o.kernel == SPFM_KERNEL_AUTO && asked_tile < 0;
@@ -1474,6 +1645,7 @@ spfm_status spfm_batch_create(int32_t n, const spfm_grid* grids, const double* l
         return fail(SPFM_E_HIP, "batch upload failed");
     }
     st = set_schedule(b, b->tile, zb);
+    if (st == SPFM_OK && seg_asked > 0) st = set_resident_segments(b, seg_asked, b->r[0].seg_halo);
     if (st != SPFM_OK) { spfm_batch_destroy(b); return st; }
     *out = b;
     return SPFM_OK;
@@ -1546,6 +1718,10 @@ spfm_status spfm_batch_get_field(spfm_batch* b, int32_t i, void* dst, int dst_on
 
 spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
     if (!b) return fail(SPFM_E_INVAL, "batch is NULL");
+    if (n > 0 && b->tune_res && !b->res_tuned) {
+        const spfm_status st = autotune_resident(b);
+        if (st != SPFM_OK) return st;
+    }
     if (b->resident) return run_resident(b, n);
     if (n > 0 && (b->tune_z || b->tune_tile) && !b->tuned) {
         spfm_status st = autotune(b);
@@ -1586,6 +1762,8 @@ spfm_status spfm_batch_get_info(const spfm_batch* b, spfm_batch_info* o) {
     o->zchunk = b->resident ? 0 : b->zlen;
     o->grids = b->n;
     o->points = b->points;
+    o->segment = b->resident ? b->seg_len : 0;
+    o->halo = b->resident ? b->seg_halo : 0;
     return SPFM_OK;
 }
 

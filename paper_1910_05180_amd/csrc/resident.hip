@@ -20,6 +20,16 @@
 //    their interior neighbours by Eq. 7 with the coefficient of their class.
 //  * The output may be the input buffer (an even number of steps): a block reads
 //    its whole grid before its first step and writes it after its last.
+//  * Segments: a grid too large for one CU's VALU to step quickly is cut along x
+//    into segments, one block each.  A block holds its segment plus a halo of h
+//    columns on each open side (the grid's own walls need none) and takes at most
+//    h steps: the values it has not updated, or updated from stale neighbours,
+//    advance one column per step from the open sides, so after h steps its
+//    segment is still exact.  The block writes back only its segment, to the
+//    other buffer (every block reads its halo from the input).  Each step does
+//    the same work on the same values as the tiled step, so the results are
+//    the same bit for bit; the halos are computed twice, which buys many blocks
+//    per grid and no synchronisation between them.
 #include "spfm_impl.h"
 
 namespace spfm {
@@ -57,24 +67,39 @@ __device__ __forceinline__ void column_plane(const T* __restrict__ F, int pl, in
 template <typename T, int S, int C, bool W>
 __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
     const T* buf_in, T* buf_out, const StepCoef<T>* __restrict__ coef,
-    const int64_t* __restrict__ offset, const WallCoef<T>* __restrict__ wall, int nsteps) {
+    const int64_t* __restrict__ offset, const WallCoef<T>* __restrict__ wall,
+    const ResItem* __restrict__ items, int nsteps) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
-    const int g = blockIdx.x;
     const int tid = threadIdx.x;
+    const int g = items ? items[blockIdx.x].inst : (int)blockIdx.x;
     const StepCoef<T> k = coef[g];
     const int sx = k.nx, sy = k.ny, sz = k.nz;
-    const int pl = sx * sy, cells = pl * sz;
+    // The region this block holds: stored x in [rx0, rx0 + rw) (mod sx on a
+    // periodic x axis), all y and z; it writes back x in [ox, ox + olen).
+    const ResItem it = items ? items[blockIdx.x] : ResItem{g, 0, sx, 0, sx};
+    const int rw = it.rw, rx0 = it.rx0;
+    const bool whole = rw == sx && rx0 == 0;
+    const int pl = rw * sy, cells = pl * sz;
     T* A = lds;
     T* B = lds + cells;
     const T* in = buf_in + offset[g];
     T* out = buf_out + offset[g];
-    for (int i = tid; i < cells; i += kResThreads) A[i] = in[i];
+    for (int i = tid; i < cells; i += kResThreads) {
+        const int lx = i % rw, row = i / rw;   // row = z sy + y
+        A[i] = in[(size_t)row * sx + wrap1(rx0 + lx, sx)];
+    }
     __syncthreads();   // the ghost fill reads cells that other threads loaded
 
     const int walls = W ? wall[g].walls : 0;
     const int wx = walls & 1, wy = (walls >> 1) & 1, wz = (walls >> 2) & 1;
-    const int nxi = sx - 2 * wx, nyi = sy - 2 * wy, nzi = sz - 2 * wz;
+    // Columns computed: the interior of a whole grid (x wraps when periodic);
+    // in a segment every column with both x neighbours in the region.  The
+    // outermost columns of an open side are never updated, so after n steps the
+    // n columns next to it are stale: the host gives each side a halo of at
+    // least nsteps columns beyond the segment written back.
+    const int xa = whole ? wx : 1, xb = whole ? sx - wx : rw - 1;
+    const int nxi = xb - xa, nyi = sy - 2 * wy, nzi = sz - 2 * wz;
     const int ncol = nxi * nyi;
     // z-segments per column: the count that minimises the planes a thread
     // touches, (points + 2 planes of each segment's halo) x segments per thread.
@@ -87,66 +112,75 @@ __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
             if (cost < best) { best = cost; nseg = q; }
         }
     }
-    const int items = ncol * nseg;
+    const int items_n = ncol * nseg;
 
     for (int step = 0; step < nsteps; ++step) {
         if (W) {   // ghosts of the current copy from their interior neighbours (Eq. 7)
             const WallCoef<T>& wc = wall[g];
             for (int i = tid; i < cells; i += kResThreads) {
-                const int x = i % sx, y = (i / sx) % sy, z = i / pl;
+                const int lx = i % rw, y = (i / rw) % sy, z = i / pl;
+                const int x = rx0 + lx;   // a walled x axis is never wrapped
                 const int cx = wx ? (x == 0 ? -1 : (x == sx - 1 ? 1 : 0)) : 0;
                 const int cy = wy ? (y == 0 ? -1 : (y == sy - 1 ? 1 : 0)) : 0;
                 const int cz = wz ? (z == 0 ? -1 : (z == sz - 1 ? 1 : 0)) : 0;
                 if (cx | cy | cz)
-                    A[i] = wall_map(A[(z - cz) * pl + (y - cy) * sx + (x - cx)],
+                    A[i] = wall_map(A[(z - cz) * pl + (y - cy) * rw + (lx - cx)],
                                     wc.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)]);
             }
         }
         __syncthreads();
-        for (int it = tid; it < items; it += kResThreads) {
-            const int col = it % ncol, seg = it / ncol;
-            const int x = wx + col % nxi, y = wy + col / nxi;
-            const int xm = wrap1(x - 1, sx), xp = wrap1(x + 1, sx);
+        for (int t = tid; t < items_n; t += kResThreads) {
+            const int col = t % ncol, seg = t / ncol;
+            const int x = xa + col % nxi, y = wy + col / nxi;
+            const int xm = whole ? wrap1(x - 1, sx) : x - 1, xp = whole ? wrap1(x + 1, sx) : x + 1;
             const int ym = wrap1(y - 1, sy), yp = wrap1(y + 1, sy);
             const int za = wz + (seg * nzi) / nseg, zb = wz + ((seg + 1) * nzi) / nseg;
             PlaneRegs<T> Rm{}, R0{}, Rp{};
-            column_plane<T, S, C>(A, pl, sx, wrap1(za - 1, sz), x, xm, xp, y, ym, yp, false, k.eps, Rm);
-            column_plane<T, S, C>(A, pl, sx, za, x, xm, xp, y, ym, yp, true, k.eps, R0);
+            column_plane<T, S, C>(A, pl, rw, wrap1(za - 1, sz), x, xm, xp, y, ym, yp, false, k.eps, Rm);
+            column_plane<T, S, C>(A, pl, rw, za, x, xm, xp, y, ym, yp, true, k.eps, R0);
             for (int z = za; z < zb; ++z) {
-                column_plane<T, S, C>(A, pl, sx, wrap1(z + 1, sz), x, xm, xp, y, ym, yp, true, k.eps, Rp);
-                B[z * pl + y * sx + x] = point_from_planes<T, S, C>(Rm, R0, Rp, k);
+                column_plane<T, S, C>(A, pl, rw, wrap1(z + 1, sz), x, xm, xp, y, ym, yp, true, k.eps, Rp);
+                B[z * pl + y * rw + x] = point_from_planes<T, S, C>(Rm, R0, Rp, k);
                 Rm = R0;
                 R0 = Rp;
             }
         }
         __syncthreads();
-        T* t = A;
+        T* tmp = A;
         A = B;
-        B = t;
+        B = tmp;
     }
-    for (int i = tid; i < cells; i += kResThreads) out[i] = A[i];
+    if (whole) {
+        for (int i = tid; i < cells; i += kResThreads) out[i] = A[i];
+    } else {
+        const int n = it.olen * sy * sz, lx0 = it.ox - rx0;
+        for (int i = tid; i < n; i += kResThreads) {
+            const int j = i % it.olen, row = i / it.olen;
+            out[(size_t)row * sx + it.ox + j] = A[row * rw + lx0 + j];
+        }
+    }
 }
 
 template <typename T, int S, int C>
 struct ResidentLaunch {
     static hipError_t run(const T* in, T* out, const StepCoef<T>* coef, const int64_t* offset,
-                          const WallCoef<T>* wall, int ngrids, int max_cells, int nsteps,
-                          hipStream_t s) {
+                          const WallCoef<T>* wall, const ResItem* items, int nblocks, int max_cells,
+                          int nsteps, hipStream_t s) {
         const size_t lds = 2 * (size_t)max_cells * sizeof(T);
         if (wall) {
             auto kfn = k_step_resident<T, S, C, true>;
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kfn, dim3(ngrids), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
-                               nsteps);
+            hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
+                               items, nsteps);
         } else {
             auto kfn = k_step_resident<T, S, C, false>;
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kfn, dim3(ngrids), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
-                               nsteps);
+            hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
+                               items, nsteps);
         }
         return hipGetLastError();
     }
@@ -171,19 +205,21 @@ int resident_max_cells(int elem_bytes) { return kResidentLdsBytes / (2 * elem_by
 
 template <typename T>
 hipError_t launch_step_resident(const T* buf_in, T* buf_out, const StepCoef<T>* d_coef,
-                                const int64_t* d_offset, const WallCoef<T>* d_wall, int ngrids,
-                                int max_cells, int nsteps, int stencil, int coupling, hipStream_t s) {
-    if (ngrids <= 0 || nsteps <= 0) return hipSuccess;
+                                const int64_t* d_offset, const WallCoef<T>* d_wall,
+                                const ResItem* d_items, int nblocks, int max_cells, int nsteps,
+                                int stencil, int coupling, hipStream_t s) {
+    if (nblocks <= 0 || nsteps <= 0) return hipSuccess;
     if (max_cells <= 0 || max_cells > resident_max_cells((int)sizeof(T))) return hipErrorInvalidValue;
-    return resident_dispatch<T>(stencil, coupling, buf_in, buf_out, d_coef, d_offset, d_wall, ngrids,
-                                max_cells, nsteps, s);
+    if (d_items && buf_in == buf_out) return hipErrorInvalidValue;   // blocks read each other's halos
+    return resident_dispatch<T>(stencil, coupling, buf_in, buf_out, d_coef, d_offset, d_wall, d_items,
+                                nblocks, max_cells, nsteps, s);
 }
 
 template hipError_t launch_step_resident<float>(const float*, float*, const StepCoef<float>*,
-                                                const int64_t*, const WallCoef<float>*, int, int, int,
-                                                int, int, hipStream_t);
+                                                const int64_t*, const WallCoef<float>*, const ResItem*,
+                                                int, int, int, int, int, hipStream_t);
 template hipError_t launch_step_resident<double>(const double*, double*, const StepCoef<double>*,
-                                                 const int64_t*, const WallCoef<double>*, int, int,
-                                                 int, int, int, hipStream_t);
+                                                 const int64_t*, const WallCoef<double>*, const ResItem*,
+                                                 int, int, int, int, int, hipStream_t);
 
 }  // namespace spfm

@@ -549,12 +549,24 @@ hipError_t launch_step_batched(const float* buf_in, float* buf_out, const StepCo
 // (two copies, 2 x cells x sizeof(T) <= kResidentLdsBytes) and takes nsteps steps
 // in one launch: reads buf_in + offset[g], writes buf_out + offset[g] (which may
 // be the same buffer).  Results equal nsteps tiled steps bit for bit.
+// d_items null: block g holds grid g whole.  Otherwise block b holds the part
+// of grid items[b].inst given there (x segments with halos, see resident.hip):
+// then nsteps must not exceed any halo, buf_in and buf_out must differ, and
+// max_cells bounds the cells of any block's region.
+struct ResItem {
+    int inst;   // grid
+    int rx0;    // region: stored x in [rx0, rx0 + rw), mod nx (rx0 < 0 wraps a periodic axis)
+    int rw;
+    int ox;     // columns written back: stored x in [ox, ox + olen)
+    int olen;
+};
 constexpr int kResidentLdsBytes = 163840;   // gfx950: LDS one workgroup may allocate
 int resident_max_cells(int elem_bytes);
 template <typename T>
 hipError_t launch_step_resident(const T* buf_in, T* buf_out, const StepCoef<T>* d_coef,
-                                const int64_t* d_offset, const WallCoef<T>* d_wall, int ngrids,
-                                int max_cells, int nsteps, int stencil, int coupling, hipStream_t s);
+                                const int64_t* d_offset, const WallCoef<T>* d_wall,
+                                const ResItem* d_items, int nblocks, int max_cells, int nsteps,
+                                int stencil, int coupling, hipStream_t s);
 // Tile shapes of the single-step tiled kernels: a block marches one tile
 // column TX x TY along z, each of its waves computing a 16 x 4 patch.  The
 // untuned shapes: FP32 TI_n uses 16 x 8 columns (two waves): its full-coupling
@@ -580,10 +592,12 @@ constexpr bool tile_compiled(bool f32, int C, bool W, int t) {
            (!W && (f32 ? C <= kCF : (C == kLocal && (t == kTile32x8 || t == kTile16x8))));
 }
 constexpr int kWaveX = 16;
-// LDS row stride of a staged halo plane.  48 and 80 put the rows of a 16 x 4
-// wave patch in distinct LDS banks; the 16-wide tiles keep 18, the smallest,
-// since their blocks are many per CU and larger rows would cap them by LDS.
-constexpr int lds_row(int tx) { return tx == 16 ? 18 : (tx == 32 ? 48 : 80); }
+// LDS row stride of a staged halo plane: 48 (16- and 32-wide tiles) and 80
+// (64-wide) put the four rows of a 16 x 4 wave patch in distinct LDS banks.
+// Every smaller stride that holds a 16-wide row and its halo gives two-way bank
+// conflicts; 48 caps 16 x 8 blocks at 10 per CU by LDS (5 waves per SIMD
+// instead of 7) and still runs the TI_n step 1.8% faster.
+constexpr int lds_row(int tx) { return tx == 64 ? 80 : 48; }
 constexpr int kTileZ = 32;   // default planes per block (the z-chunk is a launch argument)
 constexpr int kNumXcd = 8;   // MI355X: workgroup IDs are dealt to the 8 XCDs round robin
 

@@ -260,17 +260,17 @@ struct Smem {
 #ifndef SPFM_WAVES_F32
 #define SPFM_WAVES_F32 7
 #endif
-// Waves per SIMD the tiled kernels are compiled for: FP32 TI_n fits in 72 VGPRs
-// (7 waves; left free, the compiler takes 79 and 6 waves, which ran 1.5%
-// slower); FP64 TI_n needs more than twice as many (2 waves, no spills).  The
+// Waves per SIMD the tiled kernels are compiled for: FP32 TI_n on 16-wide
+// tiles is held to 5 by its LDS (two staged arrays of row stride 48), the
+// wider tiles need a few more registers than 7 waves allow (they spill at 72)
+// and are compiled for 6; the FP32 couplings without psi' staging take 7; FP64
+// TI_n needs more than twice as many registers (2 waves, no spills).  The
 // walled variants (small grids, never many waves) are compiled for fewer waves,
 // which keeps them free of spills.
-// FP32 TI_n on tiles wider than 16 needs a few more registers (it spills at 72)
-// and is compiled for 6 waves.
 // The constant-volume variants carry two 128-bit sums per thread (4 waves FP32).
 template <typename T, int C = kLocal, int TX = 16>
 struct WavesPerSimd {
-    static constexpr int value = sizeof(T) == 4 ? (C == kLocal && TX != 16 ? 6 : SPFM_WAVES_F32) : 2;
+    static constexpr int value = sizeof(T) == 4 ? (C == kLocal ? (TX == 16 ? 5 : 6) : SPFM_WAVES_F32) : 2;
     static constexpr int walled = sizeof(T) == 4 ? 4 : 2;
 };
 template <typename T, int C, bool W, bool V, int TX>

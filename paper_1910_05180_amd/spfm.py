@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("zchunk", ctypes.c_int32), ("tsteps", ctypes.c_int32),
                 ("walls", ctypes.c_int32), ("wall_sin", ctypes.c_double * 6),
                 ("interp", ctypes.c_int32), ("conserve_volume", ctypes.c_int32),
-                ("batch_wall_sin", ctypes.c_void_p), ("tile", ctypes.c_int32 * 2)]
+                ("batch_wall_sin", ctypes.c_void_p), ("tile", ctypes.c_int32 * 2),
+                ("segment", ctypes.c_int32 * 2)]
 
 
 class Diag(ctypes.Structure):
@@ -72,7 +73,8 @@ class Info(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32), ("grids", ctypes.c_int32), ("points", ctypes.c_int64)]
+                ("zchunk", ctypes.c_int32), ("grids", ctypes.c_int32), ("points", ctypes.c_int64),
+                ("segment", ctypes.c_int32), ("halo", ctypes.c_int32)]
 
 
 class Contour(ctypes.Structure):
@@ -176,7 +178,7 @@ def _stream_handle(stream):
 def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma=None,
              C_Gamma=None, eps=None, tau=None, kernel="auto", stream=None,
              allow_unstable=False, zchunk=0, tsteps=0, walls=0, wall_sin=None,
-             interp="h3", conserve_volume=False, tile=None) -> Options:
+             interp="h3", conserve_volume=False, tile=None, segment=None) -> Options:
     o = Options()
     o.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.coupling = _COUPLINGS[coupling] if isinstance(coupling, str) else int(coupling)
@@ -196,6 +198,7 @@ def _options(*, dtype="f32", coupling="local", u=(1.0, 0.0, 0.0), dt=None, gamma
     o.interp = _INTERPS[interp] if isinstance(interp, str) else int(interp)
     o.conserve_volume = 1 if conserve_volume else 0
     o.tile[:] = [int(v) for v in tile] if tile is not None else [0, 0]
+    o.segment[:] = [int(v) for v in segment] if segment is not None else [0, 0]
     return o
 
 

@@ -119,9 +119,9 @@ def test_batch_zchunk_choice_does_not_change_results(S):
             b.step(30)
             chosen[name] = b.zchunk
             out[name] = [b.get_field(i) for i in range(len(cases))]
-    assert chosen["auto"] in (4, 8, 16, 32, 64)
+    assert chosen["auto"] in (2, 4, 8, 16, 32, 64)
     assert chosen["auto_z7"] == 7 and chosen["z32"] == 32
-    assert chosen["tiled"] == 4   # 278824 points: 32 planes would give 2^16 threads
+    assert chosen["tiled"] in (2, 4)   # 278824 points: 32 planes would give 2^16 threads
     for name in ("tiled", "auto_z7", "z32"):
         for i in range(len(cases)):
             assert np.array_equal(out[name][i], out["auto"][i]), (name, i)

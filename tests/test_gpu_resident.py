@@ -7,7 +7,9 @@ batch and the model-comparison slabs of the other tests run it too; here it is
 compared with the tiled batched kernel explicitly, across couplings, stencils,
 driving-force interpolations, walls, grid shapes that wrap onto themselves,
 odd and even step counts (the output goes to the other buffer or back into the
-same one) and runs longer than one launch's share of steps."""
+same one) and runs longer than one launch's share of steps.  Grids cut into x
+segments (one workgroup each, redundant halos, at most a halo's worth of steps
+per launch) must give the same bits again."""
 import math
 
 import numpy as np
@@ -165,3 +167,92 @@ def test_context_matches_oracle_and_tiled(S, dtype, tol, walls):
             out[kernel] = s.get_field()
     assert float(np.abs(out["resident"].astype(np.float64) - ref).max()) <= tol
     assert np.array_equal(out["resident"], out["tiled"])
+
+
+def segment_batch(S, shapes, segment, steps, init, kernel="resident", **kw):
+    with S.SpfmBatch(shapes, kernel=kernel, segment=segment, **kw) as b:
+        init(b)
+        out = []
+        for n in steps:
+            b.step(n)
+            out.append([b.get_field(i) for i in range(len(shapes))])
+        info = b.info()
+        d = b.diagnostics()
+    return out, info, d
+
+
+@pytest.mark.parametrize("segment", [(8, 4), (16, 8), (4, 32), (1, 1), (30, 3)])
+def test_walled_orientation_segments_equal_tiled(S, segment):
+    """The walled orientation batch (TI_n, 26 neighbours) cut into x segments:
+    1, 2, 97 and 300 more steps equal the tiled kernel bit for bit."""
+    ns = [np.asarray(n) / np.linalg.norm(n) for n in
+          [(1, 0, 0), rot011(math.radians(15)), rot011(math.radians(45)), (0.8, 0.6, 0.0)]]
+    sins = [oracle.front_sin_alpha(n) for n in ns]
+    kw = dict(lam=4.0, mu=[0.05 * n[0] for n in ns], stencil=26, coupling="local", dt=0.05, walls=7,
+              wall_sin=sins)
+    init = lambda b: b.init_front(ns, [20.0] * len(ns))
+    print(f"case resident segments {segment} orientation", flush=True)
+    r, info, dr = segment_batch(S, [(10, 10, 120)] * len(ns), segment, [1, 2, 97, 300], init, **kw)
+    assert info["kernel"] == S.KERNEL_RESIDENT and (info["segment"], info["halo"]) == segment
+    t, dt_ = batch_fields(S, [(10, 10, 120)] * len(ns), "tiled", [1, 2, 97, 300], init, **kw)
+    assert_bitwise(r, t)
+    for a, b in zip(dr, dt_):
+        assert a["interface_position"] == b["interface_position"] and a["step"] == 400
+
+
+@pytest.mark.parametrize("coupling,interp", [("local", "h3"), ("global", "h3"), ("cf", "h5")])
+@pytest.mark.parametrize("segment", [(8, 4), (16, 16), (5, 2)])
+def test_periodic_segments_equal_tiled(S, coupling, interp, segment):
+    """Periodic slabs and ragged grids, some long enough to be cut (their
+    segments' halos wrap around the x axis), some kept whole in the same launch:
+    7 and 10 steps equal the tiled kernel bit for bit."""
+    shapes = [(3, 3, 256), (3, 3, 64), (5, 4, 33), (7, 11, 9), (4, 6, 101)]
+    hkl = [(1, 0, 0), (1, 1, 1), (2, 1, 1), (1, 2, 3), (3, 1, 0)]
+    mu = 0.3 if coupling == "cf" else 0.04
+    kw = dict(lam=2.5, mu=mu, stencil=26, coupling=coupling, interp=interp, u=(1.0, 2.0, 0.0), dt=0.02)
+    init = lambda b: b.init_planar(hkl, [0.3, 0.1, 0.7, 0.2, 0.5])
+    print(f"case resident segments {segment} periodic {coupling}+{interp}", flush=True)
+    r, _, _ = segment_batch(S, shapes, segment, [7, 10], init, **kw)
+    t, _ = batch_fields(S, shapes, "tiled", [7, 10], init, **kw)
+    assert_bitwise(r, t)
+
+
+def test_segments_over_many_launches_match_oracle(S):
+    """Segments with a halo of 3 over 301 steps (101 launches, the last one
+    step): within the FP32 bar of the oracle and equal to the tiled kernel."""
+    shapes = [(4, 5, 90), (3, 3, 47)]
+    lam, mu, steps = 3.0, 0.02, 301
+    hkl = [(1, 0, 0), (2, 1, 0)]
+    fields = [as_f32_input(oracle.init_planar(sh, h, 0.4, lam=lam)) for sh, h in zip(shapes, hkl)]
+    ps = [oracle.params(sh, lam=lam, mu=mu, stencil=18, coupling="local", eps=1e-30) for sh in shapes]
+    dt = min(stable_dt(p) for p in ps)
+    kw = dict(lam=lam, mu=mu, stencil=18, coupling="local", dt=dt)
+    def init(b):
+        for i, f in enumerate(fields):
+            b.set_field(i, f)
+    print("case resident segments 301 steps", flush=True)
+    r, info, _ = segment_batch(S, shapes, (7, 3), [steps], init, **kw)
+    t, _ = batch_fields(S, shapes, "tiled", [steps], init, **kw)
+    assert_bitwise(r, t)
+    for i, p in enumerate(ps):
+        p.dt = dt
+        ref = oracle.step(p, fields[i], steps)
+        assert float(np.abs(r[0][i].astype(np.float64) - ref).max()) <= 1e-5, i
+
+
+def test_auto_picks_a_kernel_by_timing_and_equals_tiled(S):
+    """Kernel AUTO on a batch of small grids times the tiled kernel, whole grids
+    and x segments at the first step; whatever it keeps, the fields equal the
+    tiled kernel's bit for bit, and the batch reports its choice."""
+    shapes = [(10, 10, 120)] * 3 + [(3, 3, 256)] * 2
+    hkl = [(1, 0, 0), (2, 1, 0), (1, 1, 1), (1, 0, 0), (3, 1, 1)]
+    kw = dict(lam=4.0, mu=0.02, stencil=26, coupling="local", dt=0.05)
+    init = lambda b: b.init_planar(hkl, [0.2, 0.4, 0.6, 0.1, 0.3])
+    print("case resident auto", flush=True)
+    a, info, _ = segment_batch(S, shapes, None, [50, 3], init, kernel="auto", **kw)
+    print(f"  auto chose {info}", flush=True)
+    assert info["kernel"] in (S.KERNEL_RESIDENT, S.KERNEL_TILED)
+    if info["kernel"] == S.KERNEL_TILED:
+        assert info["segment"] == 0 and info["halo"] == 0
+    t, _ = batch_fields(S, shapes, "tiled", [50, 3], init, **kw)
+    assert_bitwise(a, t)

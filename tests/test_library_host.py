@@ -193,6 +193,30 @@ def test_resident_batch_refuses_a_grid_it_cannot_hold(S):
     assert st == -1 and "resident" in msg, msg
 
 
+@pytest.mark.parametrize("kw", [dict(segment=(0, 4)), dict(segment=(8, 0)), dict(segment=(8, 5000)),
+                                dict(segment=(-1, 4)), dict(segment=(8, 4), kernel="tiled")])
+def test_batch_segments_are_validated(S, kw):
+    """Resident x segments need a length >= 1, a halo in 1..4096 and the
+    resident kernel (or AUTO)."""
+    st, msg = try_batch(S, [(8, 8, 40)], **kw)
+    assert st == -1 and "segment" in msg, msg
+
+
+def test_segments_are_an_option_of_batches(S):
+    st, msg = S.try_create((8, 8, 40), segment=(8, 4))
+    assert st == -1 and "segment" in msg, msg
+
+
+def test_segmented_batch_refuses_a_grid_the_resident_kernel_cannot_hold(S):
+    st, msg = try_batch(S, [(8, 8, 8), (32, 32, 32)], segment=(8, 4))
+    assert st == -1 and "resident" in msg, msg
+
+
+def test_segmented_batch_accepts_what_fits(S):
+    st, msg = try_batch(S, [(10, 10, 120), (3, 3, 256)], segment=(8, 4), walls=0)
+    assert st != -1, msg
+
+
 @pytest.mark.parametrize("kw", [
     dict(tile=(8, 8)), dict(tile=(16, 4)), dict(tile=(128, 8)),
     dict(tile=(32, 8), walls=1),                     # walled grids: the default shape only
