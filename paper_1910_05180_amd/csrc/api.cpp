@@ -569,8 +569,13 @@ struct spfm_batch {
     int resident_chunk() const { return seg_len > 0 ? seg_halo : kResidentChunk; }
     bool resident_in_place() const { return seg_len == 0; }
 
-    int unit() const { return 1; }
-    hipError_t launch_unit(int from) { return launch_one(from); }
+    // Steps per unit launch: one, or a halo's worth for resident segments, whose
+    // launches then run like tiled ones (graph replays, out of place).
+    bool segmented() const { return resident && seg_len > 0; }
+    int unit() const { return segmented() ? seg_halo : 1; }
+    hipError_t launch_unit(int from) {
+        return segmented() ? launch_resident(from, 1 - from, seg_halo) : launch_one(from);
+    }
     hipError_t launch_one(int from) {
         if (resident) return launch_resident(from, 1 - from, 1);
         return launch_step_batched(buf[from], buf[1 - from], d_coef, d_offset, d_items, nitems,
@@ -976,6 +981,7 @@ int64_t resident_items(const std::vector<GridDims>& dims, int walls, int seg_len
 // (seg_len 0: whole grids), after the stream has drained.
 spfm_status set_resident_segments(spfm_batch* b, int seg_len, int halo) {
     HIP_TRY(hipStreamSynchronize(b->stream));
+    b->graphs.clear();   // captured launches of the previous configuration
     if (seg_len <= 0) {
         b->seg_len = b->seg_halo = b->nres = b->res_cells = 0;
         return SPFM_OK;
@@ -1722,6 +1728,7 @@ spfm_status spfm_batch_step(spfm_batch* b, int64_t n) {
         const spfm_status st = autotune_resident(b);
         if (st != SPFM_OK) return st;
     }
+    if (b->segmented()) return run_steps(b, n);
     if (b->resident) return run_resident(b, n);
     if (n > 0 && (b->tune_z || b->tune_tile) && !b->tuned) {
         spfm_status st = autotune(b);

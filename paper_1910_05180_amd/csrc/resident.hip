@@ -30,6 +30,8 @@
 //    the same work on the same values as the tiled step, so the results are
 //    the same bit for bit; the halos are computed twice, which buys many blocks
 //    per grid and no synchronisation between them.
+#include <atomic>
+
 #include "spfm_impl.h"
 
 namespace spfm {
@@ -161,23 +163,38 @@ __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
     }
 }
 
+// Lets kernel kfn take up to kResidentLdsBytes of dynamic LDS on the current
+// device; set once per kernel and device (segmented runs launch often, and the
+// attribute call costs host time on every launch).
+template <typename K>
+hipError_t allow_resident_lds(K kfn, std::atomic<unsigned>& done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned bit = dev < 32 ? 1u << dev : 0u;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kResidentLdsBytes);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
+
 template <typename T, int S, int C>
 struct ResidentLaunch {
     static hipError_t run(const T* in, T* out, const StepCoef<T>* coef, const int64_t* offset,
                           const WallCoef<T>* wall, const ResItem* items, int nblocks, int max_cells,
                           int nsteps, hipStream_t s) {
+        static std::atomic<unsigned> done_walled{0}, done_periodic{0};
         const size_t lds = 2 * (size_t)max_cells * sizeof(T);
         if (wall) {
             auto kfn = k_step_resident<T, S, C, true>;
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const hipError_t e = allow_resident_lds(kfn, done_walled);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
                                items, nsteps);
         } else {
             auto kfn = k_step_resident<T, S, C, false>;
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const hipError_t e = allow_resident_lds(kfn, done_periodic);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
                                items, nsteps);
