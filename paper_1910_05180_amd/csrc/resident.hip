@@ -13,9 +13,12 @@
 //    z-segments so that the columns and segments spread evenly over the
 //    threads; a thread marches its segment along z keeping the per-plane sums
 //    of three planes in registers, as the tiled sweep does.
-//  * TI_n: psi' of a neighbour is evaluated where it is needed (four in-plane
-//    face neighbours and the column cell of each plane) instead of being
-//    staged: the two field copies use the LDS.
+//  * TI_n: psi' of every cell is refreshed once per step into a third LDS
+//    array when the region's three copies fit (13653 FP32 or 6826 FP64
+//    points), else each point evaluates it for the cells it needs (the column
+//    cell and four in-plane face neighbours of each plane).
+//  * Regions of at most two cells per thread and one work item per thread keep
+//    their ghost and column indices in registers across the steps.
 //  * Walls: before each step the ghost cells of the current copy are set from
 //    their interior neighbours by Eq. 7 with the coefficient of their class.
 //  * The output may be the input buffer (an even number of steps): a block reads
@@ -45,28 +48,38 @@ __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >
 // Per-plane sums of the column (x, y) on plane z of the field F (row stride sx,
 // plane stride pl), with the same association as plane_sums on a staged tile:
 // xm, xp, ym, yp are the wrapped (or, next to a wall, ghost) neighbour indices.
-template <typename T, int S, int C>
-__device__ __forceinline__ void column_plane(const T* __restrict__ F, int pl, int sx, int z, int x,
-                                             int xm, int xp, int y, int ym, int yp, bool with_grad,
-                                             T eps, PlaneRegs<T>& R) {
-    const T* Q = F + (size_t)z * pl;
-    const T* r0 = Q + y * sx;
-    const T* rm = Q + ym * sx;
-    const T* rp = Q + yp * sx;
-    const T e = r0[xp], w = r0[xm], n = rp[x], s = rm[x];
-    R.c = r0[x];
+// PS: psi' of every cell is staged in Ps (same layout); else it is evaluated
+// here for the cells that need it.
+template <typename T, int S, int C, bool PS>
+__device__ __forceinline__ void column_plane(const T* __restrict__ F, const T* __restrict__ Ps, int pl,
+                                             int sx, int z, int x, int xm, int xp, int y, int ym, int yp,
+                                             bool with_grad, T eps, PlaneRegs<T>& R) {
+    const int q = z * pl, o0 = q + y * sx, om = q + ym * sx, op = q + yp * sx;
+    const T e = F[o0 + xp], w = F[o0 + xm], n = F[op + x], s = F[om + x];
+    R.c = F[o0 + x];
     R.fc = (e + w) + (n + s);
-    if (S >= 18) R.dc = (rp[xp] + rm[xm]) + (rp[xm] + rm[xp]);
+    if (S >= 18) R.dc = (F[op + xp] + F[om + xm]) + (F[op + xm] + F[om + xp]);
     if (C == kLocal) {
-        R.pc = psi2(R.c, eps);
-        if (with_grad) {
-            R.gx = psi2(e, eps) - psi2(w, eps);
-            R.gy = psi2(n, eps) - psi2(s, eps);
+        if (PS) {
+            R.pc = Ps[o0 + x];
+            if (with_grad) {
+                R.gx = Ps[o0 + xp] - Ps[o0 + xm];
+                R.gy = Ps[op + x] - Ps[om + x];
+            }
+        } else {
+            R.pc = psi2(R.c, eps);
+            if (with_grad) {
+                R.gx = psi2(e, eps) - psi2(w, eps);
+                R.gy = psi2(n, eps) - psi2(s, eps);
+            }
         }
     }
 }
 
-template <typename T, int S, int C, bool W>
+// PS (TI_n): a third LDS array holds psi' of every cell of the current copy,
+// refreshed once per step, instead of each point evaluating it for its column
+// and four in-plane neighbours on three planes.
+template <typename T, int S, int C, bool W, bool PS>
 __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
     const T* buf_in, T* buf_out, const StepCoef<T>* __restrict__ coef,
     const int64_t* __restrict__ offset, const WallCoef<T>* __restrict__ wall,
@@ -85,6 +98,7 @@ __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
     const int pl = rw * sy, cells = pl * sz;
     T* A = lds;
     T* B = lds + cells;
+    T* P = lds + 2 * cells;   // PS only
     const T* in = buf_in + offset[g];
     T* out = buf_out + offset[g];
     for (int i = tid; i < cells; i += kResThreads) {
@@ -116,36 +130,90 @@ __global__ __launch_bounds__(kResThreads, 1) void k_step_resident(
     }
     const int items_n = ncol * nseg;
 
+    // Work item t: column and z range, neighbour indices.
+    struct Item {
+        int x, xm, xp, y, ym, yp, za, zb;
+    };
+    auto item = [&](int t) {
+        const int col = t % ncol, seg = t / ncol;
+        Item m;
+        m.x = xa + col % nxi;
+        m.y = wy + col / nxi;
+        m.xm = whole ? wrap1(m.x - 1, sx) : m.x - 1;
+        m.xp = whole ? wrap1(m.x + 1, sx) : m.x + 1;
+        m.ym = wrap1(m.y - 1, sy);
+        m.yp = wrap1(m.y + 1, sy);
+        m.za = wz + (seg * nzi) / nseg;
+        m.zb = wz + ((seg + 1) * nzi) / nseg;
+        return m;
+    };
+    auto march = [&](const Item& m, const T* F, T* G) {
+        PlaneRegs<T> Rm{}, R0{}, Rp{};
+        column_plane<T, S, C, PS>(F, P, pl, rw, wrap1(m.za - 1, sz), m.x, m.xm, m.xp, m.y, m.ym, m.yp,
+                                  false, k.eps, Rm);
+        column_plane<T, S, C, PS>(F, P, pl, rw, m.za, m.x, m.xm, m.xp, m.y, m.ym, m.yp, true, k.eps, R0);
+        for (int z = m.za; z < m.zb; ++z) {
+            column_plane<T, S, C, PS>(F, P, pl, rw, wrap1(z + 1, sz), m.x, m.xm, m.xp, m.y, m.ym, m.yp, true,
+                                      k.eps, Rp);
+            G[z * pl + m.y * rw + m.x] = point_from_planes<T, S, C>(Rm, R0, Rp, k);
+            Rm = R0;
+            R0 = Rp;
+        }
+    };
+    // Ghost cell i: its interior neighbour and the Eq. 7 coefficient of its
+    // class, or src < 0 for an interior cell.
+    auto ghost = [&](int i, int& src, int& cls) {
+        const int lx = i % rw, y = (i / rw) % sy, z = i / pl;
+        const int x = rx0 + lx;   // a walled x axis is never wrapped
+        const int cx = wx ? (x == 0 ? -1 : (x == sx - 1 ? 1 : 0)) : 0;
+        const int cy = wy ? (y == 0 ? -1 : (y == sy - 1 ? 1 : 0)) : 0;
+        const int cz = wz ? (z == 0 ? -1 : (z == sz - 1 ? 1 : 0)) : 0;
+        src = (cx | cy | cz) ? (z - cz) * pl + (y - cy) * rw + (lx - cx) : -1;
+        cls = (cx + 1) + 3 * (cy + 1) + 9 * (cz + 1);
+    };
+    // Regions of at most two cells per thread and one work item per thread
+    // (segments, small grids) keep their cells' and item's indices in registers
+    // for every step; larger ones recompute them.
+    const bool few = cells <= 2 * kResThreads && items_n <= kResThreads;
+    int src0 = -1, cls0 = 0, src1 = -1, cls1 = 0;
+    Item m0{};
+    if (few) {
+        if (W) {
+            ghost(tid, src0, cls0);
+            if (tid + kResThreads < cells) ghost(tid + kResThreads, src1, cls1);
+        }
+        if (tid < items_n) m0 = item(tid);
+    }
+
     for (int step = 0; step < nsteps; ++step) {
-        if (W) {   // ghosts of the current copy from their interior neighbours (Eq. 7)
-            const WallCoef<T>& wc = wall[g];
+        // Ghosts of the current copy from their interior neighbours (Eq. 7),
+        // then (PS) psi' of every cell.  A ghost's source is an interior cell,
+        // which no thread writes in this phase.
+        if (few) {
+            if (tid < cells) {
+                if (W && src0 >= 0) A[tid] = wall_map(A[src0], wall[g].a[cls0]);
+                if (PS) P[tid] = psi2(A[tid], k.eps);
+            }
+            const int i1 = tid + kResThreads;
+            if (i1 < cells) {
+                if (W && src1 >= 0) A[i1] = wall_map(A[src1], wall[g].a[cls1]);
+                if (PS) P[i1] = psi2(A[i1], k.eps);
+            }
+        } else if (W || PS) {
             for (int i = tid; i < cells; i += kResThreads) {
-                const int lx = i % rw, y = (i / rw) % sy, z = i / pl;
-                const int x = rx0 + lx;   // a walled x axis is never wrapped
-                const int cx = wx ? (x == 0 ? -1 : (x == sx - 1 ? 1 : 0)) : 0;
-                const int cy = wy ? (y == 0 ? -1 : (y == sy - 1 ? 1 : 0)) : 0;
-                const int cz = wz ? (z == 0 ? -1 : (z == sz - 1 ? 1 : 0)) : 0;
-                if (cx | cy | cz)
-                    A[i] = wall_map(A[(z - cz) * pl + (y - cy) * rw + (lx - cx)],
-                                    wc.a[(cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)]);
+                if (W) {
+                    int src, cls;
+                    ghost(i, src, cls);
+                    if (src >= 0) A[i] = wall_map(A[src], wall[g].a[cls]);
+                }
+                if (PS) P[i] = psi2(A[i], k.eps);
             }
         }
         __syncthreads();
-        for (int t = tid; t < items_n; t += kResThreads) {
-            const int col = t % ncol, seg = t / ncol;
-            const int x = xa + col % nxi, y = wy + col / nxi;
-            const int xm = whole ? wrap1(x - 1, sx) : x - 1, xp = whole ? wrap1(x + 1, sx) : x + 1;
-            const int ym = wrap1(y - 1, sy), yp = wrap1(y + 1, sy);
-            const int za = wz + (seg * nzi) / nseg, zb = wz + ((seg + 1) * nzi) / nseg;
-            PlaneRegs<T> Rm{}, R0{}, Rp{};
-            column_plane<T, S, C>(A, pl, rw, wrap1(za - 1, sz), x, xm, xp, y, ym, yp, false, k.eps, Rm);
-            column_plane<T, S, C>(A, pl, rw, za, x, xm, xp, y, ym, yp, true, k.eps, R0);
-            for (int z = za; z < zb; ++z) {
-                column_plane<T, S, C>(A, pl, rw, wrap1(z + 1, sz), x, xm, xp, y, ym, yp, true, k.eps, Rp);
-                B[z * pl + y * rw + x] = point_from_planes<T, S, C>(Rm, R0, Rp, k);
-                Rm = R0;
-                R0 = Rp;
-            }
+        if (few) {
+            if (tid < items_n) march(m0, A, B);
+        } else {
+            for (int t = tid; t < items_n; t += kResThreads) march(item(t), A, B);
         }
         __syncthreads();
         T* tmp = A;
@@ -181,25 +249,32 @@ hipError_t allow_resident_lds(K kfn, std::atomic<unsigned>& done) {
 
 template <typename T, int S, int C>
 struct ResidentLaunch {
+    template <bool W, bool PS>
+    static hipError_t go(const T* in, T* out, const StepCoef<T>* coef, const int64_t* offset,
+                         const WallCoef<T>* wall, const ResItem* items, int nblocks, size_t lds,
+                         int nsteps, hipStream_t s) {
+        static std::atomic<unsigned> done{0};
+        auto kfn = k_step_resident<T, S, C, W, PS>;
+        const hipError_t e = allow_resident_lds(kfn, done);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall, items,
+                           nsteps);
+        return hipGetLastError();
+    }
     static hipError_t run(const T* in, T* out, const StepCoef<T>* coef, const int64_t* offset,
                           const WallCoef<T>* wall, const ResItem* items, int nblocks, int max_cells,
                           int nsteps, hipStream_t s) {
-        static std::atomic<unsigned> done_walled{0}, done_periodic{0};
-        const size_t lds = 2 * (size_t)max_cells * sizeof(T);
-        if (wall) {
-            auto kfn = k_step_resident<T, S, C, true>;
-            const hipError_t e = allow_resident_lds(kfn, done_walled);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
-                               items, nsteps);
-        } else {
-            auto kfn = k_step_resident<T, S, C, false>;
-            const hipError_t e = allow_resident_lds(kfn, done_periodic);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kfn, dim3(nblocks), dim3(kResThreads), lds, s, in, out, coef, offset, wall,
-                               items, nsteps);
+        // TI_n stages psi' in a third copy when the LDS holds it
+        if constexpr (C == kLocal) {
+            if (3 * (size_t)max_cells * sizeof(T) <= (size_t)kResidentLdsBytes) {
+                const size_t lds = 3 * (size_t)max_cells * sizeof(T);
+                return wall ? go<true, true>(in, out, coef, offset, wall, items, nblocks, lds, nsteps, s)
+                            : go<false, true>(in, out, coef, offset, wall, items, nblocks, lds, nsteps, s);
+            }
         }
-        return hipGetLastError();
+        const size_t lds = 2 * (size_t)max_cells * sizeof(T);
+        return wall ? go<true, false>(in, out, coef, offset, wall, items, nblocks, lds, nsteps, s)
+                    : go<false, false>(in, out, coef, offset, wall, items, nblocks, lds, nsteps, s);
     }
 };
 
