@@ -360,10 +360,14 @@ spfm_status spfm_batch_init_front(spfm_batch *b, const double *n /* 3n */,
 spfm_status spfm_batch_set_field(spfm_batch *b, int32_t i, const void *src, int src_on_device);
 spfm_status spfm_batch_get_field(spfm_batch *b, int32_t i, void *dst, int dst_on_device);
 /* Enqueue n >= 0 forward-Euler steps of Eq. 2 (Sec. 2.1) of every grid of
- * the batch, each with its own coefficients: one launch per step covering all
- * grids, issued as replays of captured HIP graphs of 16 launches for long
- * runs.  The same sweeps of Sec. 3.1-3.2 (driving forces, orientations) that
- * the paper runs one grid at a time. */
+ * the batch, each with its own coefficients.  Tiled kernel: one launch per
+ * step covering all grids; resident kernel in x segments: one launch per halo's
+ * worth of steps; both issued as replays of captured HIP graphs of 16 launches
+ * for long runs (on a non-null stream).  Resident kernel on whole grids: up to
+ * 4096 steps per launch.  The same sweeps of Sec. 3.1-3.2 (driving forces,
+ * orientations) that the paper runs one grid at a time.  With kernel AUTO the
+ * first call times the candidates (see spfm_kernel) and synchronises the
+ * stream once. */
 spfm_status spfm_batch_step(spfm_batch *b, int64_t n);
 /* spfm_diagnostics for every grid of the batch (out: n entries; the FP64
  * compensated sums and interface measures of each grid's interior). */
