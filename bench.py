@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
                     help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | models | "
-                         "cube | friction")
+                         "cube | friction | grainruns")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -84,6 +84,17 @@ def copy_reference(torch):
     return {"elements": n, "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
+def volume_radius(v, lam):
+    """The radius R whose ideal-profile sphere holds phase volume v:
+    (4 pi / 3)(R^3 + R pi^2 lambda^2 / 16) = v, by Newton's method."""
+    import math
+    k = math.pi ** 2 * lam ** 2 / 16.0
+    r = (3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0)
+    for _ in range(50):
+        r -= (r ** 3 + k * r - 3.0 * v / (4.0 * math.pi)) / (3.0 * r * r + k)
+    return r
+
+
 def grain_shape(d, lam):
     """Size and isotropy of the shrinking grain after the timed steps: the
     volume-equivalent radius R_V of the ideal profile's phase volume (the
@@ -91,13 +102,8 @@ def grain_shape(d, lam):
     the phi = 1/2 contour statistics of Sec. 3.3 (mean, extreme radii and
     eps_eff = (R_max - R_min) / (2 R_mean)), and, when given, the same from the
     radii along the configuration's seeded rays."""
-    import math
     c = d["contour"]
-    v = d["phase_volume"]
-    k = math.pi ** 2 * lam ** 2 / 16.0
-    r = (3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0)
-    for _ in range(50):   # Newton on R^3 + k R = 3 V / (4 pi)
-        r -= (r ** 3 + k * r - 3.0 * v / (4.0 * math.pi)) / (3.0 * r * r + k)
+    r = volume_radius(d["phase_volume"], lam)
     out = {"time": d["time"], "R_V": r, "R_mean": c["R_mean"], "R_min": c["R_min"],
            "R_max": c["R_max"], "eps_eff": c["eps_eff"], "contour_points": c["points"]}
     if "rays" in d:   # the same shape along the configuration's seeded rays
@@ -661,6 +667,57 @@ def cube_leg(spfm, torch, steps=3000):
             "steps": steps, "us_per_step": total_ms * 1e3 / (3 * steps), "runs": out}
 
 
+def sphere_law(r0, mu, t, M, Gamma, sigma, n=2000):
+    """R(t) of a sphere under the sharp-interface law dR/dt = -(M / Gamma)
+    (mu + 2 sigma / R) (Sec. 3.3: planar velocity -M mu / Gamma along the outward
+    normal of the phi = 1 grain, curvature 2 / R), by RK4 in n steps."""
+    f = lambda r: -(M / Gamma) * (mu + 2.0 * sigma / r)
+    r, h = r0, t / n
+    for _ in range(n):
+        k1 = f(r)
+        k2 = f(r + 0.5 * h * k1)
+        k3 = f(r + 0.5 * h * k2)
+        k4 = f(r + h * k3)
+        r += h * (k1 + 2 * k2 + 2 * k3 + k4) / 6.0
+    return r
+
+
+def grain_runs_leg(spfm, torch, inputs, steps=5000, every=500, mus=(0.0, 0.02)):
+    """The 256^3 grain (R0 = 60, lambda = 4, FP32, TI_n, 26 neighbours) run for
+    its full 5000 steps at mu = 0 and mu = 0.02: the volume-equivalent radius
+    R_V(t) every `every` steps against the sharp-interface law (at mu = 0, R^2
+    falls at 4 M sigma / Gamma with sigma = 2 Gamma / (3 C_Gamma)), and the shape
+    at the end (contour eps_eff, radii along the 1000 seeded rays)."""
+    w0 = inputs.sphere256(mu=0.0)
+    out = {}
+    for mu in mus:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm(w0.shape, lam=w0.lam, mu=mu, Gamma=w0.Gamma, M=w0.M, dx=w0.dx,
+                          stencil=w0.stencil, dtype="f32", coupling="local", dt=w0.dt, stream=stream)
+            s.init_spheres(w0.centers, w0.radii)
+            inf = s.info()
+            sigma = 2.0 * inf["Gamma"] / (3.0 * inf["C_Gamma"])
+            pts, worst = [], 0.0
+            for i in range(steps // every + 1):
+                if i:
+                    s.step(every)
+                d = s.diagnostics()
+                r = volume_radius(d["phase_volume"], w0.lam)
+                law = sphere_law(w0.radii[0], mu, d["time"], inf["M"], inf["Gamma"], sigma)
+                pts.append([d["time"], r, law])
+                worst = max(worst, abs(r - law) / max(abs(w0.radii[0] - law), 1e-9)) if i else worst
+            d = s.diagnostics()
+            d["contour"] = s.contour_stats()
+            d["rays"] = s.ray_radii(w0.rays, centre=d["contour"]["centre"])
+            shape = grain_shape(d, w0.lam)
+            s.close()
+        out[f"mu{mu:g}"] = {"steps": steps, "R_V_vs_law": pts,
+                            "max_rel_dev_of_change": worst, "lam_over_R_end": w0.lam / pts[-1][1],
+                            "eps_eff": shape["eps_eff"], "ray_eps": shape.get("ray_eps")}
+    return out
+
+
 def friction_leg(spfm):
     """The grid friction force study of the paper's Fig. 3: oscillation
     amplitude of the total force on an ideal front moved through the grid (12
@@ -831,6 +888,9 @@ def main():
     if args.only in ("", "friction"):
         print("leg: friction", file=sys.stderr, flush=True)
         out["fig3_friction"] = friction_leg(spfm)
+    if args.only in ("", "grainruns"):
+        print("leg: grain runs", file=sys.stderr, flush=True)
+        out["grain256_runs"] = grain_runs_leg(spfm, torch, inputs)
     if not args.no_cpu and f32 is not None:
         print("leg: cpu oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
