@@ -187,15 +187,6 @@ spfm_status resolve(const spfm_grid* g, double lambda, double Gamma, double M, d
 
 size_t elem_size(int dtype) { return dtype == SPFM_F64 ? 8 : 4; }
 
-bool is_device_ptr(const void* p) {
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return a.type == hipMemoryTypeDevice;
-}
-
 // Reduction scratch: per-block partials and the pinned host copy of the result.
 struct Reducer {
     double* d_partials = nullptr;

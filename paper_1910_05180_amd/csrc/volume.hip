@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void k_energy_partial(const T* __restrict__ ph
     se[threadIdx.x] = e;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
+        if ((int)threadIdx.x < h) {
             double a = ss[threadIdx.x], ea = se[threadIdx.x];
             comp_add(a, ea, ss[threadIdx.x + h]);
             ss[threadIdx.x] = a;
