@@ -200,6 +200,34 @@ def test_walled_orientation_segments_equal_tiled(S, segment):
         assert a["interface_position"] == b["interface_position"] and a["step"] == 400
 
 
+@pytest.mark.parametrize("walls", [1, 6])
+def test_partly_walled_segments_equal_tiled(S, walls):
+    """Walls on x only (the segments' x regions stop at the ghost layers) and on
+    y and z only (the x regions wrap around a periodic axis while the y and z
+    ghosts are refreshed inside every segment): 3 and 40 steps equal the tiled
+    kernel bit for bit."""
+    rng = np.random.default_rng(100 + walls)
+    shapes = [(9, 7, 70), (6, 11, 45), (5, 5, 33)]
+    ns, sins = [], []
+    for _ in shapes:
+        n = rng.normal(size=3)
+        n[[d for d in range(3) if not (walls >> d) & 1]] = 0.0
+        if walls & 1:
+            n[0] = abs(n[0]) + 0.5
+        n = n / np.linalg.norm(n)
+        ns.append(n)
+        sins.append(oracle.front_sin_alpha(n))
+    kw = dict(lam=3.0, mu=0.03, stencil=26, coupling="local", dt=0.05, walls=walls, wall_sin=sins)
+    init = lambda b: b.init_front(ns, [0.3, -0.2, 0.5])   # near the boxes' centres
+    print(f"case resident segments walls={walls}", flush=True)
+    r, info, _ = segment_batch(S, shapes, (6, 3), [3, 40], init, **kw)
+    assert (info["segment"], info["halo"]) == (6, 3)
+    t, _ = batch_fields(S, shapes, "tiled", [3, 40], init, **kw)
+    assert_bitwise(r, t)
+    for f in r[-1]:   # the fronts lie inside the boxes: neither phase fills them
+        assert f.min() < 0.1 and f.max() > 0.9
+
+
 @pytest.mark.parametrize("coupling,interp", [("local", "h3"), ("global", "h3"), ("cf", "h5")])
 @pytest.mark.parametrize("segment", [(8, 4), (16, 16), (5, 2)])
 def test_periodic_segments_equal_tiled(S, coupling, interp, segment):
