@@ -557,8 +557,9 @@ struct spfm_batch {
         return launch_step_resident<float>(buf[from], buf[to], d_coef, d_offset, walls ? d_wall : nullptr,
                                            nullptr, n, max_cells, nsteps, stencil, coupling, stream);
     }
-    int resident_chunk() const { return seg_len > 0 ? seg_halo : kResidentChunk; }
-    bool resident_in_place() const { return seg_len == 0; }
+    // Whole grids (run_resident); segments run through run_steps (launch_unit).
+    int resident_chunk() const { return kResidentChunk; }
+    bool resident_in_place() const { return true; }
 
     // Steps per unit launch: one, or a halo's worth for resident segments, whose
     // launches then run like tiled ones (graph replays, out of place).
@@ -913,10 +914,9 @@ spfm_status run_steps(Obj* o, int64_t n) {
     return SPFM_OK;
 }
 
-// Resident kernel: n steps in launches of at most resident_chunk() steps each
-// (kResidentChunk for whole grids, the halo for segments); a whole-grid launch
-// of an odd count writes the other buffer, of an even count the same one, and a
-// segmented launch always the other one.
+// Resident kernel on whole grids: n steps in launches of at most
+// resident_chunk() steps each; a launch of an odd count writes the other
+// buffer, of an even count (in place) the same one.
 constexpr int64_t kResidentAutoCells = 4096;   // largest stored grid AUTO steps resident untuned
 template <typename Obj>
 spfm_status run_resident(Obj* o, int64_t n) {
