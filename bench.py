@@ -53,8 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | models | "
-                         "cube | friction | grainruns")
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | fig8 | "
+                         "models | cube | friction | grainruns")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
     ap.add_argument("--coupling", default="local", choices=("local", "global", "cf"),
@@ -587,6 +587,92 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
             "rel_velocity_error": errs}
 
 
+def front_x(field):
+    """Mean x (in grid points of the interior) of the phi = 1/2 crossings of a
+    planar front with phase 1 at low x, over the x lines of field (nz, ny, nx):
+    on each line, the zero of psi = ln((1 - phi)/phi) interpolated linearly
+    between the two points that bracket phi = 1/2.  psi is linear across the
+    ideal profile of Eq. 3 (the contour reading of Eq. 8-9 at l = 1/2), so the
+    crossing is exact for it at any lambda/dx.  The phase volume is not: for
+    sharp profiles its change per cell of travel oscillates with the front's
+    offset from the grid (about 9% of the velocity at lambda = dx), so a
+    velocity taken from it over a fraction of a cell errs."""
+    import numpy as np
+    f = np.asarray(field, dtype=np.float64).reshape(-1, np.shape(field)[-1])
+    past = f < 0.5
+    i = np.argmax(past, axis=1)
+    rows = np.arange(f.shape[0])
+    ok = (i > 0) & past[rows, i]
+    a = np.clip(f[rows, i - 1], 1e-300, 1.0 - 1e-16)
+    b = np.clip(f[rows, i], 1e-300, 1.0 - 1e-16)
+    pa, pb = np.log((1.0 - a) / a), np.log((1.0 - b) / b)
+    x = (i - 1) + pa / (pa - pb)
+    return float(x[ok].mean()) if ok.any() else float("nan")
+
+
+def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5)), mu0=0.1):
+    """The orientation study of the paper's Fig. 8 (Sec. 3.2): the seven planar
+    fronts of the walls leg (rotations about [001] and [011], walls of Eq. 7 on
+    all faces, 120 x 10 x 10, 26 neighbours, mu = mu0 cos(theta), FP32) at
+    lambda/dx = 4, 1 and 0.5 for TI_n, three TI_<hkl> models (<100>, <110>,
+    <111>) and CF, one walled batch per model and resolution.  dt is half the
+    explicit stability bound (at most 0.05; at lambda = 0.5 TI_n needs about the
+    paper's 1e-5).  plan holds (lambda/dx, warm-up, window): an unpinned front
+    travels `warm-up` cells along x untimed, then `window` cells (the paper runs
+    at least five; 2.5 at lambda = 0.5, where the steps are many).  The
+    velocity is the change of front_x over the window; the relative error is
+    against -M mu0 / Gamma, the x-velocity every orientation shares."""
+    import math
+    shape = (10, 10, 120)
+    runs = [("001", d) for d in (0, 15, 30, 45)] + [("011", d) for d in (15, 30, 45)]
+    ns = []
+    for axis, deg in runs:
+        th = math.radians(deg)
+        ns.append((math.cos(th), math.sin(th), 0.0) if axis == "001" else
+                  (math.cos(th), math.sin(th) / math.sqrt(2.0), math.sin(th) / math.sqrt(2.0)))
+    models = [("TI_n", "local", (1.0, 0.0, 0.0)), ("TI_100", "global", (1.0, 0.0, 0.0)),
+              ("TI_110", "global", (1.0, 1.0, 0.0)), ("TI_111", "global", (1.0, 1.0, 1.0)),
+              ("CF", "cf", (1.0, 0.0, 0.0))]
+    out, steps_total, ms_total = {}, 0, 0.0
+    for lam, warm_cells, window in plan:
+        for name, coupling, u in models:
+            bound = min(spfm.stable_dt(26, coupling, u, None, lam, 1.0, 1.0, mu0 * n[0], 1.0) for n in ns)
+            dt = min(0.05, 0.5 * bound)
+            steps = int(math.ceil(window / mu0 / dt))
+            warm = int(math.ceil(warm_cells / mu0 / dt))
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                b = spfm.SpfmBatch([shape] * len(ns), lam=lam, mu=[mu0 * n[0] for n in ns], stencil=26,
+                                   coupling=coupling, u=u, dt=dt, walls=7,
+                                   wall_sin=[spfm.front_wall_sin(n) for n in ns], stream=stream)
+                b.init_front(ns, [20.0] * len(ns))
+                b.step(warm)
+                x0 = [front_x(b.get_field(i)) for i in range(len(ns))]
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                b.step(steps)
+                e1.record(stream)
+                stream.synchronize()
+                x1 = [front_x(b.get_field(i)) for i in range(len(ns))]
+                info = b.info()
+                b.close()
+            ms_total += e0.elapsed_time(e1)
+            steps_total += steps
+            errs = {f"{axis}:{deg}": (c - a) / (steps * dt) / (-mu0) - 1.0
+                    for (axis, deg), a, c in zip(runs, x0, x1)}
+            vals = list(errs.values())
+            out[f"lam{lam:g}_{name}"] = {
+                "dt": dt, "steps": steps, "kernel": kernel_choice(spfm, info),
+                "rel_velocity_error": errs,
+                "mean_rel_error": sum(vals) / len(vals),
+                "kinetic_anisotropy": max(vals) - min(vals),
+                "pinned": [k for k, v in errs.items() if v < -0.99]}
+    out["steps"] = steps_total
+    out["gpu_s"] = ms_total * 1e-3
+    return out
+
+
 def kernel_choice(spfm, info):
     """What a batch runs, from its info: "tiled 16x8 z4", "resident whole" or
     "resident segments 8 halo 4"."""
@@ -879,6 +965,9 @@ def main():
         out["orientation120_walls"] = walls_leg(spfm, torch)
         # the continuum-field control at the paper's mu0: friction makes it orientation dependent
         out["orientation120_walls_cf"] = walls_leg(spfm, torch, coupling="cf", mu0=0.1)
+    if args.only in ("", "fig8"):
+        print("leg: fig8", file=sys.stderr, flush=True)
+        out["fig8_orientation"] = fig8_leg(spfm, torch)
     if args.only in ("", "models"):
         print("leg: models", file=sys.stderr, flush=True)
         out["fig7_models"] = models_leg(spfm, torch)

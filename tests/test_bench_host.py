@@ -93,3 +93,32 @@ def test_traffic_from_counter_rows(tmp_path):
 def test_median():
     assert bench.median([3.0, 1.0, 2.0]) == 2.0
     assert bench.median([4.0, 1.0, 2.0, 3.0]) == 2.5
+
+
+@pytest.mark.parametrize("lam", [4.0, 1.0, 0.5])
+@pytest.mark.parametrize("n", [(1.0, 0.0, 0.0), (0.9, 0.3, 0.1), (0.7, 0.5, 0.5)])
+def test_front_x_is_exact_for_ideal_fronts(lam, n):
+    """front_x locates a planar front by the zeros of psi = ln((1 - phi)/phi)
+    along x; psi is linear across the ideal profile of Eq. 3, so moving the
+    front by d along n moves front_x by d / n_x exactly, at any lambda/dx."""
+    import numpy as np
+    import oracle
+    n = np.asarray(n) / np.linalg.norm(n)
+    offs = [0.0, 0.13, 0.5, 0.77, 1.6]
+    xs = [bench.front_x(oracle.front((10, 10, 120), n, o, lam=lam)) for o in offs]
+    assert np.allclose(np.diff(xs), np.diff(offs) / n[0], rtol=0, atol=1e-9)
+
+
+def test_phase_volume_is_not_an_exact_front_position_for_sharp_profiles():
+    """Why front_x: at lambda = dx the phase volume of the ideal profile is
+    not linear in the front's offset (its slope varies by about 9% within a
+    cell), while front_x is."""
+    import numpy as np
+    import oracle
+    n = (1.0, 0.0, 0.0)
+    offs = np.linspace(0.0, 1.0, 9)
+    vol = np.array([oracle.front((2, 2, 60), n, o, lam=1.0).sum() / 4.0 for o in offs])
+    slope = np.diff(vol) / np.diff(offs)
+    assert np.ptp(slope) > 0.1
+    xs = np.array([bench.front_x(oracle.front((2, 2, 60), n, o, lam=1.0)) for o in offs])
+    assert np.allclose(np.diff(xs) / np.diff(offs), 1.0, atol=1e-9)

@@ -294,3 +294,87 @@ def test_walled_batch_results_do_not_depend_on_the_zchunk(S, coupling):
     for zc in (32, 7):
         for i in range(len(shapes)):
             assert np.array_equal(out[zc][i], out[0][i]), (zc, i)
+
+
+# --- Fig. 8 at the paper's other two resolutions --------------------------------
+
+def fig8_errors(S, lam, coupling, u=(1.0, 0.0, 0.0), warm_cells=0.5, window_cells=1.0, mu0=0.1):
+    """Relative x-velocity errors of the seven orientations of Fig. 8 as one
+    walled FP32 batch (120 x 10 x 10, 26 neighbours, mu = mu0 cos(theta), dt
+    half the explicit bound), the front located by its psi = 0 crossings
+    (bench.front_x, exact for the ideal profile at any lambda/dx)."""
+    import bench
+    bound = min(S.stable_dt(26, coupling, u, None, lam, 1.0, 1.0, mu0 * n[0], 1.0) for n in ORIENTATIONS)
+    dt = min(0.05, 0.5 * bound)
+    warm = int(math.ceil(warm_cells / mu0 / dt))
+    steps = int(math.ceil(window_cells / mu0 / dt))
+    print(f"case fig8 lam={lam} {coupling} u={u} dt={dt:.3g} steps={warm}+{steps}", flush=True)
+    with S.SpfmBatch([(10, 10, 120)] * len(ORIENTATIONS), lam=lam, mu=[mu0 * n[0] for n in ORIENTATIONS],
+                     stencil=26, coupling=coupling, u=u, dt=dt, walls=7,
+                     wall_sin=[S.front_wall_sin(n) for n in ORIENTATIONS]) as b:
+        b.init_front(ORIENTATIONS, [20.0] * len(ORIENTATIONS))
+        b.step(warm)
+        x0 = [bench.front_x(b.get_field(i)) for i in range(len(ORIENTATIONS))]
+        b.step(steps)
+        x1 = [bench.front_x(b.get_field(i)) for i in range(len(ORIENTATIONS))]
+    errs = [(c - a) / (steps * dt) / (-mu0) - 1.0 for a, c in zip(x0, x1)]
+    print(" ".join(f"{e:+.2e}" for e in errs), flush=True)
+    return errs
+
+
+def test_fig8_ti_n_is_frictionless_at_lambda_1(S):
+    """Sec. 3.2: TI_n moves every orientation at -M mu0 / Gamma also at
+    lambda = dx; what remains is the forward-Euler error (about 7e-5 at half
+    the stability bound, the same in FP64)."""
+    errs = fig8_errors(S, 1.0, "local")
+    assert max(abs(e) for e in errs) < 2e-4
+
+
+def test_fig8_continuum_field_pins_at_lambda_1(S):
+    """Sec. 3.2: below lambda = 4 the CF model is pinned by the grid at every
+    orientation (mu0 dx / Gamma = 0.1)."""
+    errs = fig8_errors(S, 1.0, "cf")
+    assert max(errs) < -0.999
+
+
+def test_fig8_ti_hkl_is_exact_only_along_its_directions(S):
+    """Sec. 3.2: a TI_<hkl> model moves fronts normal to its <hkl> directions
+    at the expected velocity; misoriented ones not, and TI_<110> is pinned
+    near [100] at lambda = dx.  (For TI_<100> the misoriented fronts here run
+    5-21% fast over five cells, where the paper's text says slow.)"""
+    e100 = fig8_errors(S, 1.0, "global", u=(1.0, 0.0, 0.0))
+    assert abs(e100[0]) < 2e-4                      # [100]
+    assert min(abs(e) for e in e100[1:]) > 0.02     # every other orientation
+    e110 = fig8_errors(S, 1.0, "global", u=(1.0, 1.0, 0.0))
+    assert abs(e110[3]) < 2e-4                      # 45 degrees about [001]: [110]
+    assert e110[0] < -0.99                          # pinned along [100]
+
+
+@pytest.mark.parametrize("deg", [0, 15])
+def test_fig8_ti_n_at_lambda_half(S, deg):
+    """Sec. 3.2: TI_n stays frictionless at lambda = dx / 2, the error that of
+    the time step (dt = 1e-5, the paper's), in FP64.  FP32 storage resolves
+    1 - phi only to 6e-8, and two cells behind this front the ideal profile's
+    1 - phi is 1.1e-7: psi' and hence the local normal lose their accuracy
+    there, and the FP32 front errs by up to about 2% (a bound of 5% guards that
+    documented limit)."""
+    import bench
+    th = math.radians(deg)
+    n = rot001(th)
+    lam, mu0 = 0.5, 0.1
+    dt = 0.5 * S.stable_dt(26, "local", n, None, lam, 1.0, 1.0, mu0 * n[0], 1.0)
+    warm, steps = int(math.ceil(0.05 / mu0 / dt)), int(math.ceil(0.25 / mu0 / dt))
+    errs = {}
+    for dtype in ("f64", "f32"):
+        print(f"case fig8 lam=0.5 TI_n {dtype} theta={deg} dt={dt:.3g} steps={warm}+{steps}", flush=True)
+        with S.Spfm((10, 10, 120), lam=lam, mu=mu0 * n[0], stencil=26, dtype=dtype, coupling="local", dt=dt,
+                    walls=7, wall_sin=S.front_wall_sin(n)) as s:
+            s.init_front(n, 20.0)
+            s.step(warm)
+            x0 = bench.front_x(s.get_field())
+            s.step(steps)
+            x1 = bench.front_x(s.get_field())
+        errs[dtype] = (x1 - x0) / (steps * dt) / (-mu0) - 1.0
+        print(f"{dtype} err {errs[dtype]:+.3e}", flush=True)
+    assert abs(errs["f64"]) < 1e-4
+    assert abs(errs["f32"]) < 5e-2
