@@ -723,34 +723,59 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
             "rel_velocity_error": out}
 
 
-def cube_leg(spfm, torch, steps=3000):
+def cube_leg(spfm, torch, steps=3000, sweep=((4.0, 2.0, 1.5, 1.2, 1.0), 300.0)):
     """The residual-anisotropy study of the paper's Fig. 9 on its 60^3 grid: a
     cube particle (edge 30 dx) relaxed at constant volume (mu chosen on the
-    device at every step), FP32, 26 neighbours; TI_n at lambda~ = 4 and 2 and
-    CF at lambda~ = 2.  Reports eps_eff of the phi = 1/2 contour and the step rate."""
+    device at every step), FP32, 26 neighbours.  Timed: TI_n at lambda~ = 4
+    and 2 and CF at lambda~ = 2 (dt = 0.1, `steps` steps); reports eps_eff of
+    the phi = 1/2 contour and the step rate.  Then Fig. 9b: eps_eff after
+    sweep[1] time units for TI_n, TI_<100> (aligned with the cube's faces),
+    TI_<110>, TI_<120> and CF at each lambda~ of sweep[0], dt half the
+    explicit bound (at most 0.1)."""
+    import math
     n, edge = 60, 30.0
     lo = (n - edge) / 2 + 0.25
     out, total_ms = {}, 0.0
-    for name, lam, coupling in (("TI_n_lam4", 4.0, "local"), ("TI_n_lam2", 2.0, "local"),
-                                ("CF_lam2", 2.0, "cf")):
+
+    def relax(lam, coupling, u, dt, nsteps, timed):
+        nonlocal total_ms
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            s = spfm.Spfm((n, n, n), lam=lam, mu=-0.1, stencil=26, coupling=coupling,
+            s = spfm.Spfm((n, n, n), lam=lam, mu=-0.1, stencil=26, coupling=coupling, u=u, dt=dt,
                           conserve_volume=True, stream=stream)
             s.init_box((lo, lo, lo), (lo + edge, lo + edge, lo + edge))
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            s.step(steps)
+            s.step(nsteps)
             e1.record(stream)
             c = s.contour_stats()
             d = s.diagnostics()
-            total_ms += e0.elapsed_time(e1)
+            if timed:
+                total_ms += e0.elapsed_time(e1)
             s.close()
-        out[name] = {"eps_eff": c["eps_eff"], "R_mean": c["R_mean"], "mu": d["mu"]}
+        return {"eps_eff": c["eps_eff"], "R_mean": c["R_mean"], "mu": d["mu"]}
+
+    for name, lam, coupling in (("TI_n_lam4", 4.0, "local"), ("TI_n_lam2", 2.0, "local"),
+                                ("CF_lam2", 2.0, "cf")):
+        out[name] = relax(lam, coupling, (1.0, 0.0, 0.0), 0.1, steps, True)
     pts = n ** 3
-    return {"value": pts * steps * 3 / (total_ms * 1e-3) / 1e9, "unit": "GLUPS", "grid": "60^3",
-            "steps": steps, "us_per_step": total_ms * 1e3 / (3 * steps), "runs": out}
+    res = {"value": pts * steps * 3 / (total_ms * 1e-3) / 1e9, "unit": "GLUPS", "grid": "60^3",
+           "steps": steps, "us_per_step": total_ms * 1e3 / (3 * steps), "runs": out}
+    if sweep:
+        lams, T = sweep
+        models = [("TI_n", "local", (1.0, 0.0, 0.0)), ("TI_100", "global", (1.0, 0.0, 0.0)),
+                  ("TI_110", "global", (1.0, 1.0, 0.0)), ("TI_120", "global", (1.0, 2.0, 0.0)),
+                  ("CF", "cf", (1.0, 0.0, 0.0))]
+        table = {}
+        for lam in lams:
+            for name, coupling, u in models:
+                dt = min(0.1, 0.5 * spfm.stable_dt(26, coupling, u, None, lam, 1.0, 1.0, 0.2, 1.0))
+                r = relax(lam, coupling, u, dt, int(math.ceil(T / dt)), False)
+                table[f"lam{lam:g}_{name}"] = {"eps_eff": r["eps_eff"], "dt": dt}
+        res["fig9b_eps_eff"] = table
+        res["fig9b_time"] = T
+    return res
 
 
 def sphere_law(r0, mu, t, M, Gamma, sigma, n=2000):
