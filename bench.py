@@ -688,7 +688,10 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
     (3 x 3 x 256 periodic, two interfaces 128 dx apart, 6 neighbours, dt = 0.05,
     FP32): for each model one batch steps the slabs of every lambda~ in
     {4, 3, 2.5} and mu~ in {0.005, 0.01, 0.02, 0.05} (kernel AUTO, as above).  Reports the
-    relative error of the mean interface velocity against -M mu / Gamma."""
+    relative error of the mean interface velocity against -M mu / Gamma; then
+    TI_n, TI_<100> and CF with h3 at lambda~ = 1 and 0.5 (dt at most half the
+    stability bound)."""
+    import math
     models = [("CF+h3", "cf", "h3"), ("CF+h5", "cf", "h5"), ("CF+h_Abel", "cf", "habel"),
               ("TI_100+h3", "global", "h3"), ("TI_n+h3", "local", "h3")]
     cases = [(lam, mu) for lam in (4.0, 3.0, 2.5) for mu in (0.005, 0.01, 0.02, 0.05)]
@@ -716,11 +719,38 @@ def models_leg(spfm, torch, warm=2000, steps=4000):
             v = (e["interface_position"] - a["interface_position"]) / (e["time"] - a["time"])
             errs[f"lam{lam:g}_mu{mu:g}"] = v / -mu - 1.0
         out[name] = errs
+    # Fig. 7's sharp end: lambda~ = 1 and 0.5, where dt must shrink with the
+    # stability bound; the timed window stays 200 time units, a whole number of
+    # cells of travel for every mu~ here (1 to 10), over which the phase
+    # volume's within-cell oscillation of sharp profiles cancels.
+    sharp = {}
+    for lam in (1.0, 0.5):
+        mus = (0.005, 0.01, 0.02, 0.05)
+        for name, coupling, interp in (("TI_n+h3", "local", "h3"), ("TI_100+h3", "global", "h3"),
+                                       ("CF+h3", "cf", "h3")):
+            bound = min(spfm.stable_dt(6, coupling, (1.0, 0.0, 0.0), None, lam, 1.0, 1.0, mu, 1.0)
+                        for mu in mus)
+            nt = int(math.ceil(200.0 / min(0.05, 0.5 * bound)))
+            dt = 200.0 / nt
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                b = spfm.SpfmBatch([shape] * len(mus), lam=lam, mu=list(mus), stencil=6, coupling=coupling,
+                                   interp=interp, dt=dt, stream=stream)
+                b.init_planar([(1, 0, 0)] * len(mus), [0.37] * len(mus))
+                b.step(nt // 2)
+                d0 = b.diagnostics()
+                b.step(nt)
+                d1 = b.diagnostics()
+                b.close()
+            for mu, a, e in zip(mus, d0, d1):
+                v = (e["interface_position"] - a["interface_position"]) / (e["time"] - a["time"])
+                sharp.setdefault(name, {})[f"lam{lam:g}_mu{mu:g}"] = v / -mu - 1.0
+            sharp.setdefault("dt", {})[f"lam{lam:g}_{name}"] = dt
     pts = shape[0] * shape[1] * shape[2] * len(cases)
     return {"value": pts * steps * len(models) / (total_ms * 1e-3) / 1e9, "unit": "GLUPS",
             "grids_per_launch": len(cases), "steps": steps,
             "us_per_step": total_ms * 1e3 / (steps * len(models)), "kernel": kernels,
-            "rel_velocity_error": out}
+            "rel_velocity_error": out, "sharp_rel_velocity_error": sharp}
 
 
 def cube_leg(spfm, torch, steps=3000, sweep=((4.0, 2.0, 1.5, 1.2, 1.0), 300.0)):
