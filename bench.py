@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--only", default="",
-                    help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | fig8 | "
+                    help="run only this leg: f32 | f64 | batch | grains | temporal | musweep | walls | fig1 | fig8 | "
                          "models | cube | friction | grainruns")
     ap.add_argument("--side-steps", type=int, default=200,
                     help="timed steps of the batched and 512^3 legs")
@@ -588,26 +588,69 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
 
 
 def front_x(field):
-    """Mean x (in grid points of the interior) of the phi = 1/2 crossings of a
-    planar front with phase 1 at low x, over the x lines of field (nz, ny, nx):
-    on each line, the zero of psi = ln((1 - phi)/phi) interpolated linearly
-    between the two points that bracket phi = 1/2.  psi is linear across the
-    ideal profile of Eq. 3 (the contour reading of Eq. 8-9 at l = 1/2), so the
-    crossing is exact for it at any lambda/dx.  The phase volume is not: for
-    sharp profiles its change per cell of travel oscillates with the front's
-    offset from the grid (about 9% of the velocity at lambda = dx), so a
-    velocity taken from it over a fraction of a cell errs."""
+    """Mean x (in grid points) of the falling phi = 1/2 crossings of a planar
+    front, over the x lines of field (nz, ny, nx): on each line, the one place
+    where phi drops from >= 1/2 at x to < 1/2 at x + 1 (the line read
+    periodically, so a periodic slab's trailing front counts and a walled
+    front with phase 1 at low x is found as such), located at the zero of
+    psi = ln((1 - phi)/phi) interpolated linearly between those two points.
+    psi is linear across the ideal profile of Eq. 3 (the contour reading of
+    Eq. 8-9 at l = 1/2), so the crossing is exact for it at any lambda/dx.  The
+    phase volume is not: for sharp profiles its change per cell of travel
+    oscillates with the front's offset from the grid (about 9% of the velocity
+    at lambda = dx), so a velocity taken from it over a fraction of a cell
+    errs."""
     import numpy as np
     f = np.asarray(field, dtype=np.float64).reshape(-1, np.shape(field)[-1])
-    past = f < 0.5
-    i = np.argmax(past, axis=1)
+    g = np.roll(f, -1, axis=1)
+    fall = (f >= 0.5) & (g < 0.5)
+    ok = fall.any(axis=1)
+    i = np.argmax(fall, axis=1)
     rows = np.arange(f.shape[0])
-    ok = (i > 0) & past[rows, i]
-    a = np.clip(f[rows, i - 1], 1e-300, 1.0 - 1e-16)
-    b = np.clip(f[rows, i], 1e-300, 1.0 - 1e-16)
+    a = np.clip(f[rows, i], 1e-300, 1.0 - 1e-16)
+    b = np.clip(g[rows, i], 1e-300, 1.0 - 1e-16)
     pa, pb = np.log((1.0 - a) / a), np.log((1.0 - b) / b)
-    x = (i - 1) + pa / (pa - pb)
+    x = i + pa / (pa - pb)
     return float(x[ok].mean()) if ok.any() else float("nan")
+
+
+def fig1_leg(spfm, torch, mu=0.1, warm_cells=2.0, cells=3.0, per_cell=10):
+    """The paper's Fig. 1: a [100] slab driven at mu~ = 0.1 in a periodic box of
+    120 points along x (3 x 3 cross-section, 6 neighbours, FP32): CF + h3
+    at lambda~ = 4, 3, 2.5 and 2 against TI_n + h3 at lambda~ = 0.5, dt half the
+    stability bound (at most 0.05).  After warm_cells of travel at -M mu /
+    Gamma the trailing front is sampled per_cell times per cell of that travel
+    for `cells` cells: its position front_x and the interface energy F_int of
+    Eq. 1 (both fronts).  Reports the mean relative velocity error, the amplitude (half the
+    range) of the velocity between samples relative to M mu / Gamma, and that
+    of F_int relative to its mean."""
+    import math
+    import numpy as np
+    shape, n = (3, 3, 120), (1.0, 0.0, 0.0)
+    out = {}
+    for name, coupling, lam in (("CF_lam4", "cf", 4.0), ("CF_lam3", "cf", 3.0), ("CF_lam2.5", "cf", 2.5),
+                                ("CF_lam2", "cf", 2.0), ("TI_n_lam0.5", "local", 0.5)):
+        bound = spfm.stable_dt(6, coupling, n, None, lam, 1.0, 1.0, mu, 1.0)
+        per = int(math.ceil((1.0 / per_cell) / mu / min(0.05, 0.5 * bound)))
+        dt = (1.0 / per_cell) / mu / per           # per steps = 1/per_cell cell of travel
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm(shape, lam=lam, mu=mu, stencil=6, coupling=coupling, dt=dt, stream=stream)
+            s.init_planar((1, 0, 0), 0.37)
+            s.step(int(round(warm_cells * per_cell)) * per)
+            xs, fs = [], []
+            for _ in range(int(round(cells * per_cell)) + 1):
+                xs.append(front_x(s.get_field()))
+                fs.append(s.energy())
+                s.step(per)
+            s.close()
+        xs, fs = np.array(xs), np.array(fs)
+        v = np.diff(xs) / (per * dt) / -mu
+        out[name] = {"lam": lam, "dt": dt,
+                     "mean_rel_velocity_error": float((xs[-1] - xs[0]) / (per * dt * (len(xs) - 1)) / -mu - 1.0),
+                     "velocity_oscillation": float(0.5 * np.ptp(v)),
+                     "energy_oscillation": float(0.5 * np.ptp(fs) / abs(fs.mean()))}
+    return out
 
 
 def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5)), mu0=0.1):
@@ -1020,6 +1063,9 @@ def main():
         out["orientation120_walls"] = walls_leg(spfm, torch)
         # the continuum-field control at the paper's mu0: friction makes it orientation dependent
         out["orientation120_walls_cf"] = walls_leg(spfm, torch, coupling="cf", mu0=0.1)
+    if args.only in ("", "fig1"):
+        print("leg: fig1", file=sys.stderr, flush=True)
+        out["fig1_pinning"] = fig1_leg(spfm, torch)
     if args.only in ("", "fig8"):
         print("leg: fig8", file=sys.stderr, flush=True)
         out["fig8_orientation"] = fig8_leg(spfm, torch)

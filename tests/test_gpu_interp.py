@@ -147,3 +147,28 @@ def test_fig7_ti_stays_frictionless_at_sharp_resolutions(S, lam, tol):
     cf_dt = 0.5 * S.stable_dt(6, "cf", (1.0, 0.0, 0.0), None, lam, 1.0, 1.0, mu, 1.0)
     v = slab_velocities(S, "cf", "h3", (lam,), mu, dt=cf_dt, warm=2000, steps=int(math.ceil(20.0 / cf_dt)))
     assert abs(v[0]) < 1e-3 * mu
+
+
+def test_fig1_cf_friction_grows_to_pinning_while_ti_moves(S):
+    """Fig. 1 (mu~ = 0.1, a [100] slab sampled ten times per cell of travel):
+    CF + h3 runs ever slower as the profile sharpens, its velocity and
+    interface energy oscillating ever more as the front passes grid points,
+    and is pinned at lambda~ = 2; TI_n + h3 at lambda~ = 0.5 moves at
+    -M mu / Gamma with an energy that does not oscillate (measured: CF errors
+    -2.7%, -5.2%, -12%, pinned; TI 6e-5, energy oscillation 7e-11)."""
+    import torch
+    import bench
+    print("case fig1 leg", flush=True)
+    r = bench.fig1_leg(S, torch)
+    for k, v in r.items():
+        print(k, {kk: f"{vv:.3e}" for kk, vv in v.items()}, flush=True)
+    e = [r[k]["mean_rel_velocity_error"] for k in ("CF_lam4", "CF_lam3", "CF_lam2.5", "CF_lam2")]
+    assert all(b < a < 0 for a, b in zip(e, e[1:]))
+    assert e[-1] < -0.99
+    for q in ("velocity_oscillation", "energy_oscillation"):
+        o = [r[k][q] for k in ("CF_lam4", "CF_lam3", "CF_lam2.5")]
+        assert o[0] < o[1] < o[2], q
+    ti = r["TI_n_lam0.5"]
+    assert abs(ti["mean_rel_velocity_error"]) < 1e-3
+    assert ti["velocity_oscillation"] < 1e-3
+    assert ti["energy_oscillation"] < 1e-8
