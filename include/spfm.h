@@ -109,9 +109,9 @@ typedef struct {
     int32_t allow_unstable; /* nonzero: skip the dt stability check */
     int32_t zchunk;     /* planes per block of the tiled kernel, 1..4096; 0 = chosen by the
                            library: a size rule (32 planes, 64 for fused steps, shorter, down
-                           to 2 (8 fused), for grids too small to fill the GPU); for AUTO on a
-                           grid that fills
-                           it, timed among 8..64 at the first step.
+                           to 2 (8 fused, 4 with conserve_volume), for grids too small to fill
+                           the GPU); for AUTO on a grid that fills it (not with
+                           conserve_volume), timed among 8..64 at the first step.
                            Single steps cut each tile column into blocks of at most zchunk
                            planes, except a tail (about 1.4 rounds of the work the GPU keeps
                            resident, at most 35% of the column) in blocks of halving length
@@ -140,7 +140,12 @@ typedef struct {
                            sums that fix it are exact (terms rounded to 2^-54, added as
                            integers), so the result does not depend on the kernel's schedule;
                            the tiled kernel forms them in the step itself (the untuned tile
-                           shape only) and applies the correction in one more launch */
+                           shape only).  With at most 1024 work items (zchunk) each step also
+                           applies the previous step's correction as it reads its input, and
+                           spfm_step(n) ends with one correction launch: n + 1 launches, with
+                           the library's buffers plus two more fields allocated at the first
+                           step; else a correction launch follows every step.  The plain
+                           kernel adds a pass for the sums */
     const double *batch_wall_sin; /* batches with walls: 6 values per grid, wall_sin of grid i at
                            6 i (read at spfm_batch_create only); NULL = wall_sin for every grid.
                            Ignored by single contexts */

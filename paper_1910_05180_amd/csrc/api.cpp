@@ -318,9 +318,10 @@ double front_area(const Params& p, const double n[3]) {
 }
 
 // Replays of kGraphSteps launches captured from a step function, one graph per
-// starting buffer; invalidated whenever the coefficients change.
+// starting buffer (exec[0..1]; the fused constant-volume steps of a context use
+// exec[2..3]); invalidated whenever the coefficients change.
 struct GraphCache {
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
     void clear() {
         for (auto& e : exec) {
             if (e) (void)hipGraphExecDestroy(e);
@@ -424,8 +425,11 @@ struct spfm_ctx {
     int nitems = 0;
     size_t items_cap = 0;
     // Constant volume with the tiled kernel: the step's exact sums, 4 words per
-    // work item, then 4 words for their total (items_cap + 1 entries).
+    // work item, in two sets (consecutive steps of the fused form), then 4
+    // words for their total (2 items_cap + 1 entries); and the second pair of
+    // field buffers of the fused form, allocated at its first use.
     unsigned long long* d_cvpart = nullptr;
+    void* xbuf[2] = {nullptr, nullptr};
     // One grid: tile rows are dealt to the XCDs round robin.
     static constexpr bool kSpreadRows = true;
 
@@ -458,12 +462,12 @@ struct spfm_ctx {
                     ? launch_step_plain<double>((const double*)in, (double*)out, cd, S, C, stream)
                     : launch_step_tiled<double>((const double*)in, (double*)out, cd, S, C, tile,
                                                 d_items, nitems, (const WallCoef<double>*)d_wall, cvp,
-                                                stream);
+                                                nullptr, stream);
         } else {
             e = r.kernel == SPFM_KERNEL_PLAIN
                     ? launch_step_plain<float>((const float*)in, (float*)out, cf, S, C, stream)
                     : launch_step_tiled<float>((const float*)in, (float*)out, cf, S, C, tile, d_items,
-                                               nitems, (const WallCoef<float>*)d_wall, cvp, stream);
+                                               nitems, (const WallCoef<float>*)d_wall, cvp, nullptr, stream);
         }
         if (e != hipSuccess || !r.conserve_volume) return e;
         // the step ran without the driving force; add the one that keeps sum phi
@@ -476,7 +480,7 @@ struct spfm_ctx {
                        : launch_cv_correct<float>((const float*)in, (float*)out, points(), r.p.interp,
                                                   dt_beta, part, d_state(), stream);
         }
-        unsigned long long* total = d_cvpart + 4 * items_cap;
+        unsigned long long* total = d_cvpart + 8 * items_cap;
         return f64 ? launch_cv_apply<double>((const double*)in, (double*)out, points(), r.p.interp, dt_beta,
                                              d_cvpart, nitems, total, d_state(), stream)
                    : launch_cv_apply<float>((const float*)in, (float*)out, points(), r.p.interp, dt_beta,
@@ -641,7 +645,7 @@ int tail_planes(int nz, int64_t total_points) {
 // small to fill the GPU get shorter chunks: more blocks, each with a shorter
 // dependent chain of plane loads.
 int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided,
-                 int64_t min_threads, int zmin) {
+                 int64_t min_threads, int zmin, int zfloor = 2) {
     int64_t total = 0;
     for (const GridDims& d : grids) total += (int64_t)d.nx * d.ny * d.nz;
     auto threads = [&](int zb) {
@@ -656,7 +660,7 @@ int default_zlen(const std::vector<GridDims>& grids, int tx, int ty, bool guided
     };
     int z = guided ? kTileZ : 2 * kTileZ;
     while (z > zmin && threads(z) < min_threads) z /= 2;
-    while (guided && z > 2 && threads(z) < min_threads / 4) z /= 2;
+    while (guided && z > zfloor && threads(z) < min_threads / 4) z /= 2;
     return z;
 }
 
@@ -745,7 +749,7 @@ spfm_status set_schedule(Obj* o, const std::vector<GridDims>& dims, int tile, in
             if (o->r.conserve_volume) {   // the step's constant-volume sums, then their total
                 if (o->d_cvpart) (void)hipFree(o->d_cvpart);
                 o->d_cvpart = nullptr;
-                if (hipMalloc(&o->d_cvpart, (items.size() + 1) * 4 * sizeof(unsigned long long)) !=
+                if (hipMalloc(&o->d_cvpart, (2 * items.size() + 1) * 4 * sizeof(unsigned long long)) !=
                     hipSuccess) {
                     (void)hipGetLastError();
                     o->d_cvpart = nullptr;
@@ -1132,7 +1136,11 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     }
     c->stream = opt ? (hipStream_t)opt->stream : nullptr;
     const bool autok = !opt || opt->kernel == SPFM_KERNEL_AUTO;
-    c->tune_z = autok && !(opt && opt->zchunk > 0);
+    // constant volume: no timing (it would time the separate correction
+    // launches, not the fused steps); the size rule keeps at least 4 planes per
+    // chunk, since every fused block adds the previous step's sums of all
+    // work items (60^3: 4 planes 10.5 us per step, 2 planes 11.2, 8 planes 12.3)
+    c->tune_z = autok && !(opt && opt->zchunk > 0) && !r.conserve_volume;
     // constant volume: the untuned tile shape (the step's sums are compiled for it alone)
     c->tune_tile = autok && r.tile < 0 && !r.conserve_volume;
     const bool f32 = r.dtype == SPFM_F32;
@@ -1142,7 +1150,8 @@ spfm_status spfm_create(const spfm_grid* grid, double lambda, double Gamma, doub
     c->zlen = (opt && opt->zchunk > 0)
                   ? opt->zchunk
                   : default_zlen({GridDims{r.sx, r.sy, r.sz}}, tx, ty, !temporal,
-                                 temporal ? (int64_t)1 << 20 : (int64_t)1 << 19, 8);
+                                 temporal ? (int64_t)1 << 20 : (int64_t)1 << 19, 8,
+                                 r.conserve_volume ? 4 : 2);
     const size_t bytes = c->stored_bytes();
     if (opt && opt->d_phi[0]) {
         c->buf[0] = opt->d_phi[0];
@@ -1212,6 +1221,8 @@ void spfm_destroy(spfm_ctx* c) {
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_cvpart) (void)hipFree(c->d_cvpart);
+    for (void* x : c->xbuf)
+        if (x) (void)hipFree(x);
     if (c->d_wall) (void)hipFree(c->d_wall);
     if (c->d_coef) (void)hipFree(c->d_coef);
     if (c->d_off) (void)hipFree(c->d_off);
@@ -1456,6 +1467,96 @@ spfm_status spfm_force(spfm_ctx* c, double* out) {
     return SPFM_OK;
 }
 
+// Constant volume with the tiled kernel, one launch per step: the first launch
+// steps buf[c0] into buf[1 - c0] and forms the sums; every later one applies
+// the previous step's correction as it reads its input (CvFuse) and writes
+// phi* and that corrected input into the other pair of the four buffers; one
+// correction pass ends the call, into the buffer a launch per step would have
+// left current.  The fields and mu equal those of the separate step and
+// correction launches bit for bit.  The middle launches replay captured
+// graphs of kGraphSteps launches (an even count: every graph starts at the
+// same pair), one per starting buffer.
+spfm_status run_cv_fused(spfm_ctx* c, int64_t n) {
+    if (n < 0) return fail(SPFM_E_INVAL, "negative step count");
+    if (n == 0) return SPFM_OK;
+    const bool f64 = c->r.dtype == SPFM_F64;
+    if (!c->xbuf[0]) {
+        const size_t bytes = (size_t)c->points() * (f64 ? sizeof(double) : sizeof(float));
+        for (void*& x : c->xbuf) {
+            if (hipMalloc(&x, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                for (void*& y : c->xbuf) {
+                    if (y) (void)hipFree(y);
+                    y = nullptr;
+                }
+                return fail(SPFM_E_NOMEM, "device allocation of the constant-volume buffers failed");
+            }
+        }
+    }
+    const int c0 = c->cur;
+    void* const star[2] = {c->buf[1 - c0], c->xbuf[0]};   // pair 0 (buf[1 - c0], buf[c0]), pair 1
+    void* const prev[2] = {c->buf[c0], c->xbuf[1]};
+    unsigned long long* const part[2] = {c->d_cvpart, c->d_cvpart + 4 * c->items_cap};
+    const int S = c->r.p.stencil, C = kernel_coupling(c->r.p.coupling, c->r.p.interp);
+    // launch kk: kk = 0 from buf[c0] into pair 0; kk >= 1 from pair (kk - 1) & 1 into pair kk & 1
+    auto launch = [&](int64_t kk) -> hipError_t {
+        const int i = (int)((kk + 1) & 1), o = (int)(kk & 1);
+        const void* in = kk == 0 ? c->buf[c0] : star[i];
+        if (f64) {
+            const CvFuse<double> fz{(const double*)prev[i], (double*)prev[o], part[i], c->nitems};
+            return launch_step_tiled<double>((const double*)in, (double*)star[o], c->kd0, S, C, c->tile,
+                                             c->d_items, c->nitems, nullptr, part[o], kk == 0 ? nullptr : &fz,
+                                             c->stream);
+        }
+        const CvFuse<float> fz{(const float*)prev[i], (float*)prev[o], part[i], c->nitems};
+        return launch_step_tiled<float>((const float*)in, (float*)star[o], c->kf0, S, C, c->tile, c->d_items,
+                                        c->nitems, nullptr, part[o], kk == 0 ? nullptr : &fz, c->stream);
+    };
+    hipError_t e = launch(0);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "step launch: %s", hipGetErrorString(e));
+    int64_t kk = 1;
+    GraphCache& gc = c->graphs;
+    if (c->stream != nullptr && n - 1 >= 2 * (int64_t)kGraphSteps) {
+        hipGraphExec_t& ex = gc.exec[2 + c0];
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+            hipError_t le = hipSuccess;
+            for (int s = 0; s < kGraphSteps && le == hipSuccess; ++s) le = launch(1 + s);
+            const hipError_t ce = hipStreamEndCapture(c->stream, &g);
+            if (le != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(SPFM_E_HIP, "step launch during capture: %s", hipGetErrorString(le));
+            }
+            if (ce != hipSuccess) return fail(SPFM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+            const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                ex = nullptr;
+                return fail(SPFM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            }
+        }
+        for (; n - kk >= kGraphSteps; kk += kGraphSteps) HIP_TRY(hipGraphLaunch(ex, c->stream));
+    }
+    for (; kk < n; ++kk) {
+        e = launch(kk);
+        if (e != hipSuccess) return fail(SPFM_E_HIP, "step launch: %s", hipGetErrorString(e));
+    }
+    const int o = (int)((n - 1) & 1);
+    void* const dst = c->buf[c0 ^ (int)(n & 1)];
+    const double dt_beta = c->r.p.dt * 2.0 * c->r.p.M / (3.0 * c->r.p.lambda * c->r.p.Gamma);
+    unsigned long long* const total = c->d_cvpart + 8 * c->items_cap;
+    e = f64 ? launch_cv_apply<double>((const double*)prev[o], (double*)star[o], c->points(), c->r.p.interp,
+                                      dt_beta, part[o], c->nitems, total, c->d_state(), c->stream,
+                                      (double*)dst)
+            : launch_cv_apply<float>((const float*)prev[o], (float*)star[o], c->points(), c->r.p.interp,
+                                     dt_beta, part[o], c->nitems, total, c->d_state(), c->stream, (float*)dst);
+    if (e != hipSuccess) return fail(SPFM_E_HIP, "constant-volume correction: %s", hipGetErrorString(e));
+    c->cur = c0 ^ (int)(n & 1);
+    c->nsteps += n;
+    return SPFM_OK;
+}
+
 spfm_status spfm_set_mu(spfm_ctx* c, double mu) {
     if (!c) return fail(SPFM_E_INVAL, "ctx is NULL");
     if (!std::isfinite(mu)) return fail(SPFM_E_INVAL, "mu must be finite");
@@ -1482,6 +1583,8 @@ spfm_status spfm_step(spfm_ctx* c, int64_t n) {
         if (st != SPFM_OK) return st;
         c->graphs.clear();
     }
+    if (c->r.conserve_volume && c->r.kernel != SPFM_KERNEL_PLAIN && c->nitems <= kCvDirectParts)
+        return run_cv_fused(c, n);
     return run_steps(c, n);
 }
 

@@ -522,16 +522,26 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 // cv_part non-null (periodic grids, the untuned tile shape only): the step also
 // writes, for work item i, the exact sums of phi* - phi and h'(phi) over its
 // points into cv_part[4i .. 4i+3] (CvAcc; the constant-volume correction).
+// fuse non-null (with cv_part): `in` holds the previous step's uncorrected
+// phi*, and the step first applies that step's correction as it reads its
+// planes (CvFuse below), so that one launch per step does both.
+template <typename T>
+struct CvFuse {
+    const T* old;                     // the field the previous step started from
+    T* corr;                          // receives the corrected field (the step's input)
+    const unsigned long long* part;   // the previous step's sums, 4 words per work item
+    int nparts;                       // at most kCvDirectParts
+};
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              int tile, const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
-                             unsigned long long* cv_part, hipStream_t s);
+                             unsigned long long* cv_part, const CvFuse<T>* fuse, hipStream_t s);
 // The tiled and batched steps of one kernel coupling (sweep.h; instantiated in
 // the per-coupling translation units).
 template <typename T, int C>
 hipError_t launch_tiled_coupling(const T* in, T* out, const StepCoef<T>& k, int stencil, int tile,
                                  const TileItem* items, int nitems, const WallCoef<T>* wall,
-                                 unsigned long long* cv_part, hipStream_t s);
+                                 unsigned long long* cv_part, const CvFuse<T>* fuse, hipStream_t s);
 template <int C>
 hipError_t launch_batched_coupling(const float* in, float* out, const StepCoef<float>* coef,
                                    const int64_t* offset, int stencil, int tile, const TileItem* items,
@@ -643,10 +653,11 @@ constexpr int kCvDirectParts = 1024;
 template <typename T>
 hipError_t launch_cv_correct(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
                              unsigned long long* d_part, double* d_state, hipStream_t s);
+// phi_out non-null: the corrected field goes there instead of into phi_new.
 template <typename T>
 hipError_t launch_cv_apply(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
                            const unsigned long long* d_part, int nparts, unsigned long long* d_total,
-                           double* d_state, hipStream_t s);
+                           double* d_state, hipStream_t s, T* phi_out = nullptr);
 template <typename T>
 hipError_t launch_contour_stats(const T* phi, int nx, int ny, int nz, double* d_part, double* d_out,
                                 hipStream_t s);

@@ -9,12 +9,14 @@ namespace spfm {
                                                          const StepCoef<float>&, int, int,          \
                                                          const TileItem*, int,                      \
                                                          const WallCoef<float>*,                    \
-                                                         unsigned long long*, hipStream_t);         \
+                                                         unsigned long long*,                       \
+                                                         const CvFuse<float>*, hipStream_t);        \
     template hipError_t launch_tiled_coupling<double, C_>(const double*, double*,                   \
                                                           const StepCoef<double>&, int, int,        \
                                                           const TileItem*, int,                     \
                                                           const WallCoef<double>*,                  \
-                                                          unsigned long long*, hipStream_t);        \
+                                                          unsigned long long*,                      \
+                                                          const CvFuse<double>*, hipStream_t);      \
     template hipError_t launch_batched_coupling<C_>(const float*, float*, const StepCoef<float>*,   \
                                                     const int64_t*, int, int, const TileItem*, int, \
                                                     const WallCoef<float>*, hipStream_t);

@@ -76,14 +76,14 @@ hipError_t launch_step_plain(const T* in, T* out, const StepCoef<T>& k, int sten
 template <typename T>
 hipError_t launch_step_tiled(const T* in, T* out, const StepCoef<T>& k, int stencil, int coupling,
                              int tile, const TileItem* d_items, int nitems, const WallCoef<T>* d_wall,
-                             unsigned long long* cv_part, hipStream_t s) {
+                             unsigned long long* cv_part, const CvFuse<T>* fuse, hipStream_t s) {
     if (cv_part && d_wall) return hipErrorInvalidValue;
     switch (coupling) {
-        case kLocal: return launch_tiled_coupling<T, kLocal>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, s);
-        case kGlobal: return launch_tiled_coupling<T, kGlobal>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, s);
-        case kCF: return launch_tiled_coupling<T, kCF>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, s);
-        case kCF5: return launch_tiled_coupling<T, kCF5>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, s);
-        case kCFAbel: return launch_tiled_coupling<T, kCFAbel>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, s);
+        case kLocal: return launch_tiled_coupling<T, kLocal>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, fuse, s);
+        case kGlobal: return launch_tiled_coupling<T, kGlobal>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, fuse, s);
+        case kCF: return launch_tiled_coupling<T, kCF>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, fuse, s);
+        case kCF5: return launch_tiled_coupling<T, kCF5>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, fuse, s);
+        case kCFAbel: return launch_tiled_coupling<T, kCFAbel>(in, out, k, stencil, tile, d_items, nitems, d_wall, cv_part, fuse, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -108,9 +108,9 @@ template hipError_t launch_step_plain<double>(const double*, double*, const Step
                                               int, hipStream_t);
 template hipError_t launch_step_tiled<float>(const float*, float*, const StepCoef<float>&, int, int,
                                              int, const TileItem*, int, const WallCoef<float>*,
-                                             unsigned long long*, hipStream_t);
+                                             unsigned long long*, const CvFuse<float>*, hipStream_t);
 template hipError_t launch_step_tiled<double>(const double*, double*, const StepCoef<double>&, int,
                                               int, int, const TileItem*, int, const WallCoef<double>*,
-                                              unsigned long long*, hipStream_t);
+                                              unsigned long long*, const CvFuse<double>*, hipStream_t);
 
 }  // namespace spfm

@@ -50,13 +50,21 @@ __device__ __forceinline__ int wrap_once(int i, int n) {
 // V (periodic grids): the block also sums phi* - phi and h'(phi) over its output
 // points exactly (CvAcc) and stores the sums to cvp, for the constant-volume
 // correction that follows the step.
-template <typename T, int S, int C, bool W, bool V, int TX, int TY>
+// F (with V): `in` is the previous step's uncorrected phi*, and the block first
+// applies that step's correction as it reads: it adds the previous step's sums
+// (fz.part, the same integers in every block, so the same g) and stages
+// phi* - g h'(phi_prev) with phi_prev from fz.old, exactly as the separate
+// correction pass computes it; the corrected value of each output point, the
+// step's input, is also written to fz.corr.
+template <typename T, int S, int C, bool W, bool V, int TX, int TY, bool F = false>
 __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restrict__ out,
                                            const StepCoef<T>& k, int x0, int y0, int z0, int zlen,
                                            T* __restrict__ sphi, T* __restrict__ spsi,
                                            const WallCoef<T>* __restrict__ w,
-                                           unsigned long long* __restrict__ cvp) {
+                                           unsigned long long* __restrict__ cvp,
+                                           const CvFuse<T>& fz = CvFuse<T>{}) {
     static_assert(!(V && W), "constant volume needs a periodic grid");
+    static_assert(!F || V, "the fused correction comes with the constant-volume sums");
     // Halo plane: HY rows of HX cells, stored in LDS with row stride LX.  Each
     // wave computes a kWaveX x (64 / kWaveX) patch of the tile.
     constexpr int HX = TX + 2, HY = TY + 2, NC = HX * HY;
@@ -118,24 +126,34 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     const int last = nout + 1;             // relative index of the last plane needed
 
     // Two fetched halo cells, with (W) the Eq. 7 coefficients of their classes
-    // on the fetched plane.
+    // on the fetched plane, or (F) the previous step's values of the cells.
     struct Pair { T v0, v1, a0, a1; };
+    __amdgpu_buffer_rsrc_t fetch_old = plane_rsrc(in, plane_bytes);   // F: fz.old, same plane
     auto fetch_at = [&](__amdgpu_buffer_rsrc_t src, int zc, Pair& v) {
         v.v0 = buf_load(src, loff0, (T*)nullptr);
         v.v1 = buf_load(src, loff1, (T*)nullptr);   // loff1 = 0 where the cell does not exist
+        if (F) {
+            v.a0 = buf_load(fetch_old, loff0, (T*)nullptr);
+            v.a1 = buf_load(fetch_old, loff1, (T*)nullptr);
+        }
         if (W) {
             v.a0 = zc == 0 ? wa0[0] : (zc == 2 ? wa0[2] : wa0[1]);
             v.a1 = zc == 0 ? wa1[0] : (zc == 2 ? wa1[2] : wa1[1]);
         }
     };
+    // F: the correction g of the previous step, set before the first staging.
+    double g = 0.0;
+    auto correct = [&](T star, T prev) {
+        return (T)((double)star - g * h_slope(kernel_interp(C), (double)prev));
+    };
     auto stage_slot = [&](int slot, const Pair& v) {
         T* dphi = sphi + slot * HP;
         T* dpsi = spsi + slot * HP;
-        const T u0 = W ? wall_map(v.v0, v.a0) : v.v0;
+        const T u0 = W ? wall_map(v.v0, v.a0) : (F ? correct(v.v0, v.a0) : v.v0);
         dphi[soff0] = u0;
         if (C == kLocal) dpsi[soff0] = psi2(u0, k.eps);
         if (has1) {
-            const T u1 = W ? wall_map(v.v1, v.a1) : v.v1;
+            const T u1 = W ? wall_map(v.v1, v.a1) : (F ? correct(v.v1, v.a1) : v.v1);
             dphi[soff1] = u1;
             if (C == kLocal) dpsi[soff1] = psi2(u1, k.eps);
         }
@@ -148,10 +166,12 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     const bool active = (x0 + tx < nx) && (y0 + ty < ny);
     const int dst_off = ((y0 + ty) * nx + (x0 + tx)) * (int)sizeof(T);
     CvAcc cv{{0, 0}};
+    __amdgpu_buffer_rsrc_t out_corr = plane_rsrc(out, plane_bytes);   // F: fz.corr, same plane
     auto point = [&](__amdgpu_buffer_rsrc_t dst, const PlaneRegs<T>& Rm, const PlaneRegs<T>& R0,
                      const PlaneRegs<T>& Rp) {
         const T v = point_from_planes<T, S, C>(Rm, R0, Rp, k);
         if (active) buf_store<(C == kLocal && sizeof(T) == 4) ? kStoreThrough : 0>(v, dst, dst_off);
+        if (F && active) buf_store(R0.c, out_corr, dst_off);
         if (V && active) {
             const double c = (double)R0.c;
             cv.add((double)v - c, h_slope(kernel_interp(C), c));
@@ -172,6 +192,9 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
             else if (fetch_z == nz - 1) { ptr -= plane_bytes; zc = 2; }
         }
         const __amdgpu_buffer_rsrc_t rs = plane_rsrc(ptr, plane_bytes);
+        if (F)   // no walls here: the previous field's plane is the same plane
+            fetch_old = plane_rsrc(reinterpret_cast<const char*>(fz.old) +
+                                       (ptr - reinterpret_cast<const char*>(in)), plane_bytes);
         fetch_ptr += plane_bytes;
         if (++fetch_z == nz) {
             fetch_z = 0;
@@ -182,6 +205,9 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
     char* out_ptr = reinterpret_cast<char*>(out) + (size_t)z0 * plane_bytes;
     auto next_out = [&]() {
         const __amdgpu_buffer_rsrc_t rs = plane_rsrc(out_ptr, plane_bytes);
+        if (F)
+            out_corr = plane_rsrc(reinterpret_cast<char*>(fz.corr) +
+                                      (out_ptr - reinterpret_cast<char*>(out)), plane_bytes);
         out_ptr += plane_bytes;
         return rs;
     };
@@ -228,6 +254,19 @@ __device__ __forceinline__ void tile_sweep(const T* __restrict__ in, T* __restri
         if (5 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qa1); }
         if (6 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qb0); }
         if (7 <= last) { const auto rs = next_in(zc); fetch_at(rs, zc, qb1); }
+        if constexpr (F) {
+            // g of the previous step while the planes are in flight: the sum
+            // of its work items' sums, as the separate correction pass forms it
+            __shared__ unsigned long long ftot[4];
+            CvAcc a{{0, 0}};
+            for (int i = tid; i < fz.nparts; i += NT) a.add_words(fz.part + 4 * (size_t)i);
+            cv_block_store<NT>(a, ftot);
+            __syncthreads();
+            CvAcc t{{0, 0}};
+            t.add_words(ftot);
+            const double den = CvAcc::value(t.s[1]);
+            g = den != 0.0 ? CvAcc::value(t.s[0]) / den : 0.0;
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (r <= last) stage_slot(r, v[r]);
@@ -283,10 +322,10 @@ constexpr int waves_per_simd() {
 // zlen = 0 pad the table and exit at once (with V, after storing zero sums).
 // W: walled grid, coefficients at w.  V: constant-volume sums of item i to
 // cvp + 4i.
-template <typename T, int S, int C, bool W, bool V, int TX, int TY>
+template <typename T, int S, int C, bool W, bool V, int TX, int TY, bool F = false>
 __global__ __launch_bounds__((Smem<TX, TY>::NT), (waves_per_simd<T, C, W, V, TX>())) void k_step_tiled(
     const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items,
-    const WallCoef<T>* __restrict__ w, unsigned long long* __restrict__ cvp) {
+    const WallCoef<T>* __restrict__ w, unsigned long long* __restrict__ cvp, CvFuse<T> fz) {
     __shared__ T sphi[4 * Smem<TX, TY>::HP];
     __shared__ T spsi[C == kLocal ? 4 * Smem<TX, TY>::HP : 1];
     const TileItem it = items[blockIdx.x];
@@ -295,7 +334,7 @@ __global__ __launch_bounds__((Smem<TX, TY>::NT), (waves_per_simd<T, C, W, V, TX>
         if (V && threadIdx.x < 4) cvi[threadIdx.x] = 0;
         return;
     }
-    tile_sweep<T, S, C, W, V, TX, TY>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi, w, cvi);
+    tile_sweep<T, S, C, W, V, TX, TY, F>(in, out, k, it.x0, it.y0, it.z0, it.zlen, sphi, spsi, w, cvi, fz);
 }
 
 template <int S, int C, bool W, int TX, int TY>
@@ -338,11 +377,12 @@ void for_each_variant(int stencil, bool walled, int tile, F&& f) {
     else if (stencil == 26) by_walls(std::integral_constant<int, 26>{});
 }
 
-template <typename T, int S, int C, bool W, bool V, int TX, int TY>
+template <typename T, int S, int C, bool W, bool V, int TX, int TY, bool F = false>
 hipError_t run_tiled(const T* in, T* out, const StepCoef<T>& k, const TileItem* items, int nitems,
-                     const WallCoef<T>* wall, unsigned long long* cvp, hipStream_t s) {
-    hipLaunchKernelGGL((k_step_tiled<T, S, C, W, V, TX, TY>), dim3((unsigned)nitems), dim3(TX * TY), 0,
-                       s, in, out, k, items, wall, cvp);
+                     const WallCoef<T>* wall, unsigned long long* cvp, hipStream_t s,
+                     const CvFuse<T>& fz = CvFuse<T>{}) {
+    hipLaunchKernelGGL((k_step_tiled<T, S, C, W, V, TX, TY, F>), dim3((unsigned)nitems), dim3(TX * TY), 0,
+                       s, in, out, k, items, wall, cvp, fz);
     return hipGetLastError();
 }
 
@@ -356,18 +396,25 @@ hipError_t run_batched(const float* in, float* out, const StepCoef<float>* coef,
 
 // The tiled step of one kernel coupling C for the compiled tile shape `tile`
 // (hipErrorInvalidValue for a shape not compiled for this variant).  With cvp
-// (periodic grids, the untuned shape only) the constant-volume variant.
+// (periodic grids, the untuned shape only) the constant-volume variant, with
+// fuse also the correction of the previous step.
 template <typename T, int C>
 hipError_t launch_tiled_coupling(const T* in, T* out, const StepCoef<T>& k, int stencil, int tile,
                                  const TileItem* items, int nitems, const WallCoef<T>* wall,
-                                 unsigned long long* cvp, hipStream_t s) {
+                                 unsigned long long* cvp, const CvFuse<T>* fuse, hipStream_t s) {
     if (nitems <= 0) return hipErrorInvalidValue;
+    if (fuse && (!cvp || fuse->nparts < 0 || fuse->nparts > kCvDirectParts)) return hipErrorInvalidValue;
     constexpr bool f32 = sizeof(T) == 4;
     hipError_t e = hipErrorInvalidValue;
     auto one = [&](auto S_, auto W_, auto T_) {
         constexpr int S = decltype(S_)::value, t = decltype(T_)::value;
         constexpr bool W = decltype(W_)::value;
         if constexpr (!W && t == default_tile(f32, C)) {
+            if (cvp && fuse) {
+                e = run_tiled<T, S, C, false, true, tile_tx(t), tile_ty(t), true>(in, out, k, items, nitems,
+                                                                                   nullptr, cvp, s, *fuse);
+                return;
+            }
             if (cvp) {
                 e = run_tiled<T, S, C, false, true, tile_tx(t), tile_ty(t)>(in, out, k, items, nitems,
                                                                              nullptr, cvp, s);

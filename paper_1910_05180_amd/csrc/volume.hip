@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_cv_total(const unsigned long
 // state[0] = g (the correction per unit h'), state[1] = mu.  Every block adds
 // the same integers, so every block applies the same g.
 template <typename T>
-__global__ __launch_bounds__(kReduceThreads) void k_cv_apply(T* __restrict__ phi_new,
+__global__ __launch_bounds__(kReduceThreads) void k_cv_apply(const T* phi_new, T* phi_out,
                                                              const T* __restrict__ phi_old, int64_t n,
                                                              int interp,
                                                              const unsigned long long* __restrict__ part,
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_cv_apply(T* __restrict__ phi
         state[0] = g;
         state[1] = dt_beta != 0.0 ? g / dt_beta : 0.0;
     }
-    if (in) phi_new[i] = (T)((double)pn - g * h_slope(interp, (double)po));
+    if (in) phi_out[i] = (T)((double)pn - g * h_slope(interp, (double)po));
 }
 
 // Pass 1 of the contour statistics: sum phi, sum phi x, sum phi y, sum phi z.
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_ray_radii(const T* __restrict__ phi, in
 template <typename T>
 hipError_t launch_cv_apply(const T* phi_old, T* phi_new, int64_t n, int interp, double dt_beta,
                            const unsigned long long* d_part, int nparts, unsigned long long* d_total,
-                           double* d_state, hipStream_t s) {
+                           double* d_state, hipStream_t s, T* phi_out) {
     if (nparts <= 0 || n <= 0) return hipErrorInvalidValue;
     if (nparts > kCvDirectParts) {   // one block adds them first: each apply block then reads one
         hipLaunchKernelGGL(k_cv_total, dim3(1), dim3(kReduceThreads), 0, s, d_part, nparts, d_total);
@@ -463,8 +463,8 @@ hipError_t launch_cv_apply(const T* phi_old, T* phi_new, int64_t n, int interp, 
         nparts = 1;
     }
     hipLaunchKernelGGL((k_cv_apply<T>), dim3((unsigned)((n + kReduceThreads - 1) / kReduceThreads)),
-                       dim3(kReduceThreads), 0, s, phi_new, phi_old, n, interp, d_part, nparts, dt_beta,
-                       d_state);
+                       dim3(kReduceThreads), 0, s, phi_new, phi_out ? phi_out : phi_new, phi_old, n, interp,
+                       d_part, nparts, dt_beta, d_state);
     return hipGetLastError();
 }
 
@@ -535,10 +535,10 @@ template hipError_t launch_cv_correct<double>(const double*, double*, int64_t, i
                                               unsigned long long*, double*, hipStream_t);
 template hipError_t launch_cv_apply<float>(const float*, float*, int64_t, int, double,
                                            const unsigned long long*, int, unsigned long long*, double*,
-                                           hipStream_t);
+                                           hipStream_t, float*);
 template hipError_t launch_cv_apply<double>(const double*, double*, int64_t, int, double,
                                             const unsigned long long*, int, unsigned long long*, double*,
-                                            hipStream_t);
+                                            hipStream_t, double*);
 template hipError_t launch_contour_stats<float>(const float*, int, int, int, double*, double*,
                                                 hipStream_t);
 template hipError_t launch_contour_stats<double>(const double*, int, int, int, double*, double*,

@@ -74,10 +74,11 @@ def test_constant_volume_conserves_the_sum(S, dtype, tol):
 def test_constant_volume_does_not_depend_on_the_schedule(S, dtype, coupling, interp):
     """The tiled step forms exact sums per work item: one-plane chunks on 96^3
     give more than 1024 items (added in a pass of their own before the
-    correction), 64-plane chunks a few hundred, the autotuner its own choice; the
-    plain kernel's path sums 1024 block partials.  The fields after 40 steps
-    and mu agree bit for bit among the tiled runs, and with the plain kernel's
-    mu to the rounding of the step itself."""
+    correction, which follows every step), 64-plane chunks a few hundred (every
+    step applies the previous one's correction as it reads), the size rule its
+    own choice; the plain kernel's path sums 1024 block partials.  The fields
+    after 40 steps and mu agree bit for bit among the tiled runs, and with the
+    plain kernel's mu to the rounding of the step itself."""
     n, lam = 96, 3.0
     phi0 = oracle.init_spheres((n, n, n), [(47.3, 50.2, 45.1)], [20.0], lam=lam)
     if dtype == "f32":
@@ -99,6 +100,37 @@ def test_constant_volume_does_not_depend_on_the_schedule(S, dtype, coupling, int
         assert out[name][1] == out["z1"][1], name
         assert out[name][3:] == out["z1"][3:], name   # the untuned tile shape
     assert abs(out["plain"][1] / out["z1"][1] - 1.0) <= (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_constant_volume_equals_separate_correction(S, dtype):
+    """One launch per step (the correction of each step applied by the next
+    one as it reads, 4-plane chunks: 512 work items on 64^3) against a step and
+    a correction launch per step (1-plane chunks: 2048 items): equal fields and
+    mu bit for bit after 1, 2 and 3 steps, after 40 steps on a stream (graph
+    replays of the fused launches), and across consecutive calls."""
+    import torch
+    n, lam = 64, 3.0
+    phi0 = oracle.init_spheres((n, n, n), [(31.3, 30.2, 33.1), (10.0, 50.0, 12.0)], [15.0, 6.0], lam=lam)
+    if dtype == "f32":
+        phi0 = as_f32_input(phi0)
+    eps = 1e-300 if dtype == "f64" else 1e-30
+    for calls in ((1,), (2,), (3,), (40,), (3, 5, 34)):
+        out = []
+        for zc in (1, 4):
+            print(f"case fused cv {dtype} calls={calls} zchunk={zc}", flush=True)
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                with S.Spfm(phi0.shape, lam=lam, mu=-0.2, stencil=26, dtype=dtype, coupling="local",
+                            eps=eps, conserve_volume=True, kernel="tiled", zchunk=zc, stream=st) as s:
+                    s.set_field(phi0)
+                    for m in calls:
+                        s.step(m)
+                    out.append((s.get_field(), s.diagnostics()))
+        assert np.array_equal(out[0][0], out[1][0]), calls
+        assert out[0][1]["mu"] == out[1][1]["mu"], calls
+        assert out[0][1]["step"] == out[1][1]["step"] == sum(calls)
+        assert out[0][1]["phase_volume"] == out[1][1]["phase_volume"]
 
 
 def test_contour_stats_match_oracle(S):
