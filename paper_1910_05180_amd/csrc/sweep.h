@@ -321,7 +321,7 @@ constexpr int waves_per_simd() {
 // builder): the item gives the tile column origin and its z-chunk; items with
 // zlen = 0 pad the table and exit at once (with V, after storing zero sums).
 // W: walled grid, coefficients at w.  V: constant-volume sums of item i to
-// cvp + 4i.
+// cvp + 4i.  F: the previous step's correction applied on reading (fz).
 template <typename T, int S, int C, bool W, bool V, int TX, int TY, bool F = false>
 __global__ __launch_bounds__((Smem<TX, TY>::NT), (waves_per_simd<T, C, W, V, TX>())) void k_step_tiled(
     const T* __restrict__ in, T* __restrict__ out, StepCoef<T> k, const TileItem* __restrict__ items,
