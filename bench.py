@@ -664,7 +664,8 @@ def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5
     travels `warm-up` cells along x untimed, then `window` cells (the paper runs
     at least five; 2.5 at lambda = 0.5, where the steps are many).  The
     velocity is the change of front_x over the window; the relative error is
-    against -M mu0 / Gamma, the x-velocity every orientation shares."""
+    against -M mu0 / Gamma, the x-velocity every orientation shares.  Then
+    TI_n at lambda = 0.5 in FP64, one walled context per orientation."""
     import math
     shape = (10, 10, 120)
     runs = [("001", d) for d in (0, 15, 30, 45)] + [("011", d) for d in (15, 30, 45)]
@@ -711,6 +712,25 @@ def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5
                 "mean_rel_error": sum(vals) / len(vals),
                 "kinetic_anisotropy": max(vals) - min(vals),
                 "pinned": [k for k, v in errs.items() if v < -0.99]}
+    # TI_n at lambda = 0.5 in FP64 (the FP32 fronts are limited there by the
+    # storage of phi near 1): seven walled contexts, 0.05 + 0.2 cells of travel
+    lam, f64 = 0.5, {}
+    for (axis, deg), n in zip(runs, ns):
+        dt = 0.5 * spfm.stable_dt(26, "local", n, None, lam, 1.0, 1.0, mu0 * n[0], 1.0)
+        warm, steps = int(math.ceil(0.05 / mu0 / dt)), int(math.ceil(0.2 / mu0 / dt))
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm(shape, lam=lam, mu=mu0 * n[0], stencil=26, dtype="f64", coupling="local", dt=dt,
+                          walls=7, wall_sin=spfm.front_wall_sin(n), stream=stream)
+            s.init_front(n, 20.0)
+            s.step(warm)
+            x0 = front_x(s.get_field())
+            s.step(steps)
+            x1 = front_x(s.get_field())
+            s.close()
+        f64[f"{axis}:{deg}"] = (x1 - x0) / (steps * dt) / (-mu0) - 1.0
+    out["lam0.5_TI_n_fp64"] = {"rel_velocity_error": f64, "window_cells": 0.2,
+                               "kinetic_anisotropy": max(f64.values()) - min(f64.values())}
     out["steps"] = steps_total
     out["gpu_s"] = ms_total * 1e-3
     return out
