@@ -1062,45 +1062,41 @@ def main():
                              / HBM_PEAK_GBS}
         if f32 is not None:
             out["speedup_vs_fp64_plain"] = out["value"] / g64
-    if args.only in ("", "batch"):
-        print("leg: batch64", file=sys.stderr, flush=True)
-        out["batch64"] = batch_leg(spfm, torch, inputs, args.side_steps, 10)
-    if args.only in ("", "grains"):
-        print("leg: grains512", file=sys.stderr, flush=True)
-        out["grains512"] = grains_leg(spfm, torch, inputs, args.side_steps, 10)
-    if args.only in ("", "temporal"):
-        print("leg: temporal", file=sys.stderr, flush=True)
-        out["grains512_temporal2"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)
-        # CF: the HBM-bound step, where fusing steps pays
-        out["grains512_cf"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, coupling="cf")
-        out["grains512_cf_temporal3"] = grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=3,
-                                                   coupling="cf")
-    if args.only in ("", "musweep"):
-        print("leg: mu sweep", file=sys.stderr, flush=True)
-        out["mu_sweep128"] = mu_sweep_leg(spfm, torch, inputs)
-    if args.only in ("", "walls"):
-        print("leg: walls", file=sys.stderr, flush=True)
-        out["orientation120_walls"] = walls_leg(spfm, torch)
-        # the continuum-field control at the paper's mu0: friction makes it orientation dependent
-        out["orientation120_walls_cf"] = walls_leg(spfm, torch, coupling="cf", mu0=0.1)
-    if args.only in ("", "fig1"):
-        print("leg: fig1", file=sys.stderr, flush=True)
-        out["fig1_pinning"] = fig1_leg(spfm, torch)
-    if args.only in ("", "fig8"):
-        print("leg: fig8", file=sys.stderr, flush=True)
-        out["fig8_orientation"] = fig8_leg(spfm, torch)
-    if args.only in ("", "models"):
-        print("leg: models", file=sys.stderr, flush=True)
-        out["fig7_models"] = models_leg(spfm, torch)
-    if args.only in ("", "cube"):
-        print("leg: cube", file=sys.stderr, flush=True)
-        out["fig9_cube60"] = cube_leg(spfm, torch)
-    if args.only in ("", "friction"):
-        print("leg: friction", file=sys.stderr, flush=True)
-        out["fig3_friction"] = friction_leg(spfm)
-    if args.only in ("", "grainruns"):
-        print("leg: grain runs", file=sys.stderr, flush=True)
-        out["grain256_runs"] = grain_runs_leg(spfm, torch, inputs)
+    # The side legs: (--only name, label, [(output key, call)]).  A leg that
+    # raises is recorded under leg_errors and the others still run, so the
+    # headline line is printed whatever happens to them.
+    legs = [
+        ("batch", "batch64", [("batch64", lambda: batch_leg(spfm, torch, inputs, args.side_steps, 10))]),
+        ("grains", "grains512", [("grains512", lambda: grains_leg(spfm, torch, inputs, args.side_steps, 10))]),
+        ("temporal", "temporal", [
+            ("grains512_temporal2", lambda: grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=2)),
+            # CF: the HBM-bound step, where fusing steps pays
+            ("grains512_cf", lambda: grains_leg(spfm, torch, inputs, args.side_steps, 10, coupling="cf")),
+            ("grains512_cf_temporal3", lambda: grains_leg(spfm, torch, inputs, args.side_steps, 10, tsteps=3,
+                                                          coupling="cf"))]),
+        ("musweep", "mu sweep", [("mu_sweep128", lambda: mu_sweep_leg(spfm, torch, inputs))]),
+        ("walls", "walls", [
+            ("orientation120_walls", lambda: walls_leg(spfm, torch)),
+            # the continuum-field control at the paper's mu0: friction makes it orientation dependent
+            ("orientation120_walls_cf", lambda: walls_leg(spfm, torch, coupling="cf", mu0=0.1))]),
+        ("fig1", "fig1", [("fig1_pinning", lambda: fig1_leg(spfm, torch))]),
+        ("fig8", "fig8", [("fig8_orientation", lambda: fig8_leg(spfm, torch))]),
+        ("models", "models", [("fig7_models", lambda: models_leg(spfm, torch))]),
+        ("cube", "cube", [("fig9_cube60", lambda: cube_leg(spfm, torch))]),
+        ("friction", "friction", [("fig3_friction", lambda: friction_leg(spfm))]),
+        ("grainruns", "grain runs", [("grain256_runs", lambda: grain_runs_leg(spfm, torch, inputs))]),
+    ]
+    for name, label, parts in legs:
+        if args.only not in ("", name):
+            continue
+        print(f"leg: {label}", file=sys.stderr, flush=True)
+        for key, call in parts:
+            try:
+                out[key] = call()
+            except Exception as e:   # recorded, not hidden: the line carries it
+                import traceback
+                traceback.print_exc()
+                out.setdefault("leg_errors", {})[key] = f"{type(e).__name__}: {e}"
     if not args.no_cpu and f32 is not None:
         print("leg: cpu oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
