@@ -587,19 +587,18 @@ def walls_leg(spfm, torch, warm=400, steps=1600, coupling="local", mu0=0.05):
             "rel_velocity_error": errs}
 
 
-def front_x(field):
-    """Mean x (in grid points) of the falling phi = 1/2 crossings of a planar
-    front, over the x lines of field (nz, ny, nx): on each line, the one place
-    where phi drops from >= 1/2 at x to < 1/2 at x + 1 (the line read
-    periodically, so a periodic slab's trailing front counts and a walled
-    front with phase 1 at low x is found as such), located at the zero of
-    psi = ln((1 - phi)/phi) interpolated linearly between those two points.
-    psi is linear across the ideal profile of Eq. 3 (the contour reading of
-    Eq. 8-9 at l = 1/2), so the crossing is exact for it at any lambda/dx.  The
-    phase volume is not: for sharp profiles its change per cell of travel
-    oscillates with the front's offset from the grid (about 9% of the velocity
-    at lambda = dx), so a velocity taken from it over a fraction of a cell
-    errs."""
+def front_crossings(field):
+    """x (in grid points) of the falling phi = 1/2 crossing of every x line of
+    field (nz, ny, nx), NaN on lines without one: the one place where phi
+    drops from >= 1/2 at x to < 1/2 at x + 1 (the line read periodically, so
+    a periodic slab's trailing front counts and a walled front with phase 1 at
+    low x is found as such), located at the zero of psi = ln((1 - phi)/phi)
+    interpolated linearly between those two points.  psi is linear across the
+    ideal profile of Eq. 3 (the contour reading of Eq. 8-9 at l = 1/2), so the
+    crossing is exact for it at any lambda/dx.  The phase volume is not: for
+    sharp profiles its change per cell of travel oscillates with the front's
+    offset from the grid (about 9% of the velocity at lambda = dx), so a
+    velocity taken from it over a fraction of a cell errs."""
     import numpy as np
     f = np.asarray(field, dtype=np.float64).reshape(-1, np.shape(field)[-1])
     g = np.roll(f, -1, axis=1)
@@ -610,8 +609,24 @@ def front_x(field):
     a = np.clip(f[rows, i], 1e-300, 1.0 - 1e-16)
     b = np.clip(g[rows, i], 1e-300, 1.0 - 1e-16)
     pa, pb = np.log((1.0 - a) / a), np.log((1.0 - b) / b)
-    x = i + pa / (pa - pb)
-    return float(x[ok].mean()) if ok.any() else float("nan")
+    return np.where(ok, i + pa / (pa - pb), np.nan)
+
+
+def front_x(field):
+    """Mean x of the front's crossings (front_crossings) over the x lines."""
+    import numpy as np
+    c = front_crossings(field)
+    return float(np.nanmean(c)) if np.isfinite(c).any() else float("nan")
+
+
+def front_shift(c0, c1, nx):
+    """Mean displacement along a periodic x axis of nx points between two sets
+    of per-line crossings (front_crossings), each line's difference taken
+    modulo nx into [-nx/2, nx/2): an inclined front crosses every x on some
+    line, so the mean of the positions themselves does not move with it."""
+    import numpy as np
+    d = np.asarray(c1) - np.asarray(c0)
+    return float(np.nanmean((d + nx / 2.0) % nx - nx / 2.0))
 
 
 def fig1_leg(spfm, torch, mu=0.1, warm_cells=2.0, cells=3.0, per_cell=10):
@@ -665,7 +680,9 @@ def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5
     at least five; 2.5 at lambda = 0.5, where the steps are many).  The
     velocity is the change of front_x over the window; the relative error is
     against -M mu0 / Gamma, the x-velocity every orientation shares.  Then
-    TI_n at lambda = 0.5 in FP64, one walled context per orientation."""
+    TI_n at lambda = 0.5 in FP64, one walled context per orientation, and the
+    45-degree front of TI_n, TI_<100> and TI_<110> at lambda = 1 as a periodic
+    slab without walls."""
     import math
     shape = (10, 10, 120)
     runs = [("001", d) for d in (0, 15, 30, 45)] + [("011", d) for d in (15, 30, 45)]
@@ -731,6 +748,25 @@ def fig8_leg(spfm, torch, plan=((4.0, 1.0, 5.0), (1.0, 1.0, 5.0), (0.5, 0.5, 2.5
         f64[f"{axis}:{deg}"] = (x1 - x0) / (steps * dt) / (-mu0) - 1.0
     out["lam0.5_TI_n_fp64"] = {"rel_velocity_error": f64, "window_cells": 0.2,
                                "kinetic_anisotropy": max(f64.values()) - min(f64.values())}
+    # the 45-degree front without walls: a periodic (1,1,0) slab in a 128 x 128 x 3
+    # box at lambda = 1, 1 + 5 cells of travel, per-line displacements unwrapped
+    lam, per = 1.0, {}
+    n45 = (math.sqrt(0.5), math.sqrt(0.5), 0.0)
+    for name, coupling, u in models[:3]:
+        dt = 0.5 * spfm.stable_dt(26, coupling, u, None, lam, 1.0, 1.0, mu0 * n45[0], 1.0)
+        warm, steps = int(math.ceil(1.0 / mu0 / dt)), int(math.ceil(5.0 / mu0 / dt))
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = spfm.Spfm((3, 128, 128), lam=lam, mu=mu0 * n45[0], stencil=26, coupling=coupling, u=u, dt=dt,
+                          stream=stream)
+            s.init_planar((1, 1, 0), 0.37)
+            s.step(warm)
+            c0 = front_crossings(s.get_field())
+            s.step(steps)
+            c1 = front_crossings(s.get_field())
+            s.close()
+        per[name] = front_shift(c0, c1, 128) / (steps * dt) / (-mu0) - 1.0
+    out["lam1_periodic_110"] = {"rel_velocity_error": per, "window_cells": 5.0}
     out["steps"] = steps_total
     out["gpu_s"] = ms_total * 1e-3
     return out

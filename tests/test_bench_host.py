@@ -122,3 +122,17 @@ def test_phase_volume_is_not_an_exact_front_position_for_sharp_profiles():
     assert np.ptp(slope) > 0.1
     xs = np.array([bench.front_x(oracle.front((2, 2, 60), n, o, lam=1.0)) for o in offs])
     assert np.allclose(np.diff(xs) / np.diff(offs), 1.0, atol=1e-9)
+
+
+@pytest.mark.parametrize("lam", [4.0, 1.0])
+def test_front_shift_follows_an_inclined_periodic_slab(lam):
+    """On a periodic (1,1,0) slab the crossings cover every x of the box, so
+    their mean stays put as the slab moves; front_shift unwraps each line's
+    displacement and recovers the shift along x, d / n_x, exactly."""
+    import numpy as np
+    import oracle
+    shape, n_x = (3, 64, 64), np.sqrt(0.5)
+    c0 = bench.front_crossings(oracle.init_planar(shape, (1, 1, 0), 0.37, lam=lam))
+    for d in (0.3, 1.7, 4.1):
+        c1 = bench.front_crossings(oracle.init_planar(shape, (1, 1, 0), 0.37 + d, lam=lam))
+        assert bench.front_shift(c0, c1, 64) == pytest.approx(d / n_x, abs=1e-9)
