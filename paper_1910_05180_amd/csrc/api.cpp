@@ -779,8 +779,8 @@ spfm_status set_schedule(spfm_batch* b, int tile, int zb) { return set_schedule(
 // pairs on the current field, reading the current buffer and writing the other
 // one, which the next step overwrites anyway.  The untuned pair (the current
 // one: the default shape and the size rule's length) is kept unless another is
-// at least 2% faster: the first steps of a process run while the clocks still
-// ramp up, and differences below that are within the noise of these short
+// at least 1% faster: the first steps of a process run while the clocks still
+// ramp up, and differences below that are within the noise of these
 // timings.  When the size rule has already shortened the chunks below full
 // (zlen < zfull), the work cannot fill the GPU, a launch takes about as long
 // as the host needs to issue it, and timing single launches would measure the
@@ -800,14 +800,17 @@ spfm_status tune_schedule(Obj* o, const std::vector<TuneCand>& cand, int zfull) 
     std::vector<float> best(cand.size(), 1e30f);
     spfm_status st = SPFM_OK;
     // Four sweeps over the candidates, the first untimed (it warms clocks and
-    // caches); each candidate: two untimed launches, then five timed ones; the
-    // best of the timed sweeps counts.
+    // caches); each candidate: two untimed launches, then nt timed ones, nt
+    // chosen from the first sweep's time of the untuned pair so that a sample
+    // spans about 1.5 ms (5 to 64 launches: short launches alone are timed
+    // mostly by their issue jitter); the best of the timed sweeps counts.
+    int nt = 5;
     for (int sweep = 0; sweep < 4 && st == SPFM_OK; ++sweep) {
         for (size_t ci = 0; ci < cand.size(); ++ci) {
             st = set_schedule(o, cand[ci].tile, cand[ci].z);   // zlen also steers the temporal kernel
             if (st != SPFM_OK) break;
             hipError_t e = hipSuccess;
-            for (int i = 0; i < 7 && e == hipSuccess; ++i) {
+            for (int i = 0; i < 2 + nt && e == hipSuccess; ++i) {
                 if (i == 2) e = hipEventRecord(e0, o->stream);
                 if (e == hipSuccess) e = o->launch_unit(o->cur);
             }
@@ -817,13 +820,14 @@ spfm_status tune_schedule(Obj* o, const std::vector<TuneCand>& cand, int zfull) 
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) { st = fail(SPFM_E_HIP, "autotune: %s", hipGetErrorString(e)); break; }
             if (sweep > 0) best[ci] = std::min(best[ci], ms);
+            else if (ci == 0 && ms > 0.0f) nt = std::min(64, std::max(5, (int)std::ceil(1.5f * nt / ms)));
         }
     }
     size_t bi = 0;
     for (size_t ci = 1; ci < cand.size(); ++ci)
         if (best[ci] < best[bi]) bi = ci;
     for (size_t ci = 0; ci < cand.size(); ++ci)
-        if (cand[ci].tile == rule.tile && cand[ci].z == rule.z && best[ci] <= 1.02f * best[bi]) bi = ci;
+        if (cand[ci].tile == rule.tile && cand[ci].z == rule.z && best[ci] <= 1.01f * best[bi]) bi = ci;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SPFM_OK) {
