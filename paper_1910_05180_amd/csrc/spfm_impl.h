@@ -321,20 +321,27 @@ __device__ __forceinline__ T point_incr(T p, T s1, T s2, T s3, Grad grad, const 
                 sy = ey - ry;
                 sz = ez - rz;
             }
-            // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
-            // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
-            // K_1 s_1 + K_2 s_2 + K_3 s_3 = A1 c1 + A2 c2 + K_3 cx cy cz with
-            // c1 = sum c, c2 = sum of pair products (A1, A2 folded on the host).
-            const T cxy = cx + cy, pxy = cx * cy;
-            const T c1 = cxy + cz;
-            q = k.A1 * c1;
-            if (S >= 18) q = fma(k.A2, fma(cz, cxy, pxy), q);
-            if (S >= 26) q = fma(k.K[2], pxy * cz, q);
-            q *= x;
-            // The full coupling only where some lane of the wave needs it; the vote
-            // keeps the branch wave-uniform, so tail-only waves skip it entirely.
+            // The full coupling only where some lane of the wave needs it, the tail
+            // form only where some lane can take it: the votes keep both branches
+            // wave-uniform, so tail-only waves skip the full coupling and waves
+            // whose every lane needs it skip the tail sums.
             const bool full = !(fabs(x) < k.xtail);
-            if (__ballot(full) != 0) {
+            const unsigned long long vfull = __ballot(full);
+            q = T(0);
+            if (vfull != __ballot(true)) {
+                keep_branch();
+                // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
+                // sum_2 = sum_pairs (C_a C_b - 4), sum_3 = C_x C_y C_z - 8, C = c + 2.
+                // K_1 s_1 + K_2 s_2 + K_3 s_3 = A1 c1 + A2 c2 + K_3 cx cy cz with
+                // c1 = sum c, c2 = sum of pair products (A1, A2 folded on the host).
+                const T cxy = cx + cy, pxy = cx * cy;
+                const T c1 = cxy + cz;
+                q = k.A1 * c1;
+                if (S >= 18) q = fma(k.A2, fma(cz, cxy, pxy), q);
+                if (S >= 26) q = fma(k.K[2], pxy * cz, q);
+                q *= x;
+            }
+            if (vfull != 0) {
                 keep_branch();
                 // y_k = x m_k straight from x-scaled pieces: with
                 // 2cosh(a +- b) - 2 = c_a + c_b + (c_a c_b +- s_a s_b)/2,
