@@ -115,7 +115,8 @@ typedef struct {
                            Single steps cut each tile column into blocks of at most zchunk
                            planes, except a tail (about 1.4 rounds of the work the GPU keeps
                            resident, at most 35% of the column) in blocks of halving length
-                           down to 4, dispatched last so that the GPU drains evenly; fused
+                           down to 8 (4 for zchunk < 16), dispatched last so that the GPU
+                           drains evenly; fused
                            steps (tsteps > 1) use zchunk planes throughout */
     int32_t tsteps;     /* temporal blocking: steps fused into one pass over the field, 0 or 1 =
                            none, 2..4 = that many (F32 with kernel AUTO or TILED only).  Results
