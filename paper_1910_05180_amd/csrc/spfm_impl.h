@@ -325,9 +325,10 @@ __device__ __forceinline__ T point_incr(T p, T s1, T s2, T s3, Grad grad, const 
             // form only where some lane can take it: the votes keep both branches
             // wave-uniform, so tail-only waves skip the full coupling and waves
             // whose every lane needs it skip the tail sums.
+            // (q is set below for every lane that reads it: a lane without the
+            // full coupling makes its wave take the tail branch.)
             const bool full = !(fabs(x) < k.xtail);
             const unsigned long long vfull = __ballot(full);
-            q = T(0);
             if (vfull != __ballot(true)) {
                 keep_branch();
                 // Tail: y/(1+y) -> y, with the per-shell sums of m_k in closed form,
